@@ -1,0 +1,855 @@
+/*
+ * oracle.c -- FP64 reference Whitted ray tracer.  TEST INFRASTRUCTURE ONLY.
+ *
+ * This file is the plain, slow, brute-force statement of what the GPU ray
+ * tracer computes.  Only the tests, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it; the product library never does, and the two
+ * share no code (no headers, no helpers, no tables).
+ *
+ * What it computes (paper: "Massively Parallel Ray Tracing Algorithm Using
+ * GPU", arXiv 1504.03151):
+ *   - Closest hit by brute force over every primitive: the object loop of
+ *     Algorithm 1 (Section III).  No acceleration structure.
+ *   - Sphere hits from the quadratic of Eq. 11-12 (Section IV.B), taking the
+ *     smallest root in (0, tmax) (the paper does not say which root).
+ *   - Triangles by an edge-function test in FP64 (inclusive edges, zero-area
+ *     never hit); planes by the plane equation.
+ *   - Shadow rays to each point light, counted as blocked by the first
+ *     primitive found on the segment: the inner loop of Algorithm 1 with its
+ *     ELSE branch read as "add the light's term only if nothing blocks".
+ *   - Recursion over reflected and refracted secondary rays up to a maximum
+ *     depth (Section III after Algorithm 1, Section IV.A, Fig. 3), with the
+ *     local term from Phong reflection (ambient + diffuse + specular) in place
+ *     of the hemisphere integral of Eq. 8.
+ *   - Several samples per pixel averaged (anti-aliasing, end of Section III).
+ *
+ * Besides colours and ids it reports, for every ray it traces, a robustness
+ * margin: how far each discrete decision (which primitive is hit, whether a
+ * shadow ray is blocked, whether the ray is inside a dielectric, total
+ * internal reflection) is from flipping.  It combines
+ *   (a) relative margins: barycentric min(lambda) for triangles,
+ *       1-(d_perp/r)^2 for spheres, |n.d| for planes, (t2-t1)/t1 for depth
+ *       ties, |t|/max(1,|o|) and |tmax-t|/tmax for the ends of the segment;
+ *   (b) 1e-4 x (world-space clearance / FP32 error envelope), where the
+ *       envelope is propagated along the ray tree (curved mirrors and
+ *       refraction amplify round-off of the FP32 implementation).
+ * margin = min over all decisions; a ray is robust when margin > 1e-4.
+ * Rays that are not robust may legitimately differ between an FP32 and an
+ * FP64 implementation; a pixel is robust when every ray of its tree is.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so oracle.c -lm -lpthread
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+#define OR_INF (1.0 / 0.0)
+/* FP32 arithmetic error allowance, relative to coordinate magnitude (~7 ulp). */
+#define EA 4e-7
+/* Margins are reported capped at this value: above it they are irrelevant
+ * for the 1e-4 robustness threshold. */
+#define MARGIN_CAP 1e-2
+
+enum { MAT_PHONG = 0, MAT_MIRROR = 1, MAT_DIELECTRIC = 2 };
+
+typedef struct {
+    int64_t n_spheres;
+    const float* spheres;     /* [n][4] cx cy cz r */
+    const int32_t* sphere_mat;
+    int64_t n_tris;
+    const float* tris;        /* [n][3][3] */
+    const int32_t* tri_mat;
+    int64_t n_planes;
+    const float* planes;      /* [n][4] nx ny nz h : n.x = h */
+    const int32_t* plane_mat;
+    int32_t n_materials;
+    const float* materials;   /* [m][10] albedo rgb, ka, kd, ks, shininess, kr, ior, type */
+    int32_t n_lights;
+    const float* lights;      /* [l][6] pos, intensity */
+} or_scene;
+
+typedef struct {
+    double eye[3], look_at[3], up[3];
+    double vfov_deg;
+    int32_t width, height;
+} or_camera;
+
+typedef struct {
+    int32_t spp, max_depth, jitter, pad0;
+    uint64_t seed;
+    uint32_t frame, pad1;
+    double bg[3];
+    double eps;
+} or_params;
+
+/* ------------------------------------------------------------------------ */
+/* small vector helpers                                                     */
+/* ------------------------------------------------------------------------ */
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+static void sub3(double* r, const double* a, const double* b) { r[0] = a[0] - b[0]; r[1] = a[1] - b[1]; r[2] = a[2] - b[2]; }
+static void cross3(double* r, const double* a, const double* b) {
+    double x = a[1] * b[2] - a[2] * b[1];
+    double y = a[2] * b[0] - a[0] * b[2];
+    double z = a[0] * b[1] - a[1] * b[0];
+    r[0] = x; r[1] = y; r[2] = z;
+}
+static double norm3(const double* a) { return sqrt(dot3(a, a)); }
+static void normalize3(double* a) { double n = norm3(a); a[0] /= n; a[1] /= n; a[2] /= n; }
+static double maxabs3(const double* a) { return fmax(fabs(a[0]), fmax(fabs(a[1]), fabs(a[2]))); }
+static void load3f(double* r, const float* f) { r[0] = f[0]; r[1] = f[1]; r[2] = f[2]; }
+
+/* ------------------------------------------------------------------------ */
+/* counter-based hash for pixel jitter: the 32-bit PCG hash of Jarzynski and */
+/* Olano, "Hash Functions for GPU Rendering", JCGT 9(3), 2020 (after         */
+/* O'Neill's PCG generator).                                                 */
+/* ------------------------------------------------------------------------ */
+uint32_t or_pcg(uint32_t v) {
+    uint32_t state = v * 747796405u + 2891336453u;
+    uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+/* xi in [0,1): 24 random bits, exact in FP32 and FP64 */
+double or_jitter(uint64_t seed, uint32_t frame, uint32_t pixel, uint32_t s, uint32_t dim) {
+    uint32_t h = or_pcg((uint32_t)seed);
+    h = or_pcg(h ^ (uint32_t)(seed >> 32));
+    h = or_pcg(h ^ frame);
+    h = or_pcg(h ^ pixel);
+    h = or_pcg(h ^ (s * 2u + dim));
+    return (double)(h >> 8) * (1.0 / 16777216.0);
+}
+
+/* Pinhole camera: vertical field of view, row 0 at the top, right = up x forward. */
+void or_camera_ray(const or_camera* cam, const or_params* p, int64_t pixel, int32_t s, double* o, double* d) {
+    double f[3], r[3], u[3];
+    sub3(f, cam->look_at, cam->eye);
+    normalize3(f);
+    cross3(r, cam->up, f);
+    normalize3(r);
+    cross3(u, f, r);
+    const int W = cam->width, H = cam->height;
+    const int64_t px = pixel % W, py = pixel / W;
+    double jx = 0.5, jy = 0.5;
+    const int spp = p->spp;
+    int m = (int)floor(sqrt((double)spp) + 0.5);
+    double xi0 = 0.5, xi1 = 0.5;
+    if (p->jitter) {
+        xi0 = or_jitter(p->seed, p->frame, (uint32_t)pixel, (uint32_t)s, 0);
+        xi1 = or_jitter(p->seed, p->frame, (uint32_t)pixel, (uint32_t)s, 1);
+    }
+    if (spp > 1 && m * m == spp) {
+        jx = ((double)(s % m) + xi0) / m;
+        jy = ((double)(s / m) + xi1) / m;
+    } else {
+        jx = xi0;
+        jy = xi1;
+    }
+    const double th = tan(cam->vfov_deg * 0.5 * M_PI / 180.0);
+    const double X = (2.0 * ((double)px + jx) / W - 1.0) * ((double)W / H) * th;
+    const double Y = (1.0 - 2.0 * ((double)py + jy) / H) * th;
+    for (int i = 0; i < 3; ++i) {
+        o[i] = cam->eye[i];
+        d[i] = f[i] + X * r[i] + Y * u[i];
+    }
+    normalize3(d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* rays and error envelopes                                                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double o[3], d[3];
+    double tmax;
+    double so;   /* origin uncertainty of an FP32 implementation (world units) */
+    double sd;   /* direction uncertainty (radians) */
+} oray;
+
+/* world-space uncertainty of the point o + t d */
+static double envelope(const oray* r, double t) {
+    double tt = fabs(t);
+    if (!isfinite(tt)) tt = 1e30;
+    return r->so + r->sd * tt + EA * (maxabs3(r->o) + tt) + 1e-30;
+}
+
+/* One primitive evaluated against one ray. */
+typedef struct {
+    int ok;          /* passes the shape test */
+    int nroot;       /* roots (ascending) when ok */
+    double t[2];
+    double cs[2];    /* |cos| between ray and surface normal at each root */
+    double rel;      /* signed relative shape margin (>= 0 when ok) */
+    double clr;      /* signed world clearance perpendicular to the ray */
+    double tref;     /* ray parameter at which the shape decision is taken */
+    int valid;       /* 0: primitive can never be hit (degenerate or parallel) */
+} cand;
+
+/* Sphere: the quadratic of Eq. 11, roots by Eq. 12 with a = d.d, b = 2(o-c).d,
+ * c' = (o-c).(o-c) - r^2 (the paper's c is renamed c' to keep c for the centre). */
+static void eval_sphere(const float* s, const oray* ray, cand* c) {
+    double ctr[3], f[3];
+    load3f(ctr, s);
+    const double r = s[3];
+    sub3(f, ray->o, ctr);
+    const double a = dot3(ray->d, ray->d);
+    const double b = 2.0 * dot3(f, ray->d);
+    const double cc = dot3(f, f) - r * r;
+    const double disc = b * b - 4.0 * a * cc;
+    const double fd = dot3(f, ray->d);
+    double dp2 = dot3(f, f) - fd * fd / a;
+    if (dp2 < 0) dp2 = 0;
+    const double dp = sqrt(dp2);
+    c->valid = 1;
+    c->rel = 1.0 - dp2 / (r * r);
+    c->clr = r - dp;
+    c->tref = -b / (2.0 * a);
+    c->ok = disc >= 0.0;
+    c->nroot = 0;
+    if (c->ok) {
+        const double sq = sqrt(disc);
+        c->t[0] = (-b - sq) / (2.0 * a);
+        c->t[1] = (-b + sq) / (2.0 * a);
+        c->nroot = 2;
+        const double dl = sqrt(a);
+        for (int i = 0; i < 2; ++i) {
+            double p[3], n[3];
+            for (int k = 0; k < 3; ++k) p[k] = ray->o[k] + c->t[i] * ray->d[k];
+            sub3(n, p, ctr);
+            c->cs[i] = fabs(dot3(n, ray->d)) / (r * dl);
+        }
+    }
+}
+
+/* Triangle: plane distance, then the three edge functions (barycentrics)
+ * computed from cross products at the plane point; edges inclusive. */
+static void eval_tri(const float* tv, const oray* ray, cand* c) {
+    double v0[3], v1[3], v2[3], e1[3], e2[3], n[3];
+    load3f(v0, tv);
+    load3f(v1, tv + 3);
+    load3f(v2, tv + 6);
+    sub3(e1, v1, v0);
+    sub3(e2, v2, v0);
+    cross3(n, e1, e2);
+    const double nn = dot3(n, n);
+    const double denom = dot3(n, ray->d);
+    c->valid = 0;
+    c->ok = 0;
+    c->nroot = 0;
+    if (nn == 0.0 || denom == 0.0) return;
+    c->valid = 1;
+    double w[3];
+    sub3(w, v0, ray->o);
+    const double t = dot3(n, w) / denom;
+    double p[3], a[3], b[3], q[3], lam[3];
+    for (int k = 0; k < 3; ++k) p[k] = ray->o[k] + t * ray->d[k];
+    const double* V[3] = {v0, v1, v2};
+    double elen[3];
+    for (int i = 0; i < 3; ++i) {
+        const double* A = V[(i + 1) % 3];
+        const double* B = V[(i + 2) % 3];
+        sub3(a, A, p);
+        sub3(b, B, p);
+        cross3(q, a, b);
+        lam[i] = dot3(n, q) / nn;
+        double e[3];
+        sub3(e, B, A);
+        elen[i] = norm3(e);
+    }
+    const double nl = sqrt(nn);
+    const double cs = fabs(denom) / (nl * norm3(ray->d));
+    double rel = lam[0], clr = lam[0] * nl / elen[0];
+    for (int i = 1; i < 3; ++i) {
+        rel = fmin(rel, lam[i]);
+        clr = fmin(clr, lam[i] * nl / elen[i]);
+    }
+    /* the ray passes the triangle where it spans along the ray, not at the
+     * (possibly very distant) plane point of a grazing ray */
+    const double dd = dot3(ray->d, ray->d);
+    double tlo = OR_INF, thi = -OR_INF;
+    for (int i = 0; i < 3; ++i) {
+        double q0[3];
+        sub3(q0, V[i], ray->o);
+        const double tv = dot3(q0, ray->d) / dd;
+        tlo = fmin(tlo, tv);
+        thi = fmax(thi, tv);
+    }
+    c->rel = rel;
+    c->clr = clr * cs;
+    c->tref = fmin(fmax(t, tlo), thi);
+    c->ok = rel >= 0.0;
+    if (c->ok) {
+        c->nroot = 1;
+        c->t[0] = t;
+        c->cs[0] = cs;
+    }
+}
+
+static void eval_plane(const float* pl, const oray* ray, cand* c) {
+    double n[3];
+    load3f(n, pl);
+    const double h = pl[3];
+    const double nd = dot3(n, ray->d);
+    c->valid = 0;
+    c->ok = 0;
+    c->nroot = 0;
+    if (nd == 0.0) return;
+    c->valid = 1;
+    const double t = (h - dot3(n, ray->o)) / nd;
+    const double cs = fabs(nd) / (norm3(n) * norm3(ray->d));
+    c->rel = cs;
+    c->clr = OR_INF;
+    c->tref = t;
+    c->ok = 1;
+    c->nroot = 1;
+    c->t[0] = t;
+    c->cs[0] = cs;
+}
+
+static int64_t n_prims(const or_scene* sc) { return sc->n_spheres + sc->n_tris + sc->n_planes; }
+
+/* Per-call scene view: the input arrays plus a bounding sphere per triangle
+ * (centroid and the largest vertex distance).  The bounding spheres are a
+ * per-primitive quantity, not an acceleration structure: every primitive is
+ * still examined for every ray. */
+typedef struct {
+    const or_scene* in;
+    double* tb;   /* [n_tris][4] cx cy cz R */
+} oscene;
+
+static int oscene_init(oscene* S, const or_scene* in) {
+    S->in = in;
+    S->tb = NULL;
+    if (in->n_tris <= 0) return 0;
+    S->tb = (double*)malloc(sizeof(double) * 4 * (size_t)in->n_tris);
+    if (!S->tb) return -1;
+    for (int64_t i = 0; i < in->n_tris; ++i) {
+        const float* tv = in->tris + 9 * i;
+        double c[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) c[j] += tv[3 * k + j] / 3.0;
+        double R = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            double q[3] = {tv[3 * k] - c[0], tv[3 * k + 1] - c[1], tv[3 * k + 2] - c[2]};
+            R = fmax(R, norm3(q));
+        }
+        double* b = S->tb + 4 * i;
+        b[0] = c[0]; b[1] = c[1]; b[2] = c[2]; b[3] = R;
+    }
+    return 0;
+}
+
+static void oscene_free(oscene* S) { free(S->tb); }
+
+/* A triangle the ray passes far from is robustly missed: if the ray's line
+ * misses the triangle's bounding sphere by more than twice max(cap * R,
+ * 1e4 * cap * envelope), no admissible perturbation reaches it and its miss
+ * margin exceeds the cap.  It is also skipped when its whole extent along the
+ * ray lies outside the window [lo, hi] of parameters that can still matter. */
+static int tri_skip(const oscene* S, int64_t j, const oray* ray, double lo, double hi) {
+    const double* b = S->tb + 4 * j;
+    double f[3] = {b[0] - ray->o[0], b[1] - ray->o[1], b[2] - ray->o[2]};
+    const double dd = dot3(ray->d, ray->d);
+    const double tc = dot3(f, ray->d) / dd;
+    const double R = b[3];
+    const double dl = sqrt(dd);
+    if (tc + R / dl < lo || tc - R / dl > hi) return 1;
+    double perp2 = dot3(f, f) - tc * tc * dd;
+    if (perp2 < 0) perp2 = 0;
+    const double gap = sqrt(perp2) - R;
+    const double guard = 2.0 * fmax(MARGIN_CAP * R, 1e4 * MARGIN_CAP * envelope(ray, fabs(tc) + R / dl));
+    return gap > guard;
+}
+
+/* ids: spheres 0..ns-1, then triangles, then planes.  [lo, hi] is the window
+ * of ray parameters that can still matter to the query. */
+static void eval_prim(const oscene* S, int64_t id, const oray* ray, double lo, double hi, cand* c) {
+    const or_scene* sc = S->in;
+    if (id < sc->n_spheres) {
+        eval_sphere(sc->spheres + 4 * id, ray, c);
+    } else if (id < sc->n_spheres + sc->n_tris) {
+        const int64_t j = id - sc->n_spheres;
+        if (tri_skip(S, j, ray, lo, hi)) {
+            c->valid = 0;
+            c->ok = 0;
+            c->nroot = 0;
+            return;
+        }
+        eval_tri(sc->tris + 9 * j, ray, c);
+    } else {
+        eval_plane(sc->planes + 4 * (id - sc->n_spheres - sc->n_tris), ray, c);
+    }
+}
+
+/* margin contribution of a root t_c lying outside (0, tmax) or of the hit's own root */
+static double range_margin(const oray* ray, double tc, double cs) {
+    const double oscale = fmax(1.0, maxabs3(ray->o));
+    double m = fabs(tc) / oscale;
+    m = fmin(m, 1e-4 * fabs(tc) * fmax(cs, 1e-12) / (ray->so + EA * maxabs3(ray->o) + 1e-30));
+    if (isfinite(ray->tmax)) {
+        const double dt = fabs(ray->tmax - tc);
+        m = fmin(m, dt / ray->tmax);
+        m = fmin(m, 1e-4 * dt * fmax(cs, 1e-12) / envelope(ray, ray->tmax));
+    }
+    return m;
+}
+
+/* margin of a shape decision (inside when ok, outside otherwise) */
+static double shape_margin(const oray* ray, const cand* c) {
+    double m = fabs(c->rel);
+    if (isfinite(c->clr)) m = fmin(m, 1e-4 * fabs(c->clr) / envelope(ray, c->tref));
+    return m;
+}
+
+typedef struct {
+    double t;
+    int64_t id;
+    double cs;
+    double margin;
+} hitrec;
+
+/* Closest hit over every primitive (brute force), ties to the smaller id. */
+static void closest_hit(const oscene* S, const oray* ray, hitrec* out) {
+    const int64_t N = n_prims(S->in);
+    double t1 = OR_INF, cs1 = 1.0, t2 = OR_INF, cs2 = 1.0;
+    int64_t id1 = -1;
+    cand best;
+    memset(&best, 0, sizeof best);
+    double m_other = MARGIN_CAP;   /* margins of primitives that are not the hit */
+    const double oscale = fmax(1.0, maxabs3(ray->o));
+    for (int64_t id = 0; id < N; ++id) {
+        cand c;
+        /* slack of the relevance window, against the running best */
+        const double tb = fmin(t1, ray->tmax);
+        const double slack = 1e-3 * fmax(oscale, isfinite(tb) ? tb : 0.0);
+        eval_prim(S, id, ray, -slack, tb + slack, &c);
+        if (!c.valid) continue;
+        int hit_root = -1;
+        if (c.ok) {
+            for (int i = 0; i < c.nroot; ++i)
+                if (c.t[i] > 0.0 && c.t[i] < ray->tmax) { hit_root = i; break; }
+        }
+        if (hit_root >= 0) {
+            const double th = c.t[hit_root];
+            if (th < t1 || (th == t1 && id < id1)) {
+                /* previous best becomes a competitor */
+                if (id1 >= 0 && t1 < t2) { t2 = t1; cs2 = cs1; }
+                t1 = th; cs1 = c.cs[hit_root]; id1 = id; best = c;
+            } else if (th < t2) {
+                t2 = th; cs2 = c.cs[hit_root];
+            }
+            /* the primitive's other roots near the segment ends */
+            for (int i = 0; i < c.nroot; ++i)
+                if (i != hit_root && c.t[i] > -slack && c.t[i] < fmin(t1, ray->tmax) + slack)
+                    m_other = fmin(m_other, range_margin(ray, c.t[i], c.cs[i]));
+        } else if (c.ok) {
+            /* shape passes but no root in (0, tmax): range decisions */
+            for (int i = 0; i < c.nroot; ++i)
+                if (c.t[i] > -slack && c.t[i] < tb + slack)
+                    m_other = fmin(m_other, range_margin(ray, c.t[i], c.cs[i]));
+        } else {
+            /* shape test fails: relevant only if the shape decision lies within the window */
+            if (c.tref > -slack && c.tref < tb + slack) m_other = fmin(m_other, shape_margin(ray, &c));
+        }
+    }
+    out->t = t1;
+    out->id = id1;
+    out->cs = cs1;
+    double m = m_other;
+    if (id1 >= 0) {
+        m = fmin(m, shape_margin(ray, &best));
+        m = fmin(m, range_margin(ray, t1, cs1));
+        if (isfinite(t2)) {
+            const double gap = t2 - t1;
+            m = fmin(m, gap / t1);
+            m = fmin(m, 1e-4 * gap * fmin(cs1, cs2) / envelope(ray, t2));
+        }
+    }
+    out->margin = fmin(m, MARGIN_CAP);
+}
+
+/* Any hit in (0, tmax): the shadow loop of Algorithm 1.  Returns 1 if blocked. */
+static int any_hit(const oscene* S, const oray* ray, double* margin) {
+    const int64_t N = n_prims(S->in);
+    double best_blocker = -1.0;  /* best robustness among blockers */
+    double m_free = MARGIN_CAP;  /* robustness of "nothing blocks" */
+    const double slack = 1e-3 * fmax(fmax(1.0, maxabs3(ray->o)), ray->tmax);
+    for (int64_t id = 0; id < N; ++id) {
+        cand c;
+        eval_prim(S, id, ray, -slack, ray->tmax + slack, &c);
+        if (!c.valid) continue;
+        if (c.ok) {
+            for (int i = 0; i < c.nroot; ++i) {
+                const double tc = c.t[i];
+                if (tc > 0.0 && tc < ray->tmax) {
+                    double mb = fmin(shape_margin(ray, &c), range_margin(ray, tc, c.cs[i]));
+                    best_blocker = fmax(best_blocker, mb);
+                } else if (tc > -slack && tc < ray->tmax + slack) {
+                    m_free = fmin(m_free, range_margin(ray, tc, c.cs[i]));
+                }
+            }
+        } else if (c.tref > -slack && c.tref < ray->tmax + slack) {
+            m_free = fmin(m_free, shape_margin(ray, &c));
+        }
+        /* one clearly robust blocker settles the query (break on first blocker) */
+        if (best_blocker >= 1e-2) break;
+    }
+    if (best_blocker >= 0.0) {
+        *margin = fmin(best_blocker, MARGIN_CAP);
+        return 1;
+    }
+    *margin = m_free;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* shading: Whitted recursion with Phong local illumination                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const oscene* S;
+    const or_scene* sc;
+    const or_params* p;
+    double margin;
+    int32_t* counts;   /* [D+1][2]: closest-hit queries, shadow queries */
+    double* rec;       /* optional ray log: [cap][RECW] */
+    int64_t rec_n, rec_cap;
+} pctx;
+
+/* ray log record: kind (0 camera, 1 reflected, 2 refracted, 3 shadow), depth,
+ * o[3], d[3], tmax, t (closest hit) or blocked (shadow), id, margin */
+#define RECW 12
+static void log_ray(pctx* P, int kind, int depth, const oray* r, double t_or_occ, int64_t id, double margin) {
+    if (!P->rec || P->rec_n >= P->rec_cap) { if (P->rec) P->rec_n++; return; }
+    double* q = P->rec + RECW * P->rec_n++;
+    q[0] = kind; q[1] = depth;
+    for (int i = 0; i < 3; ++i) { q[2 + i] = r->o[i]; q[5 + i] = r->d[i]; }
+    q[8] = r->tmax; q[9] = t_or_occ; q[10] = (double)id; q[11] = margin;
+}
+
+static const float* mat_of(const or_scene* sc, int64_t id) {
+    int32_t m;
+    if (id < sc->n_spheres) m = sc->sphere_mat[id];
+    else if (id < sc->n_spheres + sc->n_tris) m = sc->tri_mat[id - sc->n_spheres];
+    else m = sc->plane_mat[id - sc->n_spheres - sc->n_tris];
+    return sc->materials + 10 * m;
+}
+
+/* Outward geometric normal at x; returns the normal's own uncertainty. */
+static double geom_normal(const or_scene* sc, int64_t id, const double* x, double ex, double* n) {
+    if (id < sc->n_spheres) {
+        const float* s = sc->spheres + 4 * id;
+        double c[3];
+        load3f(c, s);
+        sub3(n, x, c);
+        normalize3(n);
+        return ex / s[3] + EA;
+    } else if (id < sc->n_spheres + sc->n_tris) {
+        const float* tv = sc->tris + 9 * (id - sc->n_spheres);
+        double v0[3], v1[3], v2[3], e1[3], e2[3];
+        load3f(v0, tv);
+        load3f(v1, tv + 3);
+        load3f(v2, tv + 6);
+        sub3(e1, v1, v0);
+        sub3(e2, v2, v0);
+        cross3(n, e1, e2);
+        normalize3(n);
+        return EA;
+    } else {
+        const float* pl = sc->planes + 4 * (id - sc->n_spheres - sc->n_tris);
+        load3f(n, pl);
+        normalize3(n);
+        return EA;
+    }
+}
+
+static void trace(pctx* P, const oray* ray, int kind, int k, double* out, int64_t* primary_id) {
+    const or_scene* sc = P->sc;
+    const or_params* p = P->p;
+    P->counts[2 * k + 0] += 1;
+    hitrec h;
+    closest_hit(P->S, ray, &h);
+    P->margin = fmin(P->margin, h.margin);
+    log_ray(P, kind, k, ray, h.t, h.id, h.margin);
+    if (primary_id) *primary_id = h.id;
+    if (h.id < 0) {
+        out[0] = p->bg[0]; out[1] = p->bg[1]; out[2] = p->bg[2];
+        return;
+    }
+    double x[3], ng[3], nf[3], v[3];
+    for (int i = 0; i < 3; ++i) x[i] = ray->o[i] + h.t * ray->d[i];
+    const double ex = envelope(ray, h.t);
+    const double sn = geom_normal(sc, h.id, x, ex, ng);
+    const double dn = dot3(ray->d, ng);
+    const int entering = dn < 0.0;
+    /* which side faces the ray is a discrete decision (two-sided shading) */
+    P->margin = fmin(P->margin, fmin(fabs(dn), 1e-4 * fabs(dn) / (ray->sd + sn + EA)));
+    for (int i = 0; i < 3; ++i) {
+        nf[i] = entering ? ng[i] : -ng[i];
+        v[i] = -ray->d[i];
+    }
+    const float* m = mat_of(sc, h.id);
+    const double alb[3] = {m[0], m[1], m[2]};
+    const double ka = m[3], kd = m[4], ks = m[5], shin = m[6], kr = m[7], ior = m[8];
+    const int type = (int)m[9];
+    const double eps_s = p->eps * fmax(1.0, maxabs3(x));
+    const double so2 = ex + EA * maxabs3(x);
+    double xs[3];
+    for (int i = 0; i < 3; ++i) xs[i] = x[i] + eps_s * nf[i];
+
+    /* ambient: white ambient light of unit intensity */
+    double local[3];
+    for (int i = 0; i < 3; ++i) local[i] = ka * alb[i];
+    for (int l = 0; l < sc->n_lights; ++l) {
+        const float* L = sc->lights + 6 * l;
+        double lp[3], lv[3];
+        load3f(lp, L);
+        sub3(lv, lp, x);
+        normalize3(lv);
+        const double ndl = dot3(nf, lv);
+        if (ndl <= 0.0) continue;
+        double rr[3];
+        for (int i = 0; i < 3; ++i) rr[i] = 2.0 * ndl * nf[i] - lv[i];   /* Phong mirror direction of L */
+        const double rv = fmax(0.0, dot3(rr, v));
+        const double spec = ks * pow(rv, shin);
+        double c[3];
+        double cmax = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            c[i] = (double)L[3 + i] * (kd * alb[i] * ndl + spec);
+            cmax = fmax(cmax, c[i]);
+        }
+        if (!(cmax > 0.0)) continue;
+        oray sr;
+        double sdir[3];
+        sub3(sdir, lp, xs);
+        const double dist = norm3(sdir);
+        for (int i = 0; i < 3; ++i) { sr.o[i] = xs[i]; sr.d[i] = sdir[i] / dist; }
+        sr.tmax = dist;
+        sr.so = so2;
+        sr.sd = so2 / dist + EA;
+        P->counts[2 * k + 1] += 1;
+        double sm;
+        const int blocked = any_hit(P->S, &sr, &sm);
+        P->margin = fmin(P->margin, sm);
+        log_ray(P, 3, k, &sr, (double)blocked, -1, sm);
+        if (!blocked)
+            for (int i = 0; i < 3; ++i) local[i] += c[i];
+    }
+    for (int i = 0; i < 3; ++i) out[i] = local[i];
+    if (k >= p->max_depth) return;
+
+    const double cosi = -dot3(ray->d, nf);   /* > 0 */
+    oray rf;
+    for (int i = 0; i < 3; ++i) {
+        rf.o[i] = xs[i];
+        rf.d[i] = ray->d[i] + 2.0 * cosi * nf[i];
+    }
+    normalize3(rf.d);
+    rf.tmax = OR_INF;
+    rf.so = so2;
+    rf.sd = ray->sd + 2.0 * sn + EA;
+
+    if (type == MAT_DIELECTRIC) {
+        const double eta = entering ? 1.0 / ior : ior;
+        const double k2 = 1.0 - eta * eta * (1.0 - cosi * cosi);
+        P->margin = fmin(P->margin, 1e-4 * fabs(k2) / (2.0 * eta * eta * (ray->sd + sn) + EA));
+        const double r0 = ((ior - 1.0) / (ior + 1.0)) * ((ior - 1.0) / (ior + 1.0));
+        double F = 1.0;
+        oray tr;
+        int has_t = 0;
+        if (k2 >= 0.0) {
+            const double ck = sqrt(k2);
+            const double cc = entering ? cosi : ck;
+            const double om = 1.0 - cc;
+            F = r0 + (1.0 - r0) * om * om * om * om * om;
+            for (int i = 0; i < 3; ++i) {
+                tr.o[i] = x[i] - eps_s * nf[i];
+                tr.d[i] = eta * ray->d[i] + (eta * cosi - ck) * nf[i];
+            }
+            normalize3(tr.d);
+            tr.tmax = OR_INF;
+            tr.so = so2;
+            tr.sd = (ray->sd + 2.0 * sn) * (1.0 + eta / fmax(ck, 1e-2)) + EA;
+            has_t = 1;
+        }
+        double lr[3];
+        trace(P, &rf, 1, k + 1, lr, NULL);
+        for (int i = 0; i < 3; ++i) out[i] += F * lr[i];
+        if (has_t) {
+            double lt[3];
+            trace(P, &tr, 2, k + 1, lt, NULL);
+            for (int i = 0; i < 3; ++i) out[i] += (1.0 - F) * lt[i];
+        }
+    } else if (kr > 0.0) {
+        double lr[3];
+        trace(P, &rf, 1, k + 1, lr, NULL);
+        for (int i = 0; i < 3; ++i) out[i] += kr * lr[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* threading                                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    int64_t next;
+    pthread_mutex_t mu;
+    void (*fn)(void* ctx, int64_t i);
+    void* ctx;
+} pool;
+
+static void* pool_worker(void* arg) {
+    pool* P = (pool*)arg;
+    for (;;) {
+        pthread_mutex_lock(&P->mu);
+        int64_t i = P->next++;
+        pthread_mutex_unlock(&P->mu);
+        if (i >= P->n) break;
+        P->fn(P->ctx, i);
+    }
+    return NULL;
+}
+
+static void run_parallel(int64_t n, int nthreads, void (*fn)(void*, int64_t), void* ctx) {
+    if (nthreads <= 0) nthreads = (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if ((int64_t)nthreads > n) nthreads = (int)(n > 0 ? n : 1);
+    pool P = {n, 0, PTHREAD_MUTEX_INITIALIZER, fn, ctx};
+    pthread_t th[256];
+    for (int i = 0; i < nthreads; ++i) pthread_create(&th[i], NULL, pool_worker, &P);
+    for (int i = 0; i < nthreads; ++i) pthread_join(th[i], NULL);
+}
+
+/* ------------------------------------------------------------------------ */
+/* exported entry points                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const oscene* S;
+    const or_scene* sc;
+    const or_camera* cam;
+    const or_params* p;
+    const int64_t* pixels;
+    double* rgb;
+    int64_t* ids;
+    double* margin;
+    int32_t* counts;
+} render_job;
+
+static void render_one(void* vctx, int64_t i) {
+    render_job* J = (render_job*)vctx;
+    const int D = J->p->max_depth;
+    int32_t local_counts[2 * 64];
+    memset(local_counts, 0, sizeof local_counts);
+    pctx P = {J->S, J->sc, J->p, MARGIN_CAP, local_counts, NULL, 0, 0};
+    double acc[3] = {0, 0, 0};
+    const int64_t pix = J->pixels[i];
+    for (int s = 0; s < J->p->spp; ++s) {
+        oray r;
+        or_camera_ray(J->cam, J->p, pix, s, r.o, r.d);
+        r.tmax = OR_INF;
+        r.so = EA * maxabs3(r.o);
+        r.sd = EA;
+        double L[3];
+        int64_t pid = -1;
+        trace(&P, &r, 0, 0, L, &pid);
+        for (int c = 0; c < 3; ++c) acc[c] += L[c];
+        if (J->ids) J->ids[i * J->p->spp + s] = pid;
+    }
+    for (int c = 0; c < 3; ++c) J->rgb[3 * i + c] = acc[c] / J->p->spp;
+    if (J->margin) J->margin[i] = P.margin;
+    if (J->counts) memcpy(J->counts + i * 2 * (D + 1), local_counts, sizeof(int32_t) * 2 * (D + 1));
+}
+
+/* Render a list of pixels.  rgb [n][3], ids [n][spp] (or NULL), margin [n]
+ * (min over the pixel's ray trees, or NULL), counts [n][D+1][2] (or NULL). */
+int or_render(const or_scene* sc, const or_camera* cam, const or_params* p, const int64_t* pixels, int64_t n,
+              int32_t nthreads, double* rgb, int64_t* ids, double* margin, int32_t* counts) {
+    if (p->max_depth < 0 || p->max_depth > 63 || p->spp < 1) return -1;
+    oscene S;
+    if (oscene_init(&S, sc) != 0) return -2;
+    render_job J = {&S, sc, cam, p, pixels, rgb, ids, margin, counts};
+    run_parallel(n, nthreads, render_one, &J);
+    oscene_free(&S);
+    return 0;
+}
+
+typedef struct {
+    const oscene* S;
+    const double* rays;
+    double* t;
+    int64_t* id;
+    uint8_t* occ;
+    double* margin;
+} ray_job;
+
+static void load_ray(const double* R, oray* r) {
+    for (int i = 0; i < 3; ++i) { r->o[i] = R[i]; r->d[i] = R[3 + i]; }
+    r->tmax = R[6] > 0 ? R[6] : OR_INF;
+    r->so = R[7];
+    r->sd = R[8];
+}
+
+static void closest_one(void* vctx, int64_t i) {
+    ray_job* J = (ray_job*)vctx;
+    oray r;
+    load_ray(J->rays + 9 * i, &r);
+    hitrec h;
+    closest_hit(J->S, &r, &h);
+    J->t[i] = h.t;
+    J->id[i] = h.id;
+    J->margin[i] = h.margin;
+}
+
+static void occluded_one(void* vctx, int64_t i) {
+    ray_job* J = (ray_job*)vctx;
+    oray r;
+    load_ray(J->rays + 9 * i, &r);
+    double m;
+    J->occ[i] = (uint8_t)any_hit(J->S, &r, &m);
+    J->margin[i] = m;
+}
+
+/* rays [n][9]: o(3), d(3), tmax (<= 0 means infinite), so, sd */
+int or_closest(const or_scene* sc, const double* rays, int64_t n, int32_t nthreads, double* t, int64_t* id,
+               double* margin) {
+    oscene S;
+    if (oscene_init(&S, sc) != 0) return -2;
+    ray_job J = {&S, rays, t, id, NULL, margin};
+    run_parallel(n, nthreads, closest_one, &J);
+    oscene_free(&S);
+    return 0;
+}
+
+int or_occluded(const or_scene* sc, const double* rays, int64_t n, int32_t nthreads, uint8_t* occ,
+                double* margin) {
+    oscene S;
+    if (oscene_init(&S, sc) != 0) return -2;
+    ray_job J = {&S, rays, NULL, NULL, occ, margin};
+    run_parallel(n, nthreads, occluded_one, &J);
+    oscene_free(&S);
+    return 0;
+}
+
+/* Ray tree of one pixel sample: every ray the recursion traces, in order.
+ * rec [cap][12] (see log_ray); returns the number of rays (may exceed cap,
+ * in which case only cap were written), or < 0 on error.  rgb [3] receives
+ * the sample's radiance. */
+int64_t or_ray_tree(const or_scene* sc, const or_camera* cam, const or_params* p, int64_t pixel, int32_t sample,
+                    double* rec, int64_t cap, double* rgb) {
+    if (p->max_depth < 0 || p->max_depth > 63) return -1;
+    oscene S;
+    if (oscene_init(&S, sc) != 0) return -2;
+    int32_t counts[2 * 64];
+    memset(counts, 0, sizeof counts);
+    pctx P = {&S, sc, p, MARGIN_CAP, counts, rec, 0, cap};
+    oray r;
+    or_camera_ray(cam, p, pixel, sample, r.o, r.d);
+    r.tmax = OR_INF;
+    r.so = EA * maxabs3(r.o);
+    r.sd = EA;
+    int64_t pid;
+    trace(&P, &r, 0, 0, rgb, &pid);
+    oscene_free(&S);
+    return P.rec_n;
+}
