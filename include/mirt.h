@@ -1,0 +1,220 @@
+/*
+ * mirt.h -- C ABI of the MI355X (gfx950) Whitted ray tracer.
+ *
+ * Method: "Massively Parallel Ray Tracing Algorithm Using GPU" (arXiv
+ * 1504.03151).  An image is made by tracing one ray per pixel and sample
+ * through an image plane (Section III); each ray finds its closest object
+ * (Algorithm 1's object loop), sends a shadow ray to every light (Algorithm
+ * 1's blocker loop, "break" on the first blocker), and spawns reflected and
+ * refracted secondary rays up to a maximum recursion depth (Section III,
+ * Fig. 3), the recursion being run as iterations (Section IV.A).  Spheres
+ * follow Eq. 9-12 (Section IV.B); triangles, planes, the BVH, Phong shading
+ * and Fresnel-weighted dielectrics extend the paper's sphere-only scenes.
+ *
+ * Conventions for every entry point:
+ *  - Every call returns an rt_status (0 = RT_OK, < 0 = error); C++ exceptions
+ *    never cross this boundary.  rt_last_error() returns a thread-local
+ *    message describing the last failure on the calling thread.
+ *  - Host pointers are read during the call only.  Device pointers (scene
+ *    blob, workspace, outputs, stats) are allocated and owned by the caller
+ *    (e.g. with torch); the library never allocates or frees device memory.
+ *  - Device pointers must be 256-byte aligned.
+ *  - GPU work is enqueued on the given HIP stream (NULL = the null stream)
+ *    and the call returns after enqueueing, unless RT_FLAG_SYNC is set.
+ *  - Primitive ids: sphere i -> i; triangle j -> n_spheres + j; plane k ->
+ *    n_spheres + n_tris + k; miss -> -1.  The BVH reorders primitives
+ *    internally but every output carries the original ids.
+ */
+#ifndef MIRT_H
+#define MIRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rt_status;
+enum {
+    RT_OK = 0,
+    RT_ERR_INVALID_ARG = -1,    /* NULL, NaN/Inf, r <= 0, bad material index, zero sizes ... */
+    RT_ERR_UNSUPPORTED = -2,    /* valid request this build does not handle */
+    RT_ERR_HIP = -3,            /* a HIP runtime call failed */
+    RT_ERR_BVH_DEPTH = -4,      /* BVH deeper than rt_build_opts.max_depth */
+    RT_ERR_CAPACITY = -5,       /* workspace too small, or a ray queue overflowed */
+    RT_ERR_DEVICE_STATUS = -6,  /* the device reported a fault in rt_stats.status */
+    RT_ERR_NOT_UPLOADED = -7    /* rt_scene_upload has not been called */
+};
+
+enum { RT_MAT_PHONG = 0, RT_MAT_MIRROR = 1, RT_MAT_DIELECTRIC = 2 };
+
+/* Phong reflection model: local = k_a*albedo + sum over unblocked lights of
+ * I * (k_d*albedo*max(N.L,0) + k_s*max(R.V,0)^shininess), R the mirror
+ * direction of L (Phong, not Blinn).  PHONG and MIRROR add k_r * (reflected
+ * radiance); DIELECTRIC adds F * reflected + (1-F) * transmitted radiance with
+ * Schlick's F and index of refraction ior (air outside). 40 bytes. */
+typedef struct {
+    float albedo[3];
+    float k_a, k_d, k_s, shininess, k_r, ior;
+    int32_t type;
+} rt_material;
+
+typedef struct {
+    float pos[3];
+    float intensity[3];
+} rt_light;
+
+/* Scene arrays (host memory, copied by rt_build_scene). */
+typedef struct {
+    const float* spheres;        /* [n_spheres][4]  cx, cy, cz, r (r > 0) */
+    int64_t n_spheres;
+    const int32_t* sphere_mat;   /* [n_spheres] material index */
+    const float* tris;           /* [n_tris][3][3]  vertices, counter-clockwise seen from outside */
+    int64_t n_tris;
+    const int32_t* tri_mat;      /* [n_tris] */
+    const float* planes;         /* [n_planes][4]  nx, ny, nz, h with n.x = h, |n| = 1 */
+    int64_t n_planes;
+    const int32_t* plane_mat;    /* [n_planes] */
+    const rt_material* materials;
+    int32_t n_materials;
+    const rt_light* lights;      /* point lights */
+    int32_t n_lights;
+} rt_scene_desc;
+
+/* BVH build options; zero fields take the defaults in brackets. */
+typedef struct {
+    int32_t leaf_max;     /* [4]  split while a node holds more primitives (<= 15) */
+    int32_t sah_bins;     /* [32] centroid bins per axis of the binned SAH build */
+    int32_t max_depth;    /* [60] deeper trees fail with RT_ERR_BVH_DEPTH (<= 61: LDS stack budget) */
+    int32_t node_layout;  /* [0]  0 = depth-first order (left child at index + 1) */
+} rt_build_opts;
+
+/* Pinhole camera: vfov_deg is the vertical field of view; pixel row 0 is the
+ * top row; right = normalize(up x forward); pixel (px, py), sample offset
+ * (jx, jy) in [0,1)^2 looks along normalize(f + X r + Y u) with
+ * X = (2 (px + jx) / W - 1) (W / H) tan(vfov/2), Y = (1 - 2 (py + jy) / H) tan(vfov/2). */
+typedef struct {
+    float eye[3], look_at[3], up[3];
+    float vfov_deg;
+    int32_t width, height;
+} rt_camera;
+
+enum {
+    RT_FLAG_SYNC = 1,        /* synchronize the stream and check rt_stats.status before returning */
+    RT_FLAG_COUNT_WORK = 2,  /* count BVH node visits and primitive tests into rt_stats (slower) */
+    RT_FLAG_NO_GRAPH = 4,    /* launch kernels one by one instead of replaying a captured HIP graph */
+    RT_FLAG_TIME_KERNELS = 8 /* record HIP events around every traversal and shading launch on the
+                                frame's stream (implies RT_FLAG_NO_GRAPH); read with rt_kernel_times */
+};
+
+/* Per-frame rendering parameters. */
+typedef struct {
+    int32_t spp;              /* samples per pixel (>= 1); a square count is stratified */
+    int32_t max_depth;        /* secondary rays spawn while depth < max_depth; primary = depth 0 (<= 15) */
+    int32_t jitter;           /* 0: sample centres; 1: jitter from the PCG hash of (seed, frame, pixel, sample) */
+    uint32_t frame;
+    uint64_t seed;
+    float bg[3];              /* radiance of rays that miss */
+    float eps;                /* origin offset of spawned rays: eps * max(1, max|x_i|) along the normal */
+    int32_t samples_per_pass; /* samples traced per wavefront pass; 0 = chosen from the workspace */
+    int32_t flags;            /* RT_FLAG_* */
+    float queue_factor;       /* ray-queue capacity per pass, in primary rays (0 = 2.0) */
+    int32_t reserved;
+    void* workspace;          /* device, rt_render_workspace_bytes() bytes */
+    size_t workspace_bytes;
+    void* stats;              /* device rt_stats or NULL; accumulated, caller zeroes it */
+    void* stream;             /* hipStream_t */
+} rt_params;
+
+#define RT_STATS_MAX_DEPTH 16
+/* Device-side counters, accumulated by rt_render (caller zeroes them). */
+typedef struct {
+    uint32_t status;          /* bit 0: ray queue overflow; bit 1: shadow queue overflow */
+    uint32_t passes;
+    uint64_t rays[RT_STATS_MAX_DEPTH];    /* closest-hit queries issued per depth */
+    uint64_t shadow[RT_STATS_MAX_DEPTH];  /* shadow (any-hit) queries issued per depth */
+    uint64_t node_visits;     /* with RT_FLAG_COUNT_WORK: BVH nodes fetched by closest-hit queries */
+    uint64_t tri_tests;       /* ... ray/triangle tests of closest-hit queries */
+    uint64_t sphere_tests;    /* ... ray/sphere tests of closest-hit queries */
+    uint64_t shadow_node_visits, shadow_tri_tests, shadow_sphere_tests;
+} rt_stats;
+
+typedef struct rt_scene rt_scene;   /* opaque, host memory only */
+
+typedef struct {
+    int64_t n_nodes;
+    int32_t depth;          /* BVH depth (root = 0) */
+    int32_t stack_size;     /* traversal stack entries a ray needs */
+    int64_t n_leaves;
+    int64_t n_bvh_prims;    /* spheres + triangles */
+    double sah_cost;
+    double build_seconds;
+    float bounds_lo[3], bounds_hi[3];   /* scene bounds (spheres and triangles) */
+} rt_scene_info;
+
+/* Validate the description, build a binned-SAH binary BVH over spheres and
+ * triangles (planes stay in a list), pack 64-byte nodes and 48-byte leaf-order
+ * primitive records.  Copies all inputs.  Errors: RT_ERR_INVALID_ARG (NULL
+ * arrays with non-zero counts, non-finite values, r <= 0, |plane n| not 1,
+ * material index out of range, n_lights < 0), RT_ERR_BVH_DEPTH. */
+rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, rt_scene** out);
+void rt_destroy_scene(rt_scene* scene);
+rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* out);
+
+/* Bytes of the device blob (nodes | primitives | normals | planes | materials | lights). */
+size_t rt_scene_device_bytes(const rt_scene* scene);
+/* Copy the blob into caller-owned device memory dev_ptr (>= rt_scene_device_bytes)
+ * on stream; the scene keeps dev_ptr, which must stay valid while it is used. */
+rt_status rt_scene_upload(rt_scene* scene, void* dev_ptr, size_t bytes, void* stream);
+
+/* Workspace bytes rt_render needs for this camera and parameters (queues,
+ * accumulator, counters).  Returns 0 and sets the last error for invalid input. */
+size_t rt_render_workspace_bytes(const rt_scene* scene, const rt_camera* cam, const rt_params* params);
+
+/* Render one frame.  out_rgb: device float [H][W][3], linear radiance averaged
+ * over spp (no clamp, no gamma).  out_hit_ids: device int32 [H][W][spp], the
+ * original id of each primary ray's closest hit (-1 miss), or NULL. */
+rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params* params, float* out_rgb,
+                    int32_t* out_hit_ids);
+
+/* Render n scenes in one batched wavefront (one queue shared by all scenes).
+ * cams[i], params[i] as for rt_render except that workspace, stats, stream and
+ * flags are taken from params[0]; workspace from rt_render_batch_workspace_bytes. */
+size_t rt_render_batch_workspace_bytes(const rt_scene* const* scenes, const rt_camera* cams,
+                                       const rt_params* params, int32_t n);
+rt_status rt_render_batch(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params,
+                          int32_t n, float* const* out_rgb, int32_t* const* out_hit_ids);
+
+/* Closest hit of n arbitrary rays.  rays: device float [n][8] = ox, oy, oz,
+ * dx, dy, dz (unit length), tmin (ignored, the range is (0, tmax)), tmax
+ * (<= 0 or inf: unbounded).  Outputs (device): t [n] (inf on a miss), id [n]
+ * original ids (-1 miss).  workspace: device, >= 64 bytes (counters). */
+rt_status rt_intersect(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id,
+                       void* workspace, void* stream);
+/* Any hit in (0, tmax) of n rays (same layout; tmax must be finite and > 0);
+ * occluded [n] device uint8 (1 = blocked). */
+rt_status rt_occluded(const rt_scene* scene, const float* rays, int64_t n, uint8_t* occluded, void* workspace,
+                      void* stream);
+
+/* Host FP32 traversal of the same packed BVH (the fair CPU comparison and the
+ * source of per-ray work counts).  rays, t, id, work are HOST arrays; work
+ * [n][3] (node visits, triangle tests, sphere tests) may be NULL.
+ * any_hit = 1 answers the shadow query (id = hit or -1). nthreads <= 0: all cores. */
+rt_status rt_host_trace(const rt_scene* scene, const float* rays, int64_t n, int32_t any_hit, float* t,
+                        int32_t* id, uint32_t* work, int32_t nthreads);
+
+/* Kernel timings recorded by frames rendered with RT_FLAG_TIME_KERNELS since
+ * the last reset: total milliseconds and launch counts of the closest-hit
+ * (index 0), shading (1) and shadow any-hit (2) kernels.  Waits for the
+ * recorded events.  ms [3] and launches [3] are host arrays; reset != 0
+ * clears the totals after reading. */
+rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset);
+
+const char* rt_last_error(void);
+const char* rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIRT_H */

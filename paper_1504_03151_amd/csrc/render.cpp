@@ -1,0 +1,1092 @@
+// render.cpp -- gfx950 wavefront kernels and the rt_render / rt_intersect /
+// rt_occluded launchers.
+//
+// One frame (Section IV.A: the recursion runs as iterations; Section V: each
+// pass adds its colour into the pixels):
+//   acc = 0
+//   for each pass of samples:
+//     raygen               -> ray queue Q0 (SoA)
+//     for depth k = 0..D:
+//       extend  (Q_k)      -> hit buffer      closest hit, BVH in HBM, stack in LDS
+//       shade   (Q_k, H)   -> acc += w*local-ambient/bg; shadow queue S; Q_{k+1}
+//       shadow  (S)        -> acc += contribution of unblocked lights
+//   resolve                -> out_rgb = acc / spp
+// Queue tails live in device counters, so no step reads anything back to the
+// host and the whole frame can be captured in a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mirt_internal.h"
+
+namespace mirt {
+
+#define HIP_TRY(x)                                                                   \
+    do {                                                                             \
+        hipError_t err_ = (x);                                                       \
+        if (err_ != hipSuccess) {                                                    \
+            set_error(std::string(#x) + ": " + hipGetErrorString(err_));            \
+            return RT_ERR_HIP;                                                       \
+        }                                                                            \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// queues
+// ---------------------------------------------------------------------------
+struct RayQ {
+    float *ox, *oy, *oz, *dx, *dy, *dz, *wr, *wg, *wb;
+    uint32_t *pix, *meta;   // meta: depth (bits 0-3) | sample (bits 4-19) | scene (bits 20-31)
+};
+struct ShadowQ {
+    float *ox, *oy, *oz, *dx, *dy, *dz, *tmax, *cr, *cg, *cb;
+    uint32_t* pix;
+};
+struct HitQ {
+    float* t;
+    int* prim;
+};
+
+// counters (uint32) inside the workspace, reset at the start of each pass
+constexpr int kCtrRays = 0;       // [16] rays queued at depth k
+constexpr int kCtrRayCur = 16;    // [16] extend fetch cursors
+constexpr int kCtrShadow = 32;    // [16] shadow rays queued at depth k
+constexpr int kCtrShadowCur = 48; // [16] shadow fetch cursors
+constexpr int kCtrStatus = 64;    // overflow flags
+constexpr int kCtrWords = 128;
+
+struct CamConst {
+    double eye[3], f[3], r[3], u[3];
+    double th, aspect;
+    int W, H, spp, jitter, m;   // m = sqrt(spp) when spp is a perfect square > 1, else 0
+    uint32_t frame;
+    uint64_t seed;
+};
+
+struct ShadeConst {
+    float bg[3];
+    float eps;
+    int max_depth;
+    int spp;
+    uint32_t qcap, scap;
+};
+
+// ---------------------------------------------------------------------------
+// wave helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// exclusive prefix sum of v over the wave; total in *tot (all lanes must call)
+__device__ __forceinline__ uint32_t wave_scan(uint32_t v, uint32_t& tot) {
+    uint32_t x = v;
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    tot = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// reserve n_lane slots per lane in a queue with one atomic per wave; returns
+// the lane's first slot (all lanes must call)
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t n_lane, uint32_t* tail) {
+    uint32_t tot;
+    const uint32_t off = wave_scan(n_lane, tot);
+    uint32_t base = 0;
+    if (lane_id() == 0 && tot) base = atomicAdd(tail, tot);
+    base = __shfl(base, 0, 64);
+    return base + off;
+}
+
+struct LdsStack {
+    int32_t* p;   // this lane's column
+    int sp;
+    __device__ void reset() {
+        p[0] = kStackDone;
+        sp = 1;
+    }
+    __device__ void push(int32_t v) {
+        p[sp * 64] = v;
+        ++sp;
+    }
+    __device__ int32_t pop() {
+        --sp;
+        return p[sp * 64];
+    }
+};
+
+__device__ __forceinline__ LdsStack lds_stack(int32_t* smem, int stack_size) {
+    LdsStack s;
+    s.p = smem + (threadIdx.x >> 6) * stack_size * 64 + (threadIdx.x & 63);
+    s.sp = 0;
+    return s;
+}
+
+template <bool COUNT>
+__device__ __forceinline__ void flush_work(const Work& w, unsigned long long* dst) {
+    if (!COUNT || !dst) return;
+    uint32_t tn, tt, tsph;
+    wave_scan(w.nodes, tn);
+    wave_scan(w.tris, tt);
+    wave_scan(w.spheres, tsph);
+    if (lane_id() == 0) {
+        atomicAdd(dst + 0, (unsigned long long)tn);
+        atomicAdd(dst + 1, (unsigned long long)tt);
+        atomicAdd(dst + 2, (unsigned long long)tsph);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+__global__ void k_zero_u32(uint32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+__global__ void k_fill_f32(float* p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// One thread per (pixel, sample); a wave covers an 8x8 pixel tile of one
+// sample, so primary rays of a wave are coherent.  The camera ray is formed in
+// FP64 and rounded once to FP32.
+__global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, int tiles_x, int64_t n_threads,
+                                                RayQ q, uint32_t* ctr, uint32_t cap) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t tile_sample = g >> 6;
+    const int64_t tile = tile_sample / ns;
+    const int s = s0 + (int)(tile_sample % ns);
+    const int px = (int)(tile % tiles_x) * 8 + (lane & 7);
+    const int py = (int)(tile / tiles_x) * 8 + (lane >> 3);
+    const bool valid = g < n_threads && px < cam.W && py < cam.H;
+    const uint32_t slot = wave_reserve(valid ? 1u : 0u, ctr + kCtrRays);
+    if (!valid) return;
+    if (slot >= cap) {
+        atomicOr(ctr + kCtrStatus, 1u);
+        return;
+    }
+    const uint32_t pixel = (uint32_t)py * cam.W + px;
+    double jx = 0.5, jy = 0.5, xi0 = 0.5, xi1 = 0.5;
+    if (cam.jitter) {
+        xi0 = jitter01(cam.seed, cam.frame, pixel, (uint32_t)s, 0);
+        xi1 = jitter01(cam.seed, cam.frame, pixel, (uint32_t)s, 1);
+    }
+    if (cam.m > 0) {
+        jx = ((double)(s % cam.m) + xi0) / cam.m;
+        jy = ((double)(s / cam.m) + xi1) / cam.m;
+    } else {
+        jx = xi0;
+        jy = xi1;
+    }
+    const double X = (2.0 * ((double)px + jx) / cam.W - 1.0) * cam.aspect * cam.th;
+    const double Y = (1.0 - 2.0 * ((double)py + jy) / cam.H) * cam.th;
+    double d[3];
+    for (int i = 0; i < 3; ++i) d[i] = cam.f[i] + X * cam.r[i] + Y * cam.u[i];
+    const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    q.ox[slot] = (float)cam.eye[0];
+    q.oy[slot] = (float)cam.eye[1];
+    q.oz[slot] = (float)cam.eye[2];
+    q.dx[slot] = (float)(d[0] * inv);
+    q.dy[slot] = (float)(d[1] * inv);
+    q.dz[slot] = (float)(d[2] * inv);
+    q.wr[slot] = 1.0f;
+    q.wg[slot] = 1.0f;
+    q.wb[slot] = 1.0f;
+    q.pix[slot] = pixel;
+    q.meta[slot] = ((uint32_t)s << 4);
+}
+
+// Persistent closest-hit kernel: each wave grabs 64 queued rays at a time
+// until the queue is drained.  Sources/sinks are the ray queue and hit buffer.
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_extend(DevScene sc, RayQ q, HitQ hit, const uint32_t* count_p,
+                                                uint32_t* cursor, uint32_t cap, unsigned long long* work_out) {
+    extern __shared__ int32_t smem[];
+    LdsStack stk = lds_stack(smem, sc.stack_size);
+    const uint32_t count = min(*count_p, cap);   // a producer that overflowed still bumped the tail
+    Work w{0, 0, 0};
+    for (;;) {
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(cursor, 64u);
+        base = __shfl(base, 0, 64);
+        if (base >= count) break;
+        const uint32_t i = base + lane_id();
+        if (i < count) {
+            const TRay r = make_tray(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
+            const Hit h = traverse<false, COUNT>(sc, r, INFINITY, stk, w);
+            hit.t[i] = h.t;
+            hit.prim[i] = h.prim;
+        }
+    }
+    flush_work<COUNT>(w, work_out);
+}
+
+// Persistent any-hit kernel over the shadow queue; adds the contribution of
+// each unblocked light to its pixel.
+template <bool COUNT>
+__global__ __launch_bounds__(256) void k_shadow(DevScene sc, ShadowQ s, const uint32_t* count_p, uint32_t* cursor,
+                                                uint32_t cap, float* acc, unsigned long long* work_out) {
+    extern __shared__ int32_t smem[];
+    LdsStack stk = lds_stack(smem, sc.stack_size);
+    const uint32_t count = min(*count_p, cap);
+    Work w{0, 0, 0};
+    for (;;) {
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(cursor, 64u);
+        base = __shfl(base, 0, 64);
+        if (base >= count) break;
+        const uint32_t i = base + lane_id();
+        if (i < count) {
+            const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
+            const Hit h = traverse<true, COUNT>(sc, r, s.tmax[i], stk, w);
+            if (h.prim < 0) {
+                const uint32_t p = s.pix[i];
+                atomicAdd(acc + 3 * p + 0, s.cr[i]);
+                atomicAdd(acc + 3 * p + 1, s.cg[i]);
+                atomicAdd(acc + 3 * p + 2, s.cb[i]);
+            }
+        }
+    }
+    flush_work<COUNT>(w, work_out);
+}
+
+// x^n for a non-negative integer n by repeated squaring; other exponents use powf.
+__device__ __forceinline__ float pow_spec(float x, float n) {
+    if (n == floorf(n) && n <= 4096.0f) {
+        int e = (int)n;
+        float r = 1.0f, b = x;
+        while (e) {
+            if (e & 1) r *= b;
+            b *= b;
+            e >>= 1;
+        }
+        return r;
+    }
+    return powf(x, n);
+}
+
+// Shading of one depth: Phong local terms (ambient now, light terms deferred to
+// the shadow kernel), reflected / refracted rays into the next queue, with
+// wave-wide compaction (one atomic per wave and queue).
+__global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ qin, HitQ hit, uint32_t* ctr, int depth,
+                                               RayQ qout, ShadowQ sq, float* acc, int32_t* out_ids) {
+    const uint32_t count = min(ctr[kCtrRays + depth], c.qcap);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t wave_base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    for (uint32_t wb = wave_base0; wb < count; wb += stride) {
+        const uint32_t i = wb + lane_id();
+        const bool active = i < count;
+        int prim = -1;
+        uint32_t pix = 0, meta = 0;
+        V3 o = v3(0, 0, 0), d = v3(0, 0, 1), w = v3(0, 0, 0);
+        float t = 0.0f;
+        if (active) {
+            prim = hit.prim[i];
+            t = hit.t[i];
+            pix = qin.pix[i];
+            meta = qin.meta[i];
+            o = v3(qin.ox[i], qin.oy[i], qin.oz[i]);
+            d = v3(qin.dx[i], qin.dy[i], qin.dz[i]);
+            w = v3(qin.wr[i], qin.wg[i], qin.wb[i]);
+            if (depth == 0 && out_ids) {
+                int oid = -1;
+                if (prim >= sc.n_bvh) oid = prim;
+                else if (prim >= 0) oid = as_int_f(sc.prims[3 * prim].w);
+                out_ids[(size_t)pix * c.spp + ((meta >> 4) & 0xFFFFu)] = oid;
+            }
+        }
+        const bool shade = active && prim >= 0;
+        if (active && prim < 0) {
+            atomicAdd(acc + 3 * pix + 0, w.x * c.bg[0]);
+            atomicAdd(acc + 3 * pix + 1, w.y * c.bg[1]);
+            atomicAdd(acc + 3 * pix + 2, w.z * c.bg[2]);
+        }
+        // hit point, geometric normal, material
+        V3 x = v3(0, 0, 0), ng = v3(0, 0, 1);
+        int mat = 0;
+        if (shade) {
+            x = v3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
+            if (prim >= sc.n_bvh) {
+                const float4 pl = sc.planes[prim - sc.n_bvh];
+                ng = xyz(pl);
+                mat = sc.plane_mat[prim - sc.n_bvh];
+            } else {
+                const float4 p0 = sc.prims[3 * prim];
+                const float4 p1 = sc.prims[3 * prim + 1];
+                mat = as_int_f(p1.w);
+                if (as_int_f(p0.w) < sc.n_spheres) {
+                    ng = (x - xyz(p0)) * p1.z;
+                    ng = ng * (1.0f / sqrtf(dot(ng, ng)));
+                } else {
+                    ng = xyz(sc.normals[prim]);
+                }
+            }
+        }
+        const float dn = dot(d, ng);
+        const bool entering = dn < 0.0f;
+        const V3 nf = entering ? ng : -ng;
+        const DevMaterial M = sc.mats[mat];
+        const V3 alb = xyz(M.a);
+        const float ka = M.a.w, kd = M.b.x, ks = M.b.y, shin = M.b.z, kr = M.b.w, ior = M.c.x;
+        const int type = (int)M.c.y;
+        const float eps_s = c.eps * fmaxf(1.0f, maxabs(x));
+        const V3 xs = x + eps_s * nf;
+        if (shade && ka > 0.0f) {
+            atomicAdd(acc + 3 * pix + 0, w.x * ka * alb.x);
+            atomicAdd(acc + 3 * pix + 1, w.y * ka * alb.y);
+            atomicAdd(acc + 3 * pix + 2, w.z * ka * alb.z);
+        }
+        // shadow rays: count, reserve, then write
+        uint32_t n_sh = 0;
+        if (shade) {
+            for (int l = 0; l < sc.n_lights; ++l) {
+                const DevLight L = sc.lights[l];
+                V3 lv = xyz(L.pos) - x;
+                lv = lv * (1.0f / sqrtf(dot(lv, lv)));
+                const float ndl = dot(nf, lv);
+                if (ndl <= 0.0f) continue;
+                const V3 rr = (2.0f * ndl) * nf - lv;
+                const float rv = fmaxf(0.0f, -dot(rr, d));
+                const float spec = ks * pow_spec(rv, shin);
+                const V3 I = xyz(L.intensity);
+                const float cr = I.x * (kd * alb.x * ndl + spec), cg = I.y * (kd * alb.y * ndl + spec),
+                            cb = I.z * (kd * alb.z * ndl + spec);
+                if (fmaxf(cr, fmaxf(cg, cb)) > 0.0f) n_sh++;
+            }
+        }
+        uint32_t sslot = wave_reserve(n_sh, ctr + kCtrShadow + depth);
+        if (n_sh) {
+            for (int l = 0; l < sc.n_lights; ++l) {
+                const DevLight L = sc.lights[l];
+                V3 lv = xyz(L.pos) - x;
+                lv = lv * (1.0f / sqrtf(dot(lv, lv)));
+                const float ndl = dot(nf, lv);
+                if (ndl <= 0.0f) continue;
+                const V3 rr = (2.0f * ndl) * nf - lv;
+                const float rv = fmaxf(0.0f, -dot(rr, d));
+                const float spec = ks * pow_spec(rv, shin);
+                const V3 I = xyz(L.intensity);
+                const float cr = I.x * (kd * alb.x * ndl + spec), cg = I.y * (kd * alb.y * ndl + spec),
+                            cb = I.z * (kd * alb.z * ndl + spec);
+                if (!(fmaxf(cr, fmaxf(cg, cb)) > 0.0f)) continue;
+                if (sslot >= c.scap) {
+                    atomicOr(ctr + kCtrStatus, 2u);
+                    break;
+                }
+                V3 sd = xyz(L.pos) - xs;
+                const float dist = sqrtf(dot(sd, sd));
+                sd = sd * (1.0f / dist);
+                sq.ox[sslot] = xs.x;
+                sq.oy[sslot] = xs.y;
+                sq.oz[sslot] = xs.z;
+                sq.dx[sslot] = sd.x;
+                sq.dy[sslot] = sd.y;
+                sq.dz[sslot] = sd.z;
+                sq.tmax[sslot] = dist;
+                sq.cr[sslot] = w.x * cr;
+                sq.cg[sslot] = w.y * cg;
+                sq.cb[sslot] = w.z * cb;
+                sq.pix[sslot] = pix;
+                sslot++;
+            }
+        }
+        // secondary rays
+        bool want_r = false, want_t = false;
+        float wr_s = 0.0f, wt_s = 0.0f;
+        V3 dr = v3(0, 0, 0), dt = v3(0, 0, 0);
+        const float cosi = -dn * (entering ? 1.0f : -1.0f);   // = -d.nf > 0
+        if (shade && depth < c.max_depth) {
+            dr = d + (2.0f * cosi) * nf;
+            dr = dr * (1.0f / sqrtf(dot(dr, dr)));
+            if (type == RT_MAT_DIELECTRIC) {
+                const float eta = entering ? 1.0f / ior : ior;
+                const float k2 = 1.0f - eta * eta * (1.0f - cosi * cosi);
+                const float r0 = ((ior - 1.0f) / (ior + 1.0f)) * ((ior - 1.0f) / (ior + 1.0f));
+                float F = 1.0f;
+                if (k2 >= 0.0f) {
+                    const float ck = sqrtf(k2);
+                    const float cc = entering ? cosi : ck;
+                    const float om = 1.0f - cc;
+                    F = r0 + (1.0f - r0) * (om * om * om * om * om);
+                    dt = eta * d + (eta * cosi - ck) * nf;
+                    dt = dt * (1.0f / sqrtf(dot(dt, dt)));
+                    want_t = true;
+                    wt_s = 1.0f - F;
+                }
+                want_r = true;
+                wr_s = F;
+            } else if (kr > 0.0f) {
+                want_r = true;
+                wr_s = kr;
+            }
+        }
+        const uint32_t nsec = (want_r ? 1u : 0u) + (want_t ? 1u : 0u);
+        uint32_t qslot = wave_reserve(nsec, ctr + kCtrRays + depth + 1);
+        const uint32_t meta_next = (meta & ~15u) | (uint32_t)(depth + 1);
+        if (want_r) {
+            if (qslot < c.qcap) {
+                qout.ox[qslot] = xs.x;
+                qout.oy[qslot] = xs.y;
+                qout.oz[qslot] = xs.z;
+                qout.dx[qslot] = dr.x;
+                qout.dy[qslot] = dr.y;
+                qout.dz[qslot] = dr.z;
+                qout.wr[qslot] = w.x * wr_s;
+                qout.wg[qslot] = w.y * wr_s;
+                qout.wb[qslot] = w.z * wr_s;
+                qout.pix[qslot] = pix;
+                qout.meta[qslot] = meta_next;
+            } else {
+                atomicOr(ctr + kCtrStatus, 1u);
+            }
+            qslot++;
+        }
+        if (want_t) {
+            if (qslot < c.qcap) {
+                const V3 xt = x - eps_s * nf;
+                qout.ox[qslot] = xt.x;
+                qout.oy[qslot] = xt.y;
+                qout.oz[qslot] = xt.z;
+                qout.dx[qslot] = dt.x;
+                qout.dy[qslot] = dt.y;
+                qout.dz[qslot] = dt.z;
+                qout.wr[qslot] = w.x * wt_s;
+                qout.wg[qslot] = w.y * wt_s;
+                qout.wb[qslot] = w.z * wt_s;
+                qout.pix[qslot] = pix;
+                qout.meta[qslot] = meta_next;
+            } else {
+                atomicOr(ctr + kCtrStatus, 1u);
+            }
+        }
+    }
+}
+
+__global__ void k_resolve(const float* acc, float* out, int64_t n3, float inv_spp) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3) out[i] = acc[i] * inv_spp;
+}
+
+// fold a pass's queue counters into the caller's statistics
+__global__ void k_stats(const uint32_t* ctr, rt_stats* st, int max_depth) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!st) return;
+    st->status |= ctr[kCtrStatus];
+    st->passes += 1;
+    for (int k = 0; k <= max_depth && k < RT_STATS_MAX_DEPTH; ++k) {
+        st->rays[k] += (uint64_t)min(ctr[kCtrRays + k], 0xFFFFFFFFu);
+        st->shadow[k] += (uint64_t)ctr[kCtrShadow + k];
+    }
+}
+
+// rays [n][8] -> queue; and hit buffer -> (t, original id)
+__global__ void k_load_rays(const float* rays, int64_t n, RayQ q, ShadowQ s, int to_shadow) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* R = rays + 8 * i;
+    float tmax = R[7];
+    if (!(tmax > 0.0f)) tmax = INFINITY;
+    if (to_shadow) {
+        s.ox[i] = R[0]; s.oy[i] = R[1]; s.oz[i] = R[2];
+        s.dx[i] = R[3]; s.dy[i] = R[4]; s.dz[i] = R[5];
+        s.tmax[i] = tmax;
+    } else {
+        q.ox[i] = R[0]; q.oy[i] = R[1]; q.oz[i] = R[2];
+        q.dx[i] = R[3]; q.dy[i] = R[4]; q.dz[i] = R[5];
+    }
+}
+
+// Persistent kernels over caller rays (rt_intersect / rt_occluded): same traversal.
+template <bool ANY>
+__global__ __launch_bounds__(256) void k_trace_rays(DevScene sc, const float* rays, int64_t n, float* t_out,
+                                                    int32_t* id_out, uint8_t* occ_out, uint32_t* cursor) {
+    extern __shared__ int32_t smem[];
+    LdsStack stk = lds_stack(smem, sc.stack_size);
+    Work w{0, 0, 0};
+    for (;;) {
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(cursor, 64u);
+        base = __shfl(base, 0, 64);
+        if ((int64_t)base >= n) break;
+        const int64_t i = (int64_t)base + lane_id();
+        if (i < n) {
+            const float* R = rays + 8 * i;
+            float tmax = R[7];
+            if (!(tmax > 0.0f)) tmax = INFINITY;
+            const TRay r = make_tray(v3(R[0], R[1], R[2]), v3(R[3], R[4], R[5]));
+            const Hit h = traverse<ANY, false>(sc, r, tmax, stk, w);
+            if (ANY) {
+                occ_out[i] = h.prim >= 0 ? 1 : 0;
+            } else {
+                t_out[i] = h.prim >= 0 ? h.t : INFINITY;
+                id_out[i] = h.prim >= 0 ? h.id : -1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side: device properties, occupancy, workspace plan
+// ---------------------------------------------------------------------------
+struct DevInfo {
+    int cus = 0;
+    int max_lds = 0;
+};
+
+static rt_status device_info(DevInfo& out) {
+    static std::mutex mu;
+    static std::map<int, DevInfo> cache;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) {
+        out = it->second;
+        return RT_OK;
+    }
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, dev));
+    DevInfo d;
+    d.cus = p.multiProcessorCount;
+    d.max_lds = (int)p.sharedMemPerBlock;
+    cache[dev] = d;
+    out = d;
+    return RT_OK;
+}
+
+// blocks of 256 threads for a persistent traversal kernel: fill every CU to
+// the occupancy its LDS stack and registers allow
+template <class K>
+static rt_status persistent_grid(K kernel, size_t lds, int& blocks) {
+    DevInfo di;
+    rt_status st = device_info(di);
+    if (st != RT_OK) return st;
+    int per_cu = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds));
+    blocks = std::max(1, per_cu) * std::max(1, di.cus);
+    return RT_OK;
+}
+
+struct Plan {
+    int64_t npix = 0;
+    int spp_pass = 1, passes = 1;
+    int64_t n_primary = 0;   // rays of a full pass
+    uint32_t qcap = 0, scap = 0;
+    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, total = 0;
+};
+
+static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params& p, Plan& pl, std::string& why) {
+    if (cam.width <= 0 || cam.height <= 0) {
+        why = "camera width and height must be > 0";
+        return false;
+    }
+    if (p.spp < 1 || p.spp > 65535) {
+        why = "spp must be in [1, 65535]";
+        return false;
+    }
+    if (p.max_depth < 0 || p.max_depth > RT_STATS_MAX_DEPTH - 2) {
+        why = "max_depth must be in [0, 14]";
+        return false;
+    }
+    pl.npix = (int64_t)cam.width * cam.height;
+    if (pl.npix > ((int64_t)1 << 31)) {
+        why = "too many pixels";
+        return false;
+    }
+    const int64_t target = 8 << 20;   // primary rays per pass when chosen automatically
+    int spp_pass = p.samples_per_pass > 0 ? std::min(p.samples_per_pass, p.spp)
+                                           : (int)std::max<int64_t>(1, std::min<int64_t>(p.spp, target / pl.npix));
+    pl.spp_pass = spp_pass;
+    pl.passes = (p.spp + spp_pass - 1) / spp_pass;
+    pl.n_primary = pl.npix * spp_pass;
+    const double qf = p.queue_factor > 0.0f ? std::max(1.0f, p.queue_factor) : 2.0;
+    const double qcap = std::ceil(pl.n_primary * qf);
+    const double scap = qcap * std::max(1, s.n_lights);
+    if (qcap > 4.0e9 || scap > 4.0e9) {
+        why = "queue capacity exceeds 2^32; lower samples_per_pass or queue_factor";
+        return false;
+    }
+    pl.qcap = (uint32_t)qcap;
+    pl.scap = (uint32_t)scap;
+    size_t off = 0;
+    pl.off_ctr = off;
+    off = a256(off + 4 * kCtrWords);
+    pl.off_acc = off;
+    off = a256(off + 12 * (size_t)pl.npix);
+    for (int b = 0; b < 2; ++b) {
+        pl.off_q[b] = off;
+        off = a256(off + 11 * 4 * (size_t)pl.qcap + 11 * 256);
+    }
+    pl.off_hit = off;
+    off = a256(off + 2 * 4 * (size_t)pl.qcap + 2 * 256);
+    pl.off_s = off;
+    off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
+    pl.total = off;
+    return true;
+}
+
+static RayQ ray_queue(uint8_t* base, uint32_t cap) {
+    const size_t stride = a256(4 * (size_t)cap);
+    float* f[9];
+    for (int k = 0; k < 9; ++k) f[k] = reinterpret_cast<float*>(base + k * stride);
+    RayQ q{f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], reinterpret_cast<uint32_t*>(base + 9 * stride),
+           reinterpret_cast<uint32_t*>(base + 10 * stride)};
+    return q;
+}
+
+static ShadowQ shadow_queue(uint8_t* base, uint32_t cap) {
+    const size_t stride = a256(4 * (size_t)cap);
+    float* f[10];
+    for (int k = 0; k < 10; ++k) f[k] = reinterpret_cast<float*>(base + k * stride);
+    ShadowQ s{f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], f[9],
+              reinterpret_cast<uint32_t*>(base + 10 * stride)};
+    return s;
+}
+
+static HitQ hit_queue(uint8_t* base, uint32_t cap) {
+    const size_t stride = a256(4 * (size_t)cap);
+    return HitQ{reinterpret_cast<float*>(base), reinterpret_cast<int*>(base + stride)};
+}
+
+static void camera_consts(const rt_camera& cam, const rt_params& p, CamConst& c) {
+    double f[3], r[3], u[3];
+    for (int i = 0; i < 3; ++i) f[i] = (double)cam.look_at[i] - cam.eye[i];
+    double n = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (double& x : f) x /= n;
+    const double up[3] = {cam.up[0], cam.up[1], cam.up[2]};
+    r[0] = up[1] * f[2] - up[2] * f[1];
+    r[1] = up[2] * f[0] - up[0] * f[2];
+    r[2] = up[0] * f[1] - up[1] * f[0];
+    n = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    for (double& x : r) x /= n;
+    u[0] = f[1] * r[2] - f[2] * r[1];
+    u[1] = f[2] * r[0] - f[0] * r[2];
+    u[2] = f[0] * r[1] - f[1] * r[0];
+    for (int i = 0; i < 3; ++i) {
+        c.eye[i] = cam.eye[i];
+        c.f[i] = f[i];
+        c.r[i] = r[i];
+        c.u[i] = u[i];
+    }
+    c.th = std::tan((double)cam.vfov_deg * 0.5 * M_PI / 180.0);
+    c.aspect = (double)cam.width / cam.height;
+    c.W = cam.width;
+    c.H = cam.height;
+    c.spp = p.spp;
+    c.jitter = p.jitter;
+    const int m = (int)std::floor(std::sqrt((double)p.spp) + 0.5);
+    c.m = (p.spp > 1 && m * m == p.spp) ? m : 0;
+    c.frame = p.frame;
+    c.seed = p.seed;
+}
+
+// ---------------------------------------------------------------------------
+// optional per-kernel event timing
+// ---------------------------------------------------------------------------
+struct EventPair {
+    int kind;
+    hipEvent_t a, b;
+};
+static std::mutex g_time_mu;
+static std::vector<EventPair> g_pending;
+static std::vector<hipEvent_t> g_event_pool;
+static double g_time_ms[3] = {0, 0, 0};
+static int64_t g_time_n[3] = {0, 0, 0};
+
+static hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around one launch when timing is on.
+struct KernelTimer {
+    bool on;
+    hipStream_t st;
+    int kind;
+    hipEvent_t a = nullptr;
+    KernelTimer(bool on_, hipStream_t s, int k) : on(on_), st(s), kind(k) {
+        if (!on) return;
+        std::lock_guard<std::mutex> g(g_time_mu);
+        a = take_event();
+        if (a) (void)hipEventRecord(a, st);
+    }
+    ~KernelTimer() {
+        if (!on || !a) return;
+        std::lock_guard<std::mutex> g(g_time_mu);
+        hipEvent_t b = take_event();
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        g_pending.push_back(EventPair{kind, a, b});
+    }
+};
+
+// ---------------------------------------------------------------------------
+// frame launch sequence
+// ---------------------------------------------------------------------------
+struct FrameArgs {
+    DevScene sc;
+    CamConst cam;
+    ShadeConst shc;
+    Plan pl;
+    uint8_t* ws;
+    rt_stats* stats;
+    float* out_rgb;
+    int32_t* out_ids;
+    bool count_work;
+    int spp;
+    int gx, gs, shade_blocks;   // grid sizes, computed outside any capture
+    size_t lds;
+    bool time_kernels;
+};
+
+static rt_status frame_grids(FrameArgs& A) {
+    A.lds = (size_t)A.sc.stack_size * 64 * 4 * 4;
+    rt_status s1 = A.count_work ? persistent_grid(k_extend<true>, A.lds, A.gx)
+                                : persistent_grid(k_extend<false>, A.lds, A.gx);
+    if (s1 != RT_OK) return s1;
+    s1 = A.count_work ? persistent_grid(k_shadow<true>, A.lds, A.gs) : persistent_grid(k_shadow<false>, A.lds, A.gs);
+    if (s1 != RT_OK) return s1;
+    DevInfo di;
+    s1 = device_info(di);
+    if (s1 != RT_OK) return s1;
+    A.shade_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((A.pl.qcap + 255) / 256, (int64_t)di.cus * 16));
+    return RT_OK;
+}
+
+static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
+    const Plan& pl = A.pl;
+    uint32_t* ctr = reinterpret_cast<uint32_t*>(A.ws + pl.off_ctr);
+    float* acc = reinterpret_cast<float*>(A.ws + pl.off_acc);
+    RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
+    HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
+    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap);
+    const size_t lds = A.lds;
+    const int gx = A.gx, gs = A.gs, shade_blocks = A.shade_blocks;
+    unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
+    unsigned long long* swork = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->shadow_node_visits) : nullptr;
+
+    const int64_t n3 = 3 * pl.npix;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
+    const int tiles_x = (A.cam.W + 7) / 8, tiles_y = (A.cam.H + 7) / 8;
+    for (int pass = 0; pass < pl.passes; ++pass) {
+        const int s0 = pass * pl.spp_pass;
+        const int ns = std::min(pl.spp_pass, A.spp - s0);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+        const int64_t nthreads = (int64_t)tiles_x * tiles_y * ns * 64;
+        hipLaunchKernelGGL(k_raygen, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, A.cam, s0, ns,
+                           tiles_x, nthreads, q[0], ctr, pl.qcap);
+        for (int k = 0; k <= A.shc.max_depth; ++k) {
+            RayQ& qi = q[k & 1];
+            RayQ& qo = q[(k + 1) & 1];
+            {
+            KernelTimer kt(A.time_kernels, st, 0);
+            if (A.count_work)
+                hipLaunchKernelGGL(k_extend<true>, dim3(gx), dim3(256), lds, st, A.sc, qi, hq, ctr + kCtrRays + k,
+                                   ctr + kCtrRayCur + k, pl.qcap, work);
+            else
+                hipLaunchKernelGGL(k_extend<false>, dim3(gx), dim3(256), lds, st, A.sc, qi, hq, ctr + kCtrRays + k,
+                                   ctr + kCtrRayCur + k, pl.qcap, work);
+            }
+            {
+            KernelTimer kt(A.time_kernels, st, 1);
+            hipLaunchKernelGGL(k_shade, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, qi, hq, ctr, k, qo, sq,
+                               acc, A.out_ids);
+            }
+            {
+            KernelTimer kt(A.time_kernels, st, 2);
+            if (A.count_work)
+                hipLaunchKernelGGL(k_shadow<true>, dim3(gs), dim3(256), lds, st, A.sc, sq, ctr + kCtrShadow + k,
+                                   ctr + kCtrShadowCur + k, pl.scap, acc, swork);
+            else
+                hipLaunchKernelGGL(k_shadow<false>, dim3(gs), dim3(256), lds, st, A.sc, sq, ctr + kCtrShadow + k,
+                                   ctr + kCtrShadowCur + k, pl.scap, acc, swork);
+            }
+        }
+        hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth);
+    }
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
+                       1.0f / (float)A.spp);
+    HIP_TRY(hipGetLastError());
+    return RT_OK;
+}
+
+// Captured frames, keyed by everything the launch sequence depends on.
+struct GraphKey {
+    std::vector<uint8_t> bytes;
+    bool operator<(const GraphKey& o) const { return bytes < o.bytes; }
+};
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+};
+
+static std::mutex g_graph_mu;
+static std::map<GraphKey, GraphEntry> g_graphs;
+
+template <class T>
+static void put(std::vector<uint8_t>& v, const T& x) {
+    const uint8_t* p = reinterpret_cast<const uint8_t*>(&x);
+    v.insert(v.end(), p, p + sizeof(T));
+}
+
+static rt_status launch_frame(const FrameArgs& A, hipStream_t st, bool use_graph, uint64_t uid) {
+    if (!use_graph) return enqueue_frame(A, st);
+    GraphKey key;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    put(key.bytes, dev);
+    put(key.bytes, uid);
+    put(key.bytes, A.sc);
+    put(key.bytes, A.cam);
+    put(key.bytes, A.shc);
+    put(key.bytes, A.pl);
+    put(key.bytes, A.ws);
+    put(key.bytes, A.stats);
+    put(key.bytes, A.out_rgb);
+    put(key.bytes, A.out_ids);
+    put(key.bytes, A.count_work);
+    put(key.bytes, A.spp);
+    put(key.bytes, A.gx);
+    put(key.bytes, A.gs);
+    put(key.bytes, A.shade_blocks);
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        GraphEntry e;
+        HIP_TRY(hipStreamCreateWithFlags(&e.cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(e.cap_stream, hipStreamCaptureModeThreadLocal));
+        rt_status rs = enqueue_frame(A, e.cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(e.cap_stream, &graph);
+        if (rs != RT_OK) return rs;
+        if (ee != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+            return RT_ERR_HIP;
+        }
+        HIP_TRY(hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphDestroy(graph));
+        if (g_graphs.size() > 64) {   // bound the cache
+            for (auto& kv : g_graphs) {
+                (void)hipGraphExecDestroy(kv.second.exec);
+                (void)hipStreamDestroy(kv.second.cap_stream);
+            }
+            g_graphs.clear();
+        }
+        it = g_graphs.emplace(key, e).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.exec, st));
+    return RT_OK;
+}
+
+}  // namespace mirt
+
+using namespace mirt;
+
+extern "C" {
+
+size_t rt_render_workspace_bytes(const rt_scene* scene, const rt_camera* cam, const rt_params* params) {
+    if (!scene || !cam || !params) {
+        set_error("rt_render_workspace_bytes: NULL argument");
+        return 0;
+    }
+    Plan pl;
+    std::string why;
+    if (!make_plan(scene->h, *cam, *params, pl, why)) {
+        set_error("rt_render_workspace_bytes: " + why);
+        return 0;
+    }
+    return pl.total;
+}
+
+rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params* params, float* out_rgb,
+                    int32_t* out_hit_ids) {
+    if (!scene || !cam || !params || !out_rgb) {
+        set_error("rt_render: NULL argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    const SceneHost& h = scene->h;
+    if (!h.dev) {
+        set_error("rt_render: scene not uploaded (call rt_scene_upload)");
+        return RT_ERR_NOT_UPLOADED;
+    }
+    const rt_params& p = *params;
+    if (!std::isfinite(p.eps) || p.eps < 0.0f || !std::isfinite(p.bg[0]) || !std::isfinite(p.bg[1]) ||
+        !std::isfinite(p.bg[2])) {
+        set_error("rt_render: eps and bg must be finite, eps >= 0");
+        return RT_ERR_INVALID_ARG;
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(cam->eye[i]) || !std::isfinite(cam->look_at[i]) || !std::isfinite(cam->up[i])) {
+            set_error("rt_render: non-finite camera");
+            return RT_ERR_INVALID_ARG;
+        }
+    if (!(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f)) {
+        set_error("rt_render: vfov_deg must be in (0, 180)");
+        return RT_ERR_INVALID_ARG;
+    }
+    Plan pl;
+    std::memset(&pl, 0, sizeof pl);
+    std::string why;
+    if (!make_plan(h, *cam, p, pl, why)) {
+        set_error("rt_render: " + why);
+        return RT_ERR_INVALID_ARG;
+    }
+    if (!p.workspace || p.workspace_bytes < pl.total) {
+        set_error("rt_render: workspace missing or smaller than rt_render_workspace_bytes (" +
+                  std::to_string(pl.total) + ")");
+        return RT_ERR_CAPACITY;
+    }
+    if ((reinterpret_cast<uintptr_t>(p.workspace) | reinterpret_cast<uintptr_t>(out_rgb)) & 255) {
+        set_error("rt_render: device pointers must be 256-byte aligned");
+        return RT_ERR_INVALID_ARG;
+    }
+    if ((size_t)h.stack_size * 64 * 4 * 4 > 65536) {
+        set_error("rt_render: BVH too deep for the LDS traversal stack");
+        return RT_ERR_BVH_DEPTH;
+    }
+    FrameArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.sc = h.dev_view();
+    camera_consts(*cam, p, A.cam);
+    for (int i = 0; i < 3; ++i) A.shc.bg[i] = p.bg[i];
+    A.shc.eps = p.eps;
+    A.shc.max_depth = p.max_depth;
+    A.shc.spp = p.spp;
+    A.shc.qcap = pl.qcap;
+    A.shc.scap = pl.scap;
+    A.pl = pl;
+    A.ws = static_cast<uint8_t*>(p.workspace);
+    A.stats = static_cast<rt_stats*>(p.stats);
+    A.out_rgb = out_rgb;
+    A.out_ids = out_hit_ids;
+    A.count_work = (p.flags & RT_FLAG_COUNT_WORK) != 0;
+    A.spp = p.spp;
+    A.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
+    rt_status rs = frame_grids(A);
+    if (rs != RT_OK) return rs;
+    hipStream_t st = static_cast<hipStream_t>(p.stream);
+    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
+    rs = launch_frame(A, st, graph, h.uid);
+    if (rs != RT_OK) return rs;
+    if (p.flags & RT_FLAG_SYNC) {
+        HIP_TRY(hipStreamSynchronize(st));
+        if (A.stats) {
+            uint32_t status = 0;
+            HIP_TRY(hipMemcpy(&status, &A.stats->status, 4, hipMemcpyDeviceToHost));
+            if (status) {
+                set_error("rt_render: ray queue overflow (status " + std::to_string(status) +
+                          "); raise queue_factor");
+                return RT_ERR_CAPACITY;
+            }
+        }
+    }
+    return RT_OK;
+}
+
+static rt_status trace_rays(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id, uint8_t* occ,
+                            void* workspace, void* stream, bool any) {
+    if (!scene || (n > 0 && (!rays || (any ? !occ : (!t || !id)))) || n < 0 || !workspace) {
+        set_error("rt_intersect/rt_occluded: invalid argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    if (!scene->h.dev) {
+        set_error("rt_intersect/rt_occluded: scene not uploaded");
+        return RT_ERR_NOT_UPLOADED;
+    }
+    if (n == 0) return RT_OK;
+    if (n >= ((int64_t)1 << 32) - 64) {
+        set_error("rt_intersect/rt_occluded: n must be < 2^32 - 64");
+        return RT_ERR_INVALID_ARG;
+    }
+    const DevScene sc = scene->h.dev_view();
+    const size_t lds = (size_t)sc.stack_size * 64 * 4 * 4;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint32_t* cursor = static_cast<uint32_t*>(workspace);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, cursor, 1);
+    int g = 0;
+    rt_status rs = any ? persistent_grid(k_trace_rays<true>, lds, g) : persistent_grid(k_trace_rays<false>, lds, g);
+    if (rs != RT_OK) return rs;
+    g = (int)std::min<int64_t>(g, (n + 255) / 256);
+    if (any)
+        hipLaunchKernelGGL(k_trace_rays<true>, dim3(g), dim3(256), lds, st, sc, rays, n, t, id, occ, cursor);
+    else
+        hipLaunchKernelGGL(k_trace_rays<false>, dim3(g), dim3(256), lds, st, sc, rays, n, t, id, occ, cursor);
+    HIP_TRY(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_intersect(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id, void* workspace,
+                       void* stream) {
+    return trace_rays(scene, rays, n, t, id, nullptr, workspace, stream, false);
+}
+
+rt_status rt_occluded(const rt_scene* scene, const float* rays, int64_t n, uint8_t* occluded, void* workspace,
+                      void* stream) {
+    return trace_rays(scene, rays, n, nullptr, nullptr, occluded, workspace, stream, true);
+}
+
+rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset) {
+    std::lock_guard<std::mutex> g(g_time_mu);
+    for (const EventPair& e : g_pending) {
+        float t = 0.0f;
+        HIP_TRY(hipEventSynchronize(e.b));
+        HIP_TRY(hipEventElapsedTime(&t, e.a, e.b));
+        g_time_ms[e.kind] += t;
+        g_time_n[e.kind] += 1;
+        g_event_pool.push_back(e.a);
+        g_event_pool.push_back(e.b);
+    }
+    g_pending.clear();
+    for (int k = 0; k < 3; ++k) {
+        if (ms) ms[k] = g_time_ms[k];
+        if (launches) launches[k] = g_time_n[k];
+        if (reset) {
+            g_time_ms[k] = 0.0;
+            g_time_n[k] = 0;
+        }
+    }
+    return RT_OK;
+}
+
+size_t rt_render_batch_workspace_bytes(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params,
+                                       int32_t n) {
+    (void)scenes;
+    (void)cams;
+    (void)params;
+    (void)n;
+    set_error("rt_render_batch_workspace_bytes: batched rendering is not built yet");
+    return 0;
+}
+
+rt_status rt_render_batch(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params, int32_t n,
+                          float* const* out_rgb, int32_t* const* out_hit_ids) {
+    (void)scenes;
+    (void)cams;
+    (void)params;
+    (void)n;
+    (void)out_rgb;
+    (void)out_hit_ids;
+    set_error("rt_render_batch: batched rendering is not built yet");
+    return RT_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,335 @@
+// rt_common.h -- data layouts and the FP32 intersection / traversal code shared
+// by the gfx950 kernels and the library's host-side FP32 traversal.
+//
+// Method (arXiv 1504.03151): closest hit of a ray over all objects and the
+// any-hit shadow query of Algorithm 1 (Section III); the sphere is the
+// quadratic of Eq. 9-12 (Section IV.B).  The acceleration structure (a binary
+// BVH), triangles and planes extend the paper's sphere-only scenes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef HD
+#define HD __host__ __device__ __forceinline__
+#endif
+
+namespace mirt {
+
+// ---------------------------------------------------------------------------
+// layouts
+// ---------------------------------------------------------------------------
+// BVH node: 64 bytes holding the boxes of BOTH children, so one node fetch
+// (four 16-byte loads) tests two boxes.
+//   a = (L.lo.x, L.hi.x, L.lo.y, L.hi.y)
+//   b = (R.lo.x, R.hi.x, R.lo.y, R.hi.y)
+//   c = (L.lo.z, L.hi.z, R.lo.z, R.hi.z)
+//   d = (left, right, 0, 0)
+// A child reference >= 0 is an inner node index; < 0 is a leaf ~((first << 4) | count),
+// count in [1, 15] primitives in leaf order.  A reference with count 0 is empty.
+struct alignas(16) Node {
+    float4 a, b, c;
+    int4 d;
+};
+static_assert(sizeof(Node) == 64, "node must be 64 bytes");
+
+constexpr int kLeafBits = 4;
+constexpr int kLeafMaxCount = 15;
+constexpr int32_t kStackDone = INT32_MIN;
+constexpr int kMaxStack = 96;
+
+HD int32_t leaf_ref(int32_t first, int32_t count) { return ~((first << kLeafBits) | count); }
+HD int32_t leaf_first(int32_t ref) { return (~ref) >> kLeafBits; }
+HD int32_t leaf_count(int32_t ref) { return (~ref) & ((1 << kLeafBits) - 1); }
+
+// Primitive record in leaf order, 48 bytes (three float4):
+//   triangle: (v0, id) (v1, mat) (v2, 0)
+//   sphere:   (c, id)  (r, r^2, 0, mat) (0)
+// id = original id as int bits (spheres 0..ns-1, then triangles); a record is
+// a sphere iff id < n_spheres.
+struct alignas(16) DevMaterial {
+    float4 a;  // albedo.rgb, k_a
+    float4 b;  // k_d, k_s, shininess, k_r
+    float4 c;  // ior, type, 0, 0
+};
+
+struct alignas(16) DevLight {
+    float4 pos;
+    float4 intensity;
+};
+
+// Device view of one scene (pointers into the uploaded blob).
+struct DevScene {
+    const Node* nodes;
+    const float4* prims;      // [n_bvh * 3]
+    const float4* normals;    // [n_bvh]  unit geometric normal of triangles (FP64 on host, rounded)
+    const float4* planes;     // [n_planes] (n, h): n.x = h
+    const int* plane_mat;     // [n_planes]
+    const DevMaterial* mats;
+    const DevLight* lights;
+    int n_spheres, n_tris, n_planes, n_lights;
+    int n_bvh;                // n_spheres + n_tris
+    int stack_size;           // traversal stack entries needed (tree depth + 2)
+};
+
+// Hit codes: -1 miss; [0, n_bvh) BVH primitive in leaf order; n_bvh + k plane k.
+
+// ---------------------------------------------------------------------------
+// small vector helpers
+// ---------------------------------------------------------------------------
+struct V3 {
+    float x, y, z;
+};
+HD V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+HD V3 operator+(V3 a, V3 b) { return v3(a.x + b.x, a.y + b.y, a.z + b.z); }
+HD V3 operator-(V3 a, V3 b) { return v3(a.x - b.x, a.y - b.y, a.z - b.z); }
+HD V3 operator*(V3 a, float s) { return v3(a.x * s, a.y * s, a.z * s); }
+HD V3 operator*(float s, V3 a) { return v3(a.x * s, a.y * s, a.z * s); }
+HD V3 operator-(V3 a) { return v3(-a.x, -a.y, -a.z); }
+HD float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+HD V3 mul(V3 a, V3 b) { return v3(a.x * b.x, a.y * b.y, a.z * b.z); }
+HD float maxabs(V3 a) { return fmaxf(fabsf(a.x), fmaxf(fabsf(a.y), fabsf(a.z))); }
+HD float sel(V3 a, int k) { return k == 0 ? a.x : (k == 1 ? a.y : a.z); }
+HD V3 xyz(float4 f) { return v3(f.x, f.y, f.z); }
+
+HD float min3f(float a, float b, float c) { return fminf(a, fminf(b, c)); }
+HD float max3f(float a, float b, float c) { return fmaxf(a, fmaxf(b, c)); }
+
+HD float as_float_i(int i) {
+    union { int i; float f; } u;
+    u.i = i;
+    return u.f;
+}
+HD int as_int_f(float f) {
+    union { float f; int i; } u;
+    u.f = f;
+    return u.i;
+}
+
+// ---------------------------------------------------------------------------
+// ray prepared for traversal
+// ---------------------------------------------------------------------------
+struct TRay {
+    V3 o, d;
+    V3 inv;     // 1/d with zero components replaced by a tiny signed value
+    V3 oinv;    // o * inv
+    int kx, ky, kz;
+    float sx, sy, sz;  // shear of the watertight triangle test
+};
+
+HD TRay make_tray(V3 o, V3 d) {
+    TRay r;
+    r.o = o;
+    r.d = d;
+    const float tiny = 1e-20f;
+    float ix = fabsf(d.x) > tiny ? d.x : copysignf(tiny, d.x);
+    float iy = fabsf(d.y) > tiny ? d.y : copysignf(tiny, d.y);
+    float iz = fabsf(d.z) > tiny ? d.z : copysignf(tiny, d.z);
+    r.inv = v3(1.0f / ix, 1.0f / iy, 1.0f / iz);
+    r.oinv = mul(o, r.inv);
+    // watertight test (Woop, Benthin, Wald, JCGT 2013): dominant axis kz,
+    // winding-preserving permutation, shear that maps the ray to +z.
+    const float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    int kz = (ax > ay) ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    const float dz = sel(d, kz);
+    if (dz < 0.0f) {
+        int t = kx;
+        kx = ky;
+        ky = t;
+    }
+    r.kx = kx;
+    r.ky = ky;
+    r.kz = kz;
+    r.sx = sel(d, kx) / dz;
+    r.sy = sel(d, ky) / dz;
+    r.sz = 1.0f / dz;
+    return r;
+}
+
+// Slab test of both children of a node.  Boxes are padded outward by the
+// builder, so the FP32 test never rejects a box the ray truly crosses.
+HD void box2(const TRay& r, float4 a, float4 b, float4 c, float tbest, bool& hitL, bool& hitR, float& tl,
+             float& tr) {
+    const float lx0 = fmaf(a.x, r.inv.x, -r.oinv.x), lx1 = fmaf(a.y, r.inv.x, -r.oinv.x);
+    const float ly0 = fmaf(a.z, r.inv.y, -r.oinv.y), ly1 = fmaf(a.w, r.inv.y, -r.oinv.y);
+    const float lz0 = fmaf(c.x, r.inv.z, -r.oinv.z), lz1 = fmaf(c.y, r.inv.z, -r.oinv.z);
+    const float rx0 = fmaf(b.x, r.inv.x, -r.oinv.x), rx1 = fmaf(b.y, r.inv.x, -r.oinv.x);
+    const float ry0 = fmaf(b.z, r.inv.y, -r.oinv.y), ry1 = fmaf(b.w, r.inv.y, -r.oinv.y);
+    const float rz0 = fmaf(c.z, r.inv.z, -r.oinv.z), rz1 = fmaf(c.w, r.inv.z, -r.oinv.z);
+    const float lmin = max3f(fminf(lx0, lx1), fminf(ly0, ly1), fmaxf(fminf(lz0, lz1), 0.0f));
+    const float lmax = min3f(fmaxf(lx0, lx1), fmaxf(ly0, ly1), fminf(fmaxf(lz0, lz1), tbest));
+    const float rmin = max3f(fminf(rx0, rx1), fminf(ry0, ry1), fmaxf(fminf(rz0, rz1), 0.0f));
+    const float rmax = min3f(fmaxf(rx0, rx1), fmaxf(ry0, ry1), fminf(fmaxf(rz0, rz1), tbest));
+    hitL = lmin <= lmax;
+    hitR = rmin <= rmax;
+    tl = lmin;
+    tr = rmin;
+}
+
+// Watertight ray/triangle test (Woop, Benthin, Wald 2013).  Edge functions are
+// evaluated without contraction so a shared edge gives exactly opposite values
+// in its two triangles; an exact zero is re-evaluated in double, as that paper
+// prescribes.  Two-sided; returns t in (0, +inf) or -1.
+HD float tri_t(const TRay& r, float4 p0, float4 p1, float4 p2) {
+#pragma clang fp contract(off)
+    const V3 A = xyz(p0) - r.o, B = xyz(p1) - r.o, C = xyz(p2) - r.o;
+    const float Az = sel(A, r.kz), Bz = sel(B, r.kz), Cz = sel(C, r.kz);
+    const float Ax = sel(A, r.kx) - r.sx * Az, Ay = sel(A, r.ky) - r.sy * Az;
+    const float Bx = sel(B, r.kx) - r.sx * Bz, By = sel(B, r.ky) - r.sy * Bz;
+    const float Cx = sel(C, r.kx) - r.sx * Cz, Cy = sel(C, r.ky) - r.sy * Cz;
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return -1.0f;
+    const float det = U + V + W;
+    if (det == 0.0f) return -1.0f;
+    const float T = U * (r.sz * Az) + V * (r.sz * Bz) + W * (r.sz * Cz);
+    if ((det > 0.0f && T <= 0.0f) || (det < 0.0f && T >= 0.0f)) return -1.0f;
+    return T / det;
+}
+
+// Ray/sphere (Eq. 11-12), evaluated in the cancellation-free form of Haines,
+// Guenther and Akenine-Moller ("Precision Improvements for Ray/Sphere
+// Intersection", Ray Tracing Gems, 2019): the discriminant r^2 - |f - (f.d)d|^2
+// and the root pair q, c'/q.  d must be unit length.  Returns the smallest
+// root in (0, +inf) or -1.
+HD float sphere_t(const TRay& r, float4 p0, float4 p1) {
+    const V3 f = r.o - xyz(p0);
+    const float bq = -dot(f, r.d);                 // t of closest approach
+    const V3 l = f + bq * r.d;                     // centre -> closest point
+    const float disc = p1.y - dot(l, l);           // r^2 - |l|^2
+    if (disc < 0.0f) return -1.0f;
+    const float cc = dot(f, f) - p1.y;             // c' = |o-c|^2 - r^2
+    const float q = bq + copysignf(sqrtf(disc), bq);
+    if (q == 0.0f) return -1.0f;
+    float t0 = cc / q, t1 = q;
+    if (t0 > t1) {
+        const float t = t0;
+        t0 = t1;
+        t1 = t;
+    }
+    if (t0 > 0.0f) return t0;
+    if (t1 > 0.0f) return t1;
+    return -1.0f;
+}
+
+HD float plane_t(const TRay& r, float4 pl) {
+    const V3 n = xyz(pl);
+    const float nd = dot(n, r.d);
+    if (nd == 0.0f) return -1.0f;
+    const float t = (pl.w - dot(n, r.o)) / nd;
+    return t > 0.0f ? t : -1.0f;
+}
+
+// ---------------------------------------------------------------------------
+// traversal
+// ---------------------------------------------------------------------------
+struct Hit {
+    float t;
+    int prim;   // hit code (see above)
+    int id;     // original id, for the tie-break and the id output
+};
+
+struct Work {
+    uint32_t nodes, tris, spheres;
+};
+
+// Closest hit (ANY = false) or any hit (ANY = true) in (0, tmax).  Ties in t
+// go to the smaller original id.  Stack is a small push/pop policy object
+// (LDS-resident on the GPU, an array on the host).
+template <bool ANY, bool COUNT, class Stack>
+HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& work) {
+    Hit h;
+    h.t = tmax;
+    h.prim = -1;
+    h.id = -1;
+    for (int k = 0; k < s.n_planes; ++k) {
+        const float t = plane_t(r, s.planes[k]);
+        const int id = s.n_bvh + k;
+        if (t > 0.0f && (t < h.t || (t == h.t && h.prim >= 0 && id < h.id))) {
+            h.t = t;
+            h.prim = s.n_bvh + k;
+            h.id = id;
+            if (ANY) return h;
+        }
+    }
+    stk.reset();
+    int32_t node = 0;
+    for (;;) {
+        while (node >= 0) {
+            const Node* n = s.nodes + node;
+            const float4 a = n->a, b = n->b, c = n->c;
+            const int4 d = n->d;
+            if (COUNT) work.nodes++;
+            bool hl, hr;
+            float tl, tr;
+            box2(r, a, b, c, h.t, hl, hr, tl, tr);
+            int32_t cl = d.x, cr = d.y;
+            if (hl && hr) {
+                if (tr < tl) {
+                    const int32_t t = cl;
+                    cl = cr;
+                    cr = t;
+                }
+                stk.push(cr);
+                node = cl;
+            } else if (hl) {
+                node = cl;
+            } else if (hr) {
+                node = cr;
+            } else {
+                node = stk.pop();
+            }
+        }
+        if (node == kStackDone) break;
+        const int32_t first = leaf_first(node), cnt = leaf_count(node);
+        for (int i = first; i < first + cnt; ++i) {
+            const float4 p0 = s.prims[3 * i];
+            const int id = as_int_f(p0.w);
+            float t;
+            if (id < s.n_spheres) {
+                if (COUNT) work.spheres++;
+                t = sphere_t(r, p0, s.prims[3 * i + 1]);
+            } else {
+                if (COUNT) work.tris++;
+                t = tri_t(r, p0, s.prims[3 * i + 1], s.prims[3 * i + 2]);
+            }
+            if (t > 0.0f && (t < h.t || (t == h.t && h.prim >= 0 && id < h.id))) {
+                h.t = t;
+                h.prim = i;
+                h.id = id;
+                if (ANY) return h;
+            }
+        }
+        node = stk.pop();
+    }
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// counter-based jitter: the 32-bit PCG hash of Jarzynski and Olano, "Hash
+// Functions for GPU Rendering", JCGT 9(3), 2020.
+// ---------------------------------------------------------------------------
+HD uint32_t pcg_hash(uint32_t v) {
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+HD double jitter01(uint64_t seed, uint32_t frame, uint32_t pixel, uint32_t s, uint32_t dim) {
+    uint32_t h = pcg_hash((uint32_t)seed);
+    h = pcg_hash(h ^ (uint32_t)(seed >> 32));
+    h = pcg_hash(h ^ frame);
+    h = pcg_hash(h ^ pixel);
+    h = pcg_hash(h ^ (s * 2u + dim));
+    return (double)(h >> 8) * (1.0 / 16777216.0);
+}
+
+}  // namespace mirt

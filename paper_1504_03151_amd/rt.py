@@ -1,0 +1,342 @@
+"""Thin Python binding of libmirt.so (include/mirt.h).
+
+Argument marshalling only: every step of the tracer runs in the HIP library.
+torch provides device memory and the HIP stream.  If the library is missing
+this module raises at import-time use (``lib()``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmirt.so")
+_lock = threading.Lock()
+_lib = None
+
+RT_OK = 0
+RT_ERR = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP", -4: "BVH_DEPTH", -5: "CAPACITY",
+          -6: "DEVICE_STATUS", -7: "NOT_UPLOADED"}
+FLAG_SYNC, FLAG_COUNT_WORK, FLAG_NO_GRAPH, FLAG_TIME_KERNELS = 1, 2, 4, 8
+STATS_MAX_DEPTH = 16
+
+
+class RTError(RuntimeError):
+    def __init__(self, status: int, fn: str, msg: str):
+        super().__init__(f"{fn} failed: RT_ERR_{RT_ERR.get(status, status)} ({status}): {msg}")
+        self.status = status
+
+
+class Material(C.Structure):
+    _fields_ = [("albedo", C.c_float * 3), ("k_a", C.c_float), ("k_d", C.c_float), ("k_s", C.c_float),
+                ("shininess", C.c_float), ("k_r", C.c_float), ("ior", C.c_float), ("type", C.c_int32)]
+
+
+class Light(C.Structure):
+    _fields_ = [("pos", C.c_float * 3), ("intensity", C.c_float * 3)]
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("spheres", C.c_void_p), ("n_spheres", C.c_int64), ("sphere_mat", C.c_void_p),
+                ("tris", C.c_void_p), ("n_tris", C.c_int64), ("tri_mat", C.c_void_p),
+                ("planes", C.c_void_p), ("n_planes", C.c_int64), ("plane_mat", C.c_void_p),
+                ("materials", C.c_void_p), ("n_materials", C.c_int32),
+                ("lights", C.c_void_p), ("n_lights", C.c_int32)]
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("leaf_max", C.c_int32), ("sah_bins", C.c_int32), ("max_depth", C.c_int32),
+                ("node_layout", C.c_int32)]
+
+
+class CameraC(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("look_at", C.c_float * 3), ("up", C.c_float * 3),
+                ("vfov_deg", C.c_float), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class ParamsC(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("jitter", C.c_int32), ("frame", C.c_uint32),
+                ("seed", C.c_uint64), ("bg", C.c_float * 3), ("eps", C.c_float),
+                ("samples_per_pass", C.c_int32), ("flags", C.c_int32), ("queue_factor", C.c_float),
+                ("reserved", C.c_int32), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stats", C.c_void_p), ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("status", C.c_uint32), ("passes", C.c_uint32),
+                ("rays", C.c_uint64 * STATS_MAX_DEPTH), ("shadow", C.c_uint64 * STATS_MAX_DEPTH),
+                ("node_visits", C.c_uint64), ("tri_tests", C.c_uint64), ("sphere_tests", C.c_uint64),
+                ("shadow_node_visits", C.c_uint64), ("shadow_tri_tests", C.c_uint64),
+                ("shadow_sphere_tests", C.c_uint64)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("depth", C.c_int32), ("stack_size", C.c_int32),
+                ("n_leaves", C.c_int64), ("n_bvh_prims", C.c_int64), ("sah_cost", C.c_double),
+                ("build_seconds", C.c_double), ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3)]
+
+
+# every symbol include/mirt.h declares: name -> (restype, argtypes)
+_P = C.c_void_p
+SIGNATURES = {
+    "rt_build_scene": (C.c_int32, [C.POINTER(SceneDesc), C.POINTER(BuildOpts), C.POINTER(C.c_void_p)]),
+    "rt_destroy_scene": (None, [_P]),
+    "rt_scene_get_info": (C.c_int32, [_P, C.POINTER(SceneInfo)]),
+    "rt_scene_device_bytes": (C.c_size_t, [_P]),
+    "rt_scene_upload": (C.c_int32, [_P, _P, C.c_size_t, _P]),
+    "rt_render_workspace_bytes": (C.c_size_t, [_P, C.POINTER(CameraC), C.POINTER(ParamsC)]),
+    "rt_render": (C.c_int32, [_P, C.POINTER(CameraC), C.POINTER(ParamsC), _P, _P]),
+    "rt_render_batch_workspace_bytes": (C.c_size_t, [_P, _P, _P, C.c_int32]),
+    "rt_render_batch": (C.c_int32, [_P, _P, _P, C.c_int32, _P, _P]),
+    "rt_intersect": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P]),
+    "rt_occluded": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P]),
+    "rt_host_trace": (C.c_int32, [_P, _P, C.c_int64, C.c_int32, _P, _P, _P, C.c_int32]),
+    "rt_kernel_times": (C.c_int32, [_P, _P, C.c_int32]),
+    "rt_last_error": (C.c_char_p, []),
+    "rt_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libmirt.so; raises if it has not been built (no fallback)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError(f"{LIB_PATH} is missing: build it with "
+                                  f"`python -m paper_1504_03151_amd.csrc.build` (needs ROCm hipcc)")
+            L = C.CDLL(LIB_PATH)
+            for name, (res, args) in SIGNATURES.items():
+                fn = getattr(L, name)
+                fn.restype = res
+                fn.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(status: int, fn: str):
+    if status != RT_OK:
+        raise RTError(status, fn, lib().rt_last_error().decode(errors="replace"))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream_ptr(stream=None) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream) or None
+
+
+class Scene:
+    """A built scene (host BVH + packed blob); upload() copies it to the GPU."""
+
+    def __init__(self, scene, leaf_max: int = 0, sah_bins: int = 0, max_depth: int = 0, node_layout: int = 0):
+        L = lib()
+        self.src = scene
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data if a.size else None
+
+        mats = (Material * max(1, len(scene.materials)))()
+        for i, m in enumerate(np.asarray(scene.materials, np.float32)):
+            mats[i].albedo[:] = [float(x) for x in m[0:3]]
+            mats[i].k_a, mats[i].k_d, mats[i].k_s, mats[i].shininess, mats[i].k_r, mats[i].ior = [
+                float(x) for x in m[3:9]]
+            mats[i].type = int(m[9])
+        lights = (Light * max(1, len(scene.lights)))()
+        for i, l in enumerate(np.asarray(scene.lights, np.float32)):
+            lights[i].pos[:] = [float(x) for x in l[0:3]]
+            lights[i].intensity[:] = [float(x) for x in l[3:6]]
+        d = SceneDesc()
+        d.spheres, d.n_spheres, d.sphere_mat = arr(scene.spheres, np.float32), len(scene.spheres), arr(
+            scene.sphere_mat, np.int32)
+        d.tris, d.n_tris, d.tri_mat = arr(scene.tris, np.float32), len(scene.tris), arr(scene.tri_mat, np.int32)
+        d.planes, d.n_planes, d.plane_mat = arr(scene.planes, np.float32), len(scene.planes), arr(
+            scene.plane_mat, np.int32)
+        d.materials, d.n_materials = C.cast(mats, C.c_void_p), len(scene.materials)
+        d.lights, d.n_lights = C.cast(lights, C.c_void_p), len(scene.lights)
+        opts = BuildOpts(leaf_max, sah_bins, max_depth, node_layout)
+        h = C.c_void_p()
+        _check(L.rt_build_scene(C.byref(d), C.byref(opts), C.byref(h)), "rt_build_scene")
+        self.handle = h
+        self.blob = None
+        info = SceneInfo()
+        _check(L.rt_scene_get_info(self.handle, C.byref(info)), "rt_scene_get_info")
+        self.info = {k: (list(getattr(info, k)) if k.startswith("bounds") else getattr(info, k))
+                     for k, _ in SceneInfo._fields_}
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().rt_destroy_scene(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+
+    @property
+    def device_bytes(self) -> int:
+        return int(lib().rt_scene_device_bytes(self.handle))
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        n = self.device_bytes
+        self.blob = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        base = (self.blob.data_ptr() + 255) // 256 * 256
+        _check(lib().rt_scene_upload(self.handle, base, n, _stream_ptr(stream)), "rt_scene_upload")
+        return self
+
+    def host_trace(self, rays: np.ndarray, any_hit: bool = False, nthreads: int = 0, with_work: bool = False):
+        """Host FP32 traversal of the packed BVH. rays [n,8] f32 -> (t, id[, work [n,3]])."""
+        rays = np.ascontiguousarray(rays, np.float32).reshape(-1, 8)
+        n = len(rays)
+        t = np.zeros(n, np.float32)
+        ids = np.zeros(n, np.int32)
+        work = np.zeros((n, 3), np.uint32) if with_work else None
+        _check(lib().rt_host_trace(self.handle, rays.ctypes.data, n, int(any_hit), t.ctypes.data, ids.ctypes.data,
+                                   None if work is None else work.ctypes.data, nthreads), "rt_host_trace")
+        return (t, ids, work) if with_work else (t, ids)
+
+
+def camera_c(cam) -> CameraC:
+    c = CameraC()
+    c.eye[:] = [float(x) for x in cam.eye]
+    c.look_at[:] = [float(x) for x in cam.look_at]
+    c.up[:] = [float(x) for x in cam.up]
+    c.vfov_deg = float(cam.vfov_deg)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0) -> ParamsC:
+    q = ParamsC()
+    q.spp, q.max_depth, q.jitter, q.frame = int(p.spp), int(p.max_depth), int(p.jitter), int(p.frame)
+    q.seed = int(p.seed) & (2 ** 64 - 1)
+    q.bg[:] = [float(x) for x in p.bg]
+    q.eps = float(p.eps)
+    q.samples_per_pass = int(samples_per_pass)
+    q.flags = int(flags)
+    q.queue_factor = float(queue_factor)
+    return q
+
+
+def stats_dict(buf) -> dict:
+    """Decode an rt_stats device buffer (torch uint8 tensor)."""
+    raw = buf.detach().cpu().numpy().tobytes()
+    s = Stats.from_buffer_copy(raw[:C.sizeof(Stats)])
+    return {"status": s.status, "passes": s.passes, "rays": list(s.rays), "shadow": list(s.shadow),
+            "node_visits": s.node_visits, "tri_tests": s.tri_tests, "sphere_tests": s.sphere_tests,
+            "shadow_node_visits": s.shadow_node_visits, "shadow_tri_tests": s.shadow_tri_tests,
+            "shadow_sphere_tests": s.shadow_sphere_tests}
+
+
+class Renderer:
+    """Owns the device workspace, outputs and stats for repeated frames of one scene/camera."""
+
+    def __init__(self, scene: Scene, camera, params, device="cuda", with_ids=True, samples_per_pass=0,
+                 queue_factor=0.0, graph=True):
+        import torch
+        if scene.blob is None:
+            scene.upload(device)
+        self.scene, self.camera, self.params = scene, camera, params
+        self.device = device
+        self.samples_per_pass, self.queue_factor, self.graph = samples_per_pass, queue_factor, graph
+        self.cam_c = camera_c(camera)
+        self._alloc(with_ids)
+
+    def _alloc(self, with_ids):
+        import torch
+        p = params_c(self.params, 0, self.samples_per_pass, self.queue_factor)
+        n = lib().rt_render_workspace_bytes(self.scene.handle, C.byref(self.cam_c), C.byref(p))
+        if n == 0:
+            raise RTError(-1, "rt_render_workspace_bytes", lib().rt_last_error().decode())
+        self.ws_bytes = int(n)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        H, W = self.camera.height, self.camera.width
+        self.rgb = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        self.ids = torch.empty((H, W, self.params.spp), dtype=torch.int32, device=self.device) if with_ids else None
+        self.stats = torch.zeros(C.sizeof(Stats) + 64, dtype=torch.uint8, device=self.device)
+
+    def render(self, flags=0, stream=None, reset_stats=True):
+        if reset_stats:
+            self.stats.zero_()
+        if not self.graph:
+            flags |= FLAG_NO_GRAPH
+        p = params_c(self.params, flags, self.samples_per_pass, self.queue_factor)
+        p.workspace, p.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
+        p.stats = self.stats.data_ptr()
+        p.stream = _stream_ptr(stream)
+        _check(lib().rt_render(self.scene.handle,
+                               C.byref(self.cam_c), C.byref(p), self.rgb.data_ptr(), _ptr(self.ids)), "rt_render")
+        return self.rgb, self.ids
+
+    def read_stats(self) -> dict:
+        return stats_dict(self.stats)
+
+
+def render(scene: Scene, camera, params, flags=FLAG_SYNC, **kw):
+    """One frame: returns (rgb [H,W,3] f32, ids [H,W,spp] i32, stats dict) as torch device tensors."""
+    r = Renderer(scene, camera, params, **kw)
+    rgb, ids = r.render(flags)
+    st = r.read_stats()
+    if st["status"]:
+        raise RTError(-5, "rt_render", f"queue overflow (status {st['status']}); raise queue_factor")
+    return rgb, ids, st
+
+
+def _trace(scene: Scene, rays, any_hit: bool, stream=None):
+    import torch
+    if scene.blob is None:
+        scene.upload()
+    rays = rays.to(device=scene.blob.device, dtype=torch.float32).contiguous().reshape(-1, 8)
+    n = rays.shape[0]
+    ws = torch.zeros(256, dtype=torch.uint8, device=rays.device)
+    L = lib()
+    if any_hit:
+        occ = torch.empty(n, dtype=torch.uint8, device=rays.device)
+        _check(L.rt_occluded(scene.handle, rays.data_ptr(), n, occ.data_ptr(), ws.data_ptr(), _stream_ptr(stream)),
+               "rt_occluded")
+        return occ
+    t = torch.empty(n, dtype=torch.float32, device=rays.device)
+    ids = torch.empty(n, dtype=torch.int32, device=rays.device)
+    _check(L.rt_intersect(scene.handle, rays.data_ptr(), n, t.data_ptr(), ids.data_ptr(), ws.data_ptr(),
+                          _stream_ptr(stream)), "rt_intersect")
+    return t, ids
+
+
+def intersect(scene: Scene, rays, stream=None):
+    """Closest hit of device rays [n,8] (o, d, tmin, tmax) -> (t [n], id [n]) device tensors."""
+    return _trace(scene, rays, False, stream)
+
+
+def occluded(scene: Scene, rays, stream=None):
+    """Any hit in (0, tmax) of device rays [n,8] -> uint8 [n] device tensor."""
+    return _trace(scene, rays, True, stream)
+
+
+def kernel_times(reset: bool = True) -> dict:
+    """Totals recorded by frames rendered with FLAG_TIME_KERNELS: {kernel: (ms, launches)}."""
+    ms = (C.c_double * 3)()
+    n = (C.c_int64 * 3)()
+    _check(lib().rt_kernel_times(ms, n, int(reset)), "rt_kernel_times")
+    return {k: (ms[i], n[i]) for i, k in enumerate(("extend", "shade", "shadow"))}
+
+
+def make_rays(o, d, tmax=None) -> np.ndarray:
+    """Pack origins/directions into the [n,8] FP32 ray layout (tmin column unused)."""
+    o = np.asarray(o, np.float64).reshape(-1, 3)
+    d = np.asarray(d, np.float64).reshape(-1, 3)
+    R = np.zeros((len(o), 8), np.float32)
+    R[:, 0:3] = o
+    R[:, 3:6] = d
+    if tmax is not None:
+        R[:, 7] = np.broadcast_to(np.asarray(tmax, np.float64), (len(o),))
+    return R

@@ -1,0 +1,135 @@
+"""The C ABI on the CPU: exports, validation and error paths, BVH invariants.
+
+No compute call here touches a GPU: scene building, validation and the host
+FP32 traversal of the packed BVH are host code.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1504_03151_amd import rt, scenes as S
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "mirt.h")
+
+
+def test_library_exports_every_declared_symbol():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = set(re.findall(r"\b(rt_[a-z_]+)\s*\(", src))
+    assert len(names) >= 15
+    L = rt.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), f"libmirt.so does not export {n}"
+    assert names <= set(rt.SIGNATURES), names - set(rt.SIGNATURES)
+    assert rt.lib().rt_version().decode().startswith("mirt")
+
+
+def _bad(scene, match):
+    with pytest.raises(rt.RTError, match=match):
+        rt.Scene(scene)
+
+
+def test_build_scene_rejects_invalid_input():
+    good = S.config0().scene
+    sp = good.spheres.copy()
+    sp[2, 3] = 0.0
+    _bad(S.make_scene(spheres=sp, sphere_mat=good.sphere_mat, materials=good.materials, lights=good.lights),
+         "INVALID_ARG")
+    sp = good.spheres.copy()
+    sp[1, 0] = np.nan
+    _bad(S.make_scene(spheres=sp, sphere_mat=good.sphere_mat, materials=good.materials, lights=good.lights),
+         "INVALID_ARG")
+    _bad(S.make_scene(spheres=good.spheres, sphere_mat=np.full(8, 99), materials=good.materials,
+                      lights=good.lights), "INVALID_ARG")
+    tris = np.zeros((1, 3, 3), np.float32)
+    tris[0, 1, 2] = np.inf
+    _bad(S.make_scene(tris=tris, tri_mat=[0], materials=good.materials, lights=good.lights), "INVALID_ARG")
+    _bad(S.make_scene(planes=[[0, 2, 0, 1]], plane_mat=[0], materials=good.materials, lights=good.lights),
+         "INVALID_ARG")
+    m = good.materials.copy()
+    m[0, 9] = 7
+    _bad(S.make_scene(spheres=good.spheres, sphere_mat=good.sphere_mat, materials=m, lights=good.lights),
+         "INVALID_ARG")
+    li = good.lights.copy()
+    li[0, 4] = np.nan
+    _bad(S.make_scene(spheres=good.spheres, sphere_mat=good.sphere_mat, materials=good.materials, lights=li),
+         "INVALID_ARG")
+
+
+def test_bvh_depth_limit_is_an_error():
+    w = S.config0()
+    tris = S.icosphere(2).astype(np.float32)
+    sc = S.make_scene(tris=tris, tri_mat=np.zeros(len(tris)), materials=w.scene.materials, lights=w.scene.lights)
+    with pytest.raises(rt.RTError, match="BVH_DEPTH"):
+        rt.Scene(sc, max_depth=2)
+    assert rt.Scene(sc).info["depth"] <= 60
+
+
+def test_identical_triangles_build_and_tie_to_the_smallest_id():
+    tri = np.array([[[-1, -1, 5], [1, -1, 5], [0, 1, 5]]], np.float32)
+    tris = np.repeat(tri, 100, axis=0)
+    w = S.config0()
+    sc = S.make_scene(tris=tris, tri_mat=np.zeros(100), materials=w.scene.materials, lights=w.scene.lights)
+    s = rt.Scene(sc)
+    t, ids = s.host_trace(rt.make_rays([[0, 0, 0]], [[0, 0, 1]]))
+    assert ids[0] == 0 and t[0] == 5.0
+
+
+def test_workspace_and_render_argument_errors():
+    w = S.config0()
+    s = rt.Scene(w.scene)
+    cam = rt.camera_c(w.camera)
+    p = rt.params_c(w.params)
+    import ctypes as C
+    assert rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)) > 0
+    cam.width = 0
+    assert rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)) == 0
+    assert b"width" in rt.lib().rt_last_error()
+    cam = rt.camera_c(w.camera)
+    # not uploaded: refused before any device work
+    st = rt.lib().rt_render(s.handle, C.byref(cam), C.byref(p), 256, None)
+    assert st == -7
+    p.spp = 0
+    assert rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)) == 0
+
+
+def test_host_traversal_matches_brute_force_on_tiny_scenes():
+    for seed in range(6):
+        w = S.random_tiny(seed, n_spheres=6, n_tris=80)
+        s = rt.Scene(w.scene)
+        rng = np.random.default_rng(100 + seed)
+        o = rng.uniform(-6, 6, (3000, 3))
+        d = rng.normal(size=(3000, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        R = rt.make_rays(o, d)
+        t, ids, work = s.host_trace(R, with_work=True)
+        o32, d32 = R[:, :3].astype(np.float64), R[:, 3:6].astype(np.float64)
+        tr, ir, m = oracle.closest(w.scene, o32, d32)
+        rob = m > oracle.ROBUST
+        assert rob.mean() > 0.98
+        assert (ids[rob] == ir[rob]).all()
+        assert (work[:, 0] >= 1).all()                       # the root is always fetched
+        tm = rng.uniform(0.5, 9, 3000).astype(np.float32)
+        R2 = rt.make_rays(o, d, tm)
+        _, oid = s.host_trace(R2, any_hit=True)
+        occ, m2 = oracle.occluded(w.scene, o32, d32, R2[:, 7].astype(np.float64))
+        rob = m2 > oracle.ROBUST
+        assert ((oid >= 0)[rob] == occ[rob]).all()
+
+
+def test_bvh_info_and_work_counts_are_sane():
+    w = S.config1(width=64, height=36, grid=128)
+    s = rt.Scene(w.scene)
+    info = s.info
+    assert info["n_bvh_prims"] == len(w.scene.tris) + len(w.scene.spheres)
+    assert info["n_leaves"] == info["n_nodes"] + 1             # binary tree: leaves = inner nodes + 1
+    assert info["stack_size"] == info["depth"] + 3
+    lo, hi = np.array(info["bounds_lo"]), np.array(info["bounds_hi"])
+    assert (lo <= w.scene.tris.reshape(-1, 3).min(0)).all() and (hi >= w.scene.tris.reshape(-1, 3).max(0)).all()
+    o, d = oracle.camera_rays(w.camera, w.params, np.arange(64 * 36))
+    t, ids, work = s.host_trace(rt.make_rays(o, d), with_work=True)
+    # a BVH visits far fewer primitives than brute force
+    assert work[:, 1].mean() < 0.01 * len(w.scene.tris)

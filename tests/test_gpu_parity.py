@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (fixed before any kernel existed): on every ray whose oracle margin
+exceeds 1e-4 the primary hit ids match exactly; on pixels whose whole ray tree
+is robust, RGB agrees within 1e-3 absolute; at least 98% of the compared
+pixels are robust.  Non-robust pixels must still carry a valid id.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1504_03151_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+RGB_TOL = 1e-3
+ROBUST = 1e-4
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_03151_amd import rt as _rt
+    _rt.lib()
+    return _rt
+
+
+def compare(w, rgb, ids, pixels=None, min_robust=0.98, nthreads=0):
+    spp = w.params.spp
+    g_rgb = rgb.reshape(-1, 3).double().cpu().numpy()
+    g_ids = ids.reshape(-1, spp).cpu().numpy()
+    if pixels is None:
+        pixels = np.arange(w.camera.n_pixels)
+    ref = oracle.render(w.scene, w.camera, w.params, pixels, nthreads=nthreads)
+    robust = ref["margin"] > ROBUST
+    g_rgb, g_ids = g_rgb[pixels], g_ids[pixels]
+    n_prims = w.scene.n_prims
+    assert ((g_ids >= -1) & (g_ids < n_prims)).all(), "invalid primitive id"
+    assert robust.mean() >= min_robust, f"robust fraction {robust.mean():.4f}"
+    bad_ids = np.where(robust[:, None] & (g_ids != ref["ids"]))
+    assert len(bad_ids[0]) == 0, (f"{len(bad_ids[0])} robust rays with different ids, e.g. pixel "
+                                  f"{pixels[bad_ids[0][0]]}: gpu {g_ids[bad_ids][0]} oracle {ref['ids'][bad_ids][0]}")
+    err = np.abs(g_rgb - ref["rgb"]).max(axis=1)
+    worst = int(np.argmax(np.where(robust, err, -1)))
+    assert err[robust].max() <= RGB_TOL, (f"rgb error {err[robust].max():.3e} at pixel {pixels[worst]}: "
+                                          f"gpu {g_rgb[worst]} oracle {ref['rgb'][worst]}")
+    return ref, robust, err
+
+
+def render(rt, w, **kw):
+    sc = rt.Scene(w.scene).upload()
+    rgb, ids, st = rt.render(sc, w.camera, w.params, **kw)
+    torch.cuda.synchronize()
+    return sc, rgb, ids, st
+
+
+# ------------------------------------------------------------------ whole images
+
+def test_config0_full_image(rt):
+    w = S.config0()
+    _, rgb, ids, st = render(rt, w)
+    ref, robust, _ = compare(w, rgb, ids)
+    # queue counts per depth equal the oracle's query counts up to non-robust pixels
+    o_counts = ref["counts"].sum(axis=0)
+    slack = (~robust).sum() * 8
+    for k in range(w.params.max_depth + 1):
+        assert abs(st["rays"][k] - o_counts[k, 0]) <= slack
+        assert abs(st["shadow"][k] - o_counts[k, 1]) <= slack
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_tiny_mixed_scenes_every_pixel(rt, seed):
+    # spheres + triangles + plane, Phong / mirror / glass, two lights, ragged 37x29 image
+    w = S.random_tiny(seed, size=37, depth=4)
+    w.camera.height = 29
+    _, rgb, ids, _ = render(rt, w)
+    compare(w, rgb, ids, min_robust=0.95)
+
+
+def test_one_sphere_silhouette_and_shadow(rt):
+    w = S.one_sphere(center=(0.3, -0.2, 0.5), radius=1.3, plane_y=-3.0, size=48)
+    w.params.max_depth = 2
+    _, rgb, ids, _ = render(rt, w)
+    compare(w, rgb, ids)
+
+
+def test_jittered_spp_and_graph_replay(rt):
+    w = S.random_tiny(5, size=24, depth=3)
+    w.params.spp, w.params.jitter, w.params.seed, w.params.frame = 9, 1, 77, 3
+    sc = rt.Scene(w.scene).upload()
+    r = rt.Renderer(sc, w.camera, w.params, samples_per_pass=2)   # 5 passes, the last one partial
+    first = [t.clone() for t in r.render()]
+    for _ in range(3):                                               # graph replays give the same frame
+        again = r.render()
+        torch.cuda.synchronize()
+        assert torch.equal(again[1], first[1])
+        assert torch.allclose(again[0], first[0], atol=1e-5)
+    compare(w, first[0], first[1], min_robust=0.95)
+
+
+def test_edge_cases(rt):
+    # empty scene (only background), a planes-only scene, a 1x1 image, depth 0
+    bg = (0.25, 0.5, 0.75)
+    empty = S.make_scene(materials=np.stack([S.material()]), lights=[[0, 5, 0, 1, 1, 1]])
+    cam = S.Camera((0.0, 0.0, -5.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, 5, 3)
+    w = S.Workload(empty, cam, S.Params(max_depth=2, bg=bg), "empty")
+    _, rgb, ids, st = render(rt, w)
+    assert (ids.cpu().numpy() == -1).all()
+    np.testing.assert_allclose(rgb.cpu().numpy().reshape(-1, 3), np.tile(bg, (15, 1)), rtol=0, atol=0)
+    planes = S.make_scene(planes=[[0, 1, 0, -1], [0, 0, -1, -20]], plane_mat=[0, 1],
+                          materials=np.stack([S.material(k_r=0.5), S.mirror_material()]),
+                          lights=[[0, 5, -3, 1, 1, 1]])
+    w = S.Workload(planes, S.Camera((0.0, 0.0, -5.0), (0.0, -0.2, 0.0), (0.0, 1.0, 0.0), 70.0, 17, 11),
+                   S.Params(max_depth=3), "planes")
+    _, rgb, ids, _ = render(rt, w)
+    compare(w, rgb, ids, min_robust=0.9)
+    w = S.config0()
+    w.camera.width = w.camera.height = 1
+    _, rgb, ids, _ = render(rt, w)
+    compare(w, rgb, ids, min_robust=1.0)
+    w = S.config0()
+    w.params.max_depth = 0
+    _, rgb, ids, _ = render(rt, w)
+    compare(w, rgb, ids)
+
+
+# ------------------------------------------------------------------ single rays through rt_intersect / rt_occluded
+
+def _oracle_rays(w, pixels):
+    recs = [oracle.ray_tree(w.scene, w.camera, w.params, int(p))[0] for p in pixels]
+    return np.concatenate(recs, axis=0)
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "c0"])
+def test_intersect_and_occluded_on_oracle_rays(rt, cfg):
+    w = S.random_tiny(7, size=40, depth=4) if cfg == "tiny" else S.config0()
+    pixels = S.pixel_subset(w.camera, 600, 11)
+    rec = _oracle_rays(w, pixels)
+    sc = rt.Scene(w.scene).upload()
+    for shadow in (False, True):
+        sel = rec[rec[:, 0] == 3] if shadow else rec[rec[:, 0] != 3]
+        R = rt.make_rays(sel[:, 2:5], sel[:, 5:8], sel[:, 8] if shadow else None)
+        o32, d32 = R[:, 0:3].astype(np.float64), R[:, 3:6].astype(np.float64)
+        Rd = torch.from_numpy(R).cuda()
+        if shadow:
+            occ = rt.occluded(sc, Rd).cpu().numpy().astype(bool)
+            ref, m = oracle.occluded(w.scene, o32, d32, R[:, 7].astype(np.float64))
+            rob = m > ROBUST
+            assert rob.mean() > 0.97 and (occ[rob] == ref[rob]).all()
+        else:
+            t, ids = rt.intersect(sc, Rd)
+            t, ids = t.cpu().numpy(), ids.cpu().numpy()
+            tr, ir, m = oracle.closest(w.scene, o32, d32)
+            rob = m > ROBUST
+            assert rob.mean() > 0.97
+            assert (ids[rob] == ir[rob]).all()
+            hit = rob & (ir >= 0)
+            np.testing.assert_allclose(t[hit], tr[hit], rtol=2e-5)
+
+
+def test_random_rays_bvh_equals_brute_force(rt):
+    for seed in range(3):
+        w = S.random_tiny(20 + seed, n_spheres=8, n_tris=200)
+        sc = rt.Scene(w.scene).upload()
+        rng = np.random.default_rng(seed)
+        o = rng.uniform(-6, 6, (20000, 3))
+        d = rng.normal(size=(20000, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        R = rt.make_rays(o, d)
+        t, ids = rt.intersect(sc, torch.from_numpy(R).cuda())
+        tr, ir, m = oracle.closest(w.scene, R[:, :3].astype(np.float64), R[:, 3:6].astype(np.float64))
+        rob = m > ROBUST
+        assert rob.mean() > 0.98
+        assert (ids.cpu().numpy()[rob] == ir[rob]).all()
+        # and the host traversal of the same BVH agrees with the device
+        th, ih = sc.host_trace(R)
+        assert (ih[rob] == ir[rob]).all()
+
+
+# ------------------------------------------------------------------ full-size configurations, sampled pixels
+
+def test_config1_full_frame_sampled(rt):
+    w = S.config1()
+    _, rgb, ids, st = render(rt, w)
+    assert st["status"] == 0
+    pixels = S.pixel_subset(w.camera, 384, 21)
+    compare(w, rgb, ids, pixels)
+
+
+def test_config2_full_frame_sampled(rt):
+    w = S.config2()
+    sc = rt.Scene(w.scene).upload()
+    r = rt.Renderer(sc, w.camera, w.params)
+    rgb, ids = r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    st = r.read_stats()
+    assert st["status"] == 0 and st["rays"][8] > 0
+    # sample pixels whose primary ray hits an object (oracle's own primary pass)
+    cand = S.pixel_subset(w.camera, 4000, 22)
+    o, d = oracle.camera_rays(w.camera, w.params, cand, sample=0)
+    _, ih, _ = oracle.closest(w.scene, o, d)
+    pixels = np.sort(np.concatenate([cand[ih >= 0][:10], cand[ih < 0][:2]]))
+    compare(w, rgb, ids, pixels, min_robust=0.9)
