@@ -104,8 +104,9 @@ enum {
     RT_FLAG_SYNC = 1,        /* synchronize the stream and check rt_stats.status before returning */
     RT_FLAG_COUNT_WORK = 2,  /* count BVH node visits and primitive tests into rt_stats (slower) */
     RT_FLAG_NO_GRAPH = 4,    /* launch kernels one by one instead of replaying a captured HIP graph */
-    RT_FLAG_TIME_KERNELS = 8 /* record HIP events around every traversal and shading launch on the
-                                frame's stream (implies RT_FLAG_NO_GRAPH); read with rt_kernel_times */
+    RT_FLAG_TIME_KERNELS = 8, /* record HIP events around every traversal and shading launch on the
+                                 frame's stream (implies RT_FLAG_NO_GRAPH); read with rt_kernel_times */
+    RT_FLAG_PER_SAMPLE = 16   /* keep every sample: out_rgb is [H][W][spp][3], not averaged */
 };
 
 /* Per-frame rendering parameters. */

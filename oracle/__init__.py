@@ -67,7 +67,8 @@ def lib():
             L = C.CDLL(build())
             L.or_render.restype = C.c_int
             L.or_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Params), C.c_void_p,
-                                    C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                                    C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p]
             L.or_closest.restype = C.c_int
             L.or_closest.argtypes = [C.POINTER(_Scene), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                                      C.c_void_p, C.c_void_p]
@@ -138,7 +139,8 @@ def _params(p) -> _Params:
 def render(scene, camera, params, pixels=None, nthreads: int = 0):
     """Brute-force render of the given pixels (default: all).
 
-    Returns dict(rgb [n,3] f64, ids [n,spp] i64, margin [n] f64, counts [n,D+1,2] i32, pixels [n] i64).
+    Returns dict(rgb [n,3] f64, ids [n,spp] i64, margin [n] f64, counts [n,D+1,2] i32, pixels [n] i64,
+    rgb_s [n,spp,3] f64 per-sample radiance, margin_s [n,spp] per-sample margin).
     """
     L = lib()
     if pixels is None:
@@ -150,12 +152,15 @@ def render(scene, camera, params, pixels=None, nthreads: int = 0):
     ids = np.zeros((n, params.spp), np.int64)
     margin = np.zeros((n,), np.float64)
     counts = np.zeros((n, D + 1, 2), np.int32)
+    rgb_s = np.zeros((n, params.spp, 3), np.float64)
+    margin_s = np.zeros((n, params.spp), np.float64)
     sc, cam, p = OScene(scene), _camera(camera), _params(params)
     rc = L.or_render(C.byref(sc.c), C.byref(cam), C.byref(p), pixels.ctypes.data, n, nthreads,
-                     rgb.ctypes.data, ids.ctypes.data, margin.ctypes.data, counts.ctypes.data)
+                     rgb.ctypes.data, ids.ctypes.data, margin.ctypes.data, counts.ctypes.data,
+                     rgb_s.ctypes.data, margin_s.ctypes.data)
     if rc != 0:
         raise ValueError(f"or_render failed ({rc})")
-    return dict(rgb=rgb, ids=ids, margin=margin, counts=counts, pixels=pixels)
+    return dict(rgb=rgb, ids=ids, margin=margin, counts=counts, pixels=pixels, rgb_s=rgb_s, margin_s=margin_s)
 
 
 def _rays9(o, d, tmax=None, so=0.0, sd=0.0):

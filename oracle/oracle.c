@@ -35,7 +35,11 @@
  *       refraction amplify round-off of the FP32 implementation).
  * margin = min over all decisions; a ray is robust when margin > 1e-4.
  * Rays that are not robust may legitimately differ between an FP32 and an
- * FP64 implementation; a pixel is robust when every ray of its tree is.
+ * FP64 implementation.  A sample (pixel) is robust when every decision of its
+ * ray tree that can move its radiance by more than 1e-4 is robust; decisions
+ * below that effect (deep, low-weight rays), up to 3e-4 in total per sample,
+ * cannot break a 1e-3 RGB comparison and are left out of its margin.  The
+ * per-ray margins (or_closest, or_occluded, the ray log) are never relaxed.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so oracle.c -lm -lpthread
  */
@@ -514,7 +518,50 @@ typedef struct {
     int32_t* counts;   /* [D+1][2]: closest-hit queries, shadow queries */
     double* rec;       /* optional ray log: [cap][RECW] */
     int64_t rec_n, rec_cap;
+    double lloc;       /* bound on any surface's local radiance */
+    double ignored;    /* worst-case RGB effect of decisions left out of the margin */
 } pctx;
+
+/* A decision whose worst-case effect on the sample's radiance is at most
+ * RGB_IRRELEVANT (and while the sample's total of such effects stays within
+ * RGB_BUDGET) cannot move the result by the 1e-3 RGB tolerance: it is left
+ * out of the sample's margin. */
+#define RGB_IRRELEVANT 1e-4
+#define RGB_BUDGET 3e-4
+
+static void note_margin(pctx* P, double m, double effect) {
+    if (m > 1e-4) {
+        P->margin = fmin(P->margin, m);
+        return;
+    }
+    if (effect <= RGB_IRRELEVANT && P->ignored + effect <= RGB_BUDGET) {
+        P->ignored += effect;
+        return;
+    }
+    P->margin = fmin(P->margin, m);
+}
+
+/* bound on the radiance of a ray at depth k: local radiance at most lloc per
+ * level (reflection weights k_r <= 1, F + (1 - F) = 1), plus the background */
+static double radiance_bound(const pctx* P, int k) {
+    const double* bg = P->p->bg;
+    return (P->p->max_depth - k + 1) * P->lloc + fmax(bg[0], fmax(bg[1], bg[2]));
+}
+
+static double local_bound(const or_scene* sc) {
+    double mat = 0.0, amb = 0.0, lsum = 0.0;
+    for (int m = 0; m < sc->n_materials; ++m) {
+        const float* M = sc->materials + 10 * m;
+        const double am = fmax(M[0], fmax(M[1], M[2]));
+        amb = fmax(amb, M[3] * am);
+        mat = fmax(mat, M[4] * am + M[5]);
+    }
+    for (int l = 0; l < sc->n_lights; ++l) {
+        const float* L = sc->lights + 6 * l;
+        lsum += fmax(L[3], fmax(L[4], L[5]));
+    }
+    return amb + lsum * mat;
+}
 
 /* ray log record: kind (0 camera, 1 reflected, 2 refracted, 3 shadow), depth,
  * o[3], d[3], tmax, t (closest hit) or blocked (shadow), id, margin */
@@ -563,13 +610,15 @@ static double geom_normal(const or_scene* sc, int64_t id, const double* x, doubl
     }
 }
 
-static void trace(pctx* P, const oray* ray, int kind, int k, double* out, int64_t* primary_id) {
+/* w: the ray's throughput (its weight in the sample's radiance) */
+static void trace(pctx* P, const oray* ray, int kind, int k, const double* w, double* out, int64_t* primary_id) {
     const or_scene* sc = P->sc;
     const or_params* p = P->p;
+    const double wmax = fmax(w[0], fmax(w[1], w[2]));
     P->counts[2 * k + 0] += 1;
     hitrec h;
     closest_hit(P->S, ray, &h);
-    P->margin = fmin(P->margin, h.margin);
+    note_margin(P, h.margin, wmax * radiance_bound(P, k));
     log_ray(P, kind, k, ray, h.t, h.id, h.margin);
     if (primary_id) *primary_id = h.id;
     if (h.id < 0) {
@@ -583,7 +632,7 @@ static void trace(pctx* P, const oray* ray, int kind, int k, double* out, int64_
     const double dn = dot3(ray->d, ng);
     const int entering = dn < 0.0;
     /* which side faces the ray is a discrete decision (two-sided shading) */
-    P->margin = fmin(P->margin, fmin(fabs(dn), 1e-4 * fabs(dn) / (ray->sd + sn + EA)));
+    note_margin(P, fmin(fabs(dn), 1e-4 * fabs(dn) / (ray->sd + sn + EA)), wmax * radiance_bound(P, k));
     for (int i = 0; i < 3; ++i) {
         nf[i] = entering ? ng[i] : -ng[i];
         v[i] = -ray->d[i];
@@ -630,7 +679,7 @@ static void trace(pctx* P, const oray* ray, int kind, int k, double* out, int64_
         P->counts[2 * k + 1] += 1;
         double sm;
         const int blocked = any_hit(P->S, &sr, &sm);
-        P->margin = fmin(P->margin, sm);
+        note_margin(P, sm, fmax(w[0] * c[0], fmax(w[1] * c[1], w[2] * c[2])));
         log_ray(P, 3, k, &sr, (double)blocked, -1, sm);
         if (!blocked)
             for (int i = 0; i < 3; ++i) local[i] += c[i];
@@ -652,7 +701,7 @@ static void trace(pctx* P, const oray* ray, int kind, int k, double* out, int64_
     if (type == MAT_DIELECTRIC) {
         const double eta = entering ? 1.0 / ior : ior;
         const double k2 = 1.0 - eta * eta * (1.0 - cosi * cosi);
-        P->margin = fmin(P->margin, 1e-4 * fabs(k2) / (2.0 * eta * eta * (ray->sd + sn) + EA));
+        note_margin(P, 1e-4 * fabs(k2) / (2.0 * eta * eta * (ray->sd + sn) + EA), wmax * radiance_bound(P, k + 1));
         const double r0 = ((ior - 1.0) / (ior + 1.0)) * ((ior - 1.0) / (ior + 1.0));
         double F = 1.0;
         oray tr;
@@ -672,17 +721,17 @@ static void trace(pctx* P, const oray* ray, int kind, int k, double* out, int64_
             tr.sd = (ray->sd + 2.0 * sn) * (1.0 + eta / fmax(ck, 1e-2)) + EA;
             has_t = 1;
         }
-        double lr[3];
-        trace(P, &rf, 1, k + 1, lr, NULL);
+        double lr[3], wr[3] = {w[0] * F, w[1] * F, w[2] * F};
+        trace(P, &rf, 1, k + 1, wr, lr, NULL);
         for (int i = 0; i < 3; ++i) out[i] += F * lr[i];
         if (has_t) {
-            double lt[3];
-            trace(P, &tr, 2, k + 1, lt, NULL);
+            double lt[3], wt[3] = {w[0] * (1.0 - F), w[1] * (1.0 - F), w[2] * (1.0 - F)};
+            trace(P, &tr, 2, k + 1, wt, lt, NULL);
             for (int i = 0; i < 3; ++i) out[i] += (1.0 - F) * lt[i];
         }
     } else if (kr > 0.0) {
-        double lr[3];
-        trace(P, &rf, 1, k + 1, lr, NULL);
+        double lr[3], wr[3] = {w[0] * kr, w[1] * kr, w[2] * kr};
+        trace(P, &rf, 1, k + 1, wr, lr, NULL);
         for (int i = 0; i < 3; ++i) out[i] += kr * lr[i];
     }
 }
@@ -734,6 +783,8 @@ typedef struct {
     int64_t* ids;
     double* margin;
     int32_t* counts;
+    double* rgb_s;      /* [n][spp][3] per-sample radiance, or NULL */
+    double* margin_s;   /* [n][spp] per-sample margin, or NULL */
 } render_job;
 
 static void render_one(void* vctx, int64_t i) {
@@ -741,7 +792,8 @@ static void render_one(void* vctx, int64_t i) {
     const int D = J->p->max_depth;
     int32_t local_counts[2 * 64];
     memset(local_counts, 0, sizeof local_counts);
-    pctx P = {J->S, J->sc, J->p, MARGIN_CAP, local_counts, NULL, 0, 0};
+    pctx P = {J->S, J->sc, J->p, MARGIN_CAP, local_counts, NULL, 0, 0, local_bound(J->sc), 0.0};
+    const double one[3] = {1.0, 1.0, 1.0};
     double acc[3] = {0, 0, 0};
     const int64_t pix = J->pixels[i];
     for (int s = 0; s < J->p->spp; ++s) {
@@ -752,9 +804,16 @@ static void render_one(void* vctx, int64_t i) {
         r.sd = EA;
         double L[3];
         int64_t pid = -1;
-        trace(&P, &r, 0, 0, L, &pid);
+        const double m_before = P.margin;
+        P.margin = MARGIN_CAP;
+        P.ignored = 0.0;
+        trace(&P, &r, 0, 0, one, L, &pid);
         for (int c = 0; c < 3; ++c) acc[c] += L[c];
         if (J->ids) J->ids[i * J->p->spp + s] = pid;
+        if (J->rgb_s)
+            for (int c = 0; c < 3; ++c) J->rgb_s[(i * J->p->spp + s) * 3 + c] = L[c];
+        if (J->margin_s) J->margin_s[i * J->p->spp + s] = P.margin;
+        P.margin = fmin(P.margin, m_before);
     }
     for (int c = 0; c < 3; ++c) J->rgb[3 * i + c] = acc[c] / J->p->spp;
     if (J->margin) J->margin[i] = P.margin;
@@ -762,13 +821,15 @@ static void render_one(void* vctx, int64_t i) {
 }
 
 /* Render a list of pixels.  rgb [n][3], ids [n][spp] (or NULL), margin [n]
- * (min over the pixel's ray trees, or NULL), counts [n][D+1][2] (or NULL). */
+ * (min over the pixel's ray trees, or NULL), counts [n][D+1][2] (or NULL),
+ * rgb_s [n][spp][3] and margin_s [n][spp] per sample (or NULL). */
 int or_render(const or_scene* sc, const or_camera* cam, const or_params* p, const int64_t* pixels, int64_t n,
-              int32_t nthreads, double* rgb, int64_t* ids, double* margin, int32_t* counts) {
+              int32_t nthreads, double* rgb, int64_t* ids, double* margin, int32_t* counts, double* rgb_s,
+              double* margin_s) {
     if (p->max_depth < 0 || p->max_depth > 63 || p->spp < 1) return -1;
     oscene S;
     if (oscene_init(&S, sc) != 0) return -2;
-    render_job J = {&S, sc, cam, p, pixels, rgb, ids, margin, counts};
+    render_job J = {&S, sc, cam, p, pixels, rgb, ids, margin, counts, rgb_s, margin_s};
     run_parallel(n, nthreads, render_one, &J);
     oscene_free(&S);
     return 0;
@@ -842,14 +903,15 @@ int64_t or_ray_tree(const or_scene* sc, const or_camera* cam, const or_params* p
     if (oscene_init(&S, sc) != 0) return -2;
     int32_t counts[2 * 64];
     memset(counts, 0, sizeof counts);
-    pctx P = {&S, sc, p, MARGIN_CAP, counts, rec, 0, cap};
+    pctx P = {&S, sc, p, MARGIN_CAP, counts, rec, 0, cap, local_bound(sc), 0.0};
+    const double one[3] = {1.0, 1.0, 1.0};
     oray r;
     or_camera_ray(cam, p, pixel, sample, r.o, r.d);
     r.tmax = OR_INF;
     r.so = EA * maxabs3(r.o);
     r.sd = EA;
     int64_t pid;
-    trace(&P, &r, 0, 0, rgb, &pid);
+    trace(&P, &r, 0, 0, one, rgb, &pid);
     oscene_free(&S);
     return P.rec_n;
 }

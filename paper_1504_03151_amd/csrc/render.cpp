@@ -75,6 +75,7 @@ struct ShadeConst {
     int max_depth;
     int spp;
     uint32_t qcap, scap;
+    int per_sample;   // accumulation slot = pixel * spp + sample instead of pixel
 };
 
 // ---------------------------------------------------------------------------
@@ -161,7 +162,7 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 // sample, so primary rays of a wave are coherent.  The camera ray is formed in
 // FP64 and rounded once to FP32.
 __global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, int tiles_x, int64_t n_threads,
-                                                RayQ q, uint32_t* ctr, uint32_t cap) {
+                                                RayQ q, uint32_t* ctr, uint32_t cap, int per_sample) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int64_t tile_sample = g >> 6;
@@ -203,7 +204,7 @@ __global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, in
     q.wr[slot] = 1.0f;
     q.wg[slot] = 1.0f;
     q.wb[slot] = 1.0f;
-    q.pix[slot] = pixel;
+    q.pix[slot] = per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel;
     q.meta[slot] = ((uint32_t)s << 4);
 }
 
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
                 int oid = -1;
                 if (prim >= sc.n_bvh) oid = prim;
                 else if (prim >= 0) oid = as_int_f(sc.prims[3 * prim].w);
-                out_ids[(size_t)pix * c.spp + ((meta >> 4) & 0xFFFFu)] = oid;
+                out_ids[c.per_sample ? (size_t)pix : (size_t)pix * c.spp + ((meta >> 4) & 0xFFFFu)] = oid;
             }
         }
         const bool shade = active && prim >= 0;
@@ -580,6 +581,7 @@ static rt_status persistent_grid(K kernel, size_t lds, int& blocks) {
 
 struct Plan {
     int64_t npix = 0;
+    int64_t nacc = 0;        // accumulation slots: pixels, or pixels * spp per sample
     int spp_pass = 1, passes = 1;
     int64_t n_primary = 0;   // rays of a full pass
     uint32_t qcap = 0, scap = 0;
@@ -624,8 +626,13 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     size_t off = 0;
     pl.off_ctr = off;
     off = a256(off + 4 * kCtrWords);
+    pl.nacc = (p.flags & RT_FLAG_PER_SAMPLE) ? pl.npix * p.spp : pl.npix;
+    if (pl.nacc >= ((int64_t)1 << 32)) {
+        why = "too many accumulation slots (pixels x spp) for per-sample output";
+        return false;
+    }
     pl.off_acc = off;
-    off = a256(off + 12 * (size_t)pl.npix);
+    off = a256(off + 12 * (size_t)pl.nacc);
     for (int b = 0; b < 2; ++b) {
         pl.off_q[b] = off;
         off = a256(off + 11 * 4 * (size_t)pl.qcap + 11 * 256);
@@ -784,7 +791,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
     unsigned long long* swork = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->shadow_node_visits) : nullptr;
 
-    const int64_t n3 = 3 * pl.npix;
+    const int64_t n3 = 3 * pl.nacc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
     const int tiles_x = (A.cam.W + 7) / 8, tiles_y = (A.cam.H + 7) / 8;
     for (int pass = 0; pass < pl.passes; ++pass) {
@@ -793,7 +800,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
         const int64_t nthreads = (int64_t)tiles_x * tiles_y * ns * 64;
         hipLaunchKernelGGL(k_raygen, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, A.cam, s0, ns,
-                           tiles_x, nthreads, q[0], ctr, pl.qcap);
+                           tiles_x, nthreads, q[0], ctr, pl.qcap, A.shc.per_sample);
         for (int k = 0; k <= A.shc.max_depth; ++k) {
             RayQ& qi = q[k & 1];
             RayQ& qo = q[(k + 1) & 1];
@@ -824,7 +831,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth);
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
-                       1.0f / (float)A.spp);
+                       A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp);
     HIP_TRY(hipGetLastError());
     return RT_OK;
 }
@@ -973,6 +980,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.shc.spp = p.spp;
     A.shc.qcap = pl.qcap;
     A.shc.scap = pl.scap;
+    A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
     A.pl = pl;
     A.ws = static_cast<uint8_t*>(p.workspace);
     A.stats = static_cast<rt_stats*>(p.stats);

@@ -21,7 +21,7 @@ _lib = None
 RT_OK = 0
 RT_ERR = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP", -4: "BVH_DEPTH", -5: "CAPACITY",
           -6: "DEVICE_STATUS", -7: "NOT_UPLOADED"}
-FLAG_SYNC, FLAG_COUNT_WORK, FLAG_NO_GRAPH, FLAG_TIME_KERNELS = 1, 2, 4, 8
+FLAG_SYNC, FLAG_COUNT_WORK, FLAG_NO_GRAPH, FLAG_TIME_KERNELS, FLAG_PER_SAMPLE = 1, 2, 4, 8, 16
 STATS_MAX_DEPTH = 16
 
 
@@ -242,26 +242,28 @@ class Renderer:
     """Owns the device workspace, outputs and stats for repeated frames of one scene/camera."""
 
     def __init__(self, scene: Scene, camera, params, device="cuda", with_ids=True, samples_per_pass=0,
-                 queue_factor=0.0, graph=True):
+                 queue_factor=0.0, graph=True, per_sample=False):
         import torch
         if scene.blob is None:
             scene.upload(device)
         self.scene, self.camera, self.params = scene, camera, params
         self.device = device
         self.samples_per_pass, self.queue_factor, self.graph = samples_per_pass, queue_factor, graph
+        self.base_flags = FLAG_PER_SAMPLE if per_sample else 0
         self.cam_c = camera_c(camera)
         self._alloc(with_ids)
 
     def _alloc(self, with_ids):
         import torch
-        p = params_c(self.params, 0, self.samples_per_pass, self.queue_factor)
+        p = params_c(self.params, self.base_flags, self.samples_per_pass, self.queue_factor)
         n = lib().rt_render_workspace_bytes(self.scene.handle, C.byref(self.cam_c), C.byref(p))
         if n == 0:
             raise RTError(-1, "rt_render_workspace_bytes", lib().rt_last_error().decode())
         self.ws_bytes = int(n)
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
         H, W = self.camera.height, self.camera.width
-        self.rgb = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        shape = (H, W, self.params.spp, 3) if self.base_flags & FLAG_PER_SAMPLE else (H, W, 3)
+        self.rgb = torch.empty(shape, dtype=torch.float32, device=self.device)
         self.ids = torch.empty((H, W, self.params.spp), dtype=torch.int32, device=self.device) if with_ids else None
         self.stats = torch.zeros(C.sizeof(Stats) + 64, dtype=torch.uint8, device=self.device)
 
@@ -270,7 +272,7 @@ class Renderer:
             self.stats.zero_()
         if not self.graph:
             flags |= FLAG_NO_GRAPH
-        p = params_c(self.params, flags, self.samples_per_pass, self.queue_factor)
+        p = params_c(self.params, flags | self.base_flags, self.samples_per_pass, self.queue_factor)
         p.workspace, p.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
         p.stats = self.stats.data_ptr()
         p.stream = _stream_ptr(stream)
