@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", action="store_true", help="time graph replays (no per-kernel events)")
+    ap.add_argument("--samples-per-pass", type=int, default=0, help="0 = chosen by the library")
+    ap.add_argument("--queue-chunk", type=int, default=0, help="0 = library default")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -104,7 +106,7 @@ def main():
     sc = rt.Scene(w.scene)
     log(f"BVH build {time.perf_counter() - t0:.2f} s: {sc.info}")
     sc.upload()
-    r = rt.Renderer(sc, w.camera, w.params)
+    r = rt.Renderer(sc, w.camera, w.params, samples_per_pass=args.samples_per_pass, queue_chunk=args.queue_chunk)
     log(f"workspace {r.ws_bytes / 2 ** 30:.2f} GiB")
 
     # untimed counting frame: rays per depth and BVH work of every traversal launch

@@ -121,7 +121,7 @@ typedef struct {
     int32_t samples_per_pass; /* samples traced per wavefront pass; 0 = chosen from the workspace */
     int32_t flags;            /* RT_FLAG_* */
     float queue_factor;       /* ray-queue capacity per pass, in primary rays (0 = 2.0) */
-    int32_t reserved;
+    int32_t queue_chunk;      /* queue entries a traversal wave takes per fetch (0 = 128; multiple of 64) */
     void* workspace;          /* device, rt_render_workspace_bytes() bytes */
     size_t workspace_bytes;
     void* stats;              /* device rt_stats or NULL; accumulated, caller zeroes it */

@@ -59,6 +59,7 @@ constexpr int kCtrRayCur = 16;    // [16] extend fetch cursors
 constexpr int kCtrShadow = 32;    // [16] shadow rays queued at depth k
 constexpr int kCtrShadowCur = 48; // [16] shadow fetch cursors
 constexpr int kCtrStatus = 64;    // overflow flags
+constexpr int kCtrDead = 65;      // padding slots of ragged tiles in the primary queue
 constexpr int kCtrWords = 128;
 
 struct CamConst {
@@ -131,6 +132,40 @@ __device__ __forceinline__ LdsStack lds_stack(int32_t* smem, int stack_size) {
     return s;
 }
 
+// Traversal stack of the frame kernels: the top kSplitLds entries of each lane
+// live in LDS ([entry][lane] columns), deeper entries (rare: only on long
+// paths of deep trees) in a per-thread global region ([entry][thread]).
+// Keeping LDS at 4 KB per wave lets register pressure, not LDS, set occupancy.
+constexpr int kSplitLds = 16;
+struct SplitStack {
+    int32_t* p;      // LDS column of this lane
+    int32_t* g;      // overflow column of this thread (stride = threads of the grid)
+    uint32_t gstride;
+    int sp;
+    __device__ void reset() {
+        p[0] = kStackDone;
+        sp = 1;
+    }
+    __device__ void push(int32_t v) {
+        if (sp < kSplitLds) p[sp * 64] = v;
+        else g[(size_t)(sp - kSplitLds) * gstride] = v;
+        ++sp;
+    }
+    __device__ int32_t pop() {
+        --sp;
+        return sp < kSplitLds ? p[sp * 64] : g[(size_t)(sp - kSplitLds) * gstride];
+    }
+};
+
+__device__ __forceinline__ SplitStack split_stack(int32_t* smem, int32_t* overflow) {
+    SplitStack s;
+    s.p = smem + (threadIdx.x >> 6) * kSplitLds * 64 + (threadIdx.x & 63);
+    s.gstride = gridDim.x * blockDim.x;
+    s.g = overflow + blockIdx.x * blockDim.x + threadIdx.x;
+    s.sp = 0;
+    return s;
+}
+
 template <bool COUNT>
 __device__ __forceinline__ void flush_work(const Work& w, unsigned long long* dst) {
     if (!COUNT || !dst) return;
@@ -158,23 +193,34 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
     if (i < n) p[i] = v;
 }
 
-// One thread per (pixel, sample); a wave covers an 8x8 pixel tile of one
-// sample, so primary rays of a wave are coherent.  The camera ray is formed in
-// FP64 and rounded once to FP32.
-__global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, int tiles_x, int64_t n_threads,
+// Ray slots of a pass map 1:1 to threads: a wave covers one 8x8 pixel tile of
+// one sample, so primary rays of a wave are coherent and no atomic is needed.
+// Lanes past the image edge (ragged tiles) write a dead ray (pixel kDeadRay)
+// that the later stages skip.  The camera ray is formed in FP64 and rounded
+// once to FP32.
+constexpr uint32_t kDeadRay = 0xFFFFFFFFu;
+
+__global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, int tiles_x, uint32_t n_threads,
                                                 RayQ q, uint32_t* ctr, uint32_t cap, int per_sample) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const int64_t tile_sample = g >> 6;
-    const int64_t tile = tile_sample / ns;
-    const int s = s0 + (int)(tile_sample % ns);
-    const int px = (int)(tile % tiles_x) * 8 + (lane & 7);
-    const int py = (int)(tile / tiles_x) * 8 + (lane >> 3);
-    const bool valid = g < n_threads && px < cam.W && py < cam.H;
-    const uint32_t slot = wave_reserve(valid ? 1u : 0u, ctr + kCtrRays);
-    if (!valid) return;
-    if (slot >= cap) {
-        atomicOr(ctr + kCtrStatus, 1u);
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) {
+        ctr[kCtrRays] = n_threads;
+        if (n_threads > cap) atomicOr(ctr + kCtrStatus, 1u);
+    }
+    if (g >= n_threads || g >= cap) return;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t tile_sample = g >> 6;
+    const uint32_t tile = tile_sample / (uint32_t)ns;
+    const int s = s0 + (int)(tile_sample - tile * (uint32_t)ns);
+    const uint32_t ty = tile / (uint32_t)tiles_x;
+    const int px = (int)(tile - ty * (uint32_t)tiles_x) * 8 + (int)(lane & 7u);
+    const int py = (int)ty * 8 + (int)(lane >> 3);
+    const bool dead = px >= cam.W || py >= cam.H;
+    const uint64_t dead_mask = __ballot(dead);
+    if (dead_mask && lane == (uint32_t)(__ffsll((unsigned long long)dead_mask) - 1))
+        atomicAdd(ctr + kCtrDead, (uint32_t)__popcll(dead_mask));
+    if (dead) {
+        q.pix[g] = kDeadRay;
         return;
     }
     const uint32_t pixel = (uint32_t)py * cam.W + px;
@@ -195,67 +241,80 @@ __global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, in
     double d[3];
     for (int i = 0; i < 3; ++i) d[i] = cam.f[i] + X * cam.r[i] + Y * cam.u[i];
     const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    q.ox[slot] = (float)cam.eye[0];
-    q.oy[slot] = (float)cam.eye[1];
-    q.oz[slot] = (float)cam.eye[2];
-    q.dx[slot] = (float)(d[0] * inv);
-    q.dy[slot] = (float)(d[1] * inv);
-    q.dz[slot] = (float)(d[2] * inv);
-    q.wr[slot] = 1.0f;
-    q.wg[slot] = 1.0f;
-    q.wb[slot] = 1.0f;
-    q.pix[slot] = per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel;
-    q.meta[slot] = ((uint32_t)s << 4);
+    q.ox[g] = (float)cam.eye[0];
+    q.oy[g] = (float)cam.eye[1];
+    q.oz[g] = (float)cam.eye[2];
+    q.dx[g] = (float)(d[0] * inv);
+    q.dy[g] = (float)(d[1] * inv);
+    q.dz[g] = (float)(d[2] * inv);
+    q.wr[g] = 1.0f;
+    q.wg[g] = 1.0f;
+    q.wb[g] = 1.0f;
+    q.pix[g] = per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel;
+    q.meta[g] = ((uint32_t)s << 4);
 }
 
-// Persistent closest-hit kernel: each wave grabs 64 queued rays at a time
-// until the queue is drained.  Sources/sinks are the ray queue and hit buffer.
+// Persistent traversal kernels: each wave takes `chunk` consecutive queue
+// entries per atomic on the fetch cursor (a multiple of 64) and traces them 64
+// at a time until the queue is drained.
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_extend(DevScene sc, RayQ q, HitQ hit, const uint32_t* count_p,
-                                                uint32_t* cursor, uint32_t cap, unsigned long long* work_out) {
-    extern __shared__ int32_t smem[];
-    LdsStack stk = lds_stack(smem, sc.stack_size);
+                                                uint32_t* cursor, uint32_t cap, uint32_t chunk, int32_t* overflow,
+                                                unsigned long long* work_out) {
+    __shared__ int32_t smem[4 * kSplitLds * 64];
+    SplitStack stk = split_stack(smem, overflow);
     const uint32_t count = min(*count_p, cap);   // a producer that overflowed still bumped the tail
     Work w{0, 0, 0};
     for (;;) {
         uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(cursor, 64u);
+        if (lane_id() == 0) base = atomicAdd(cursor, chunk);
         base = __shfl(base, 0, 64);
         if (base >= count) break;
-        const uint32_t i = base + lane_id();
-        if (i < count) {
-            const TRay r = make_tray(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
-            const Hit h = traverse<false, COUNT>(sc, r, INFINITY, stk, w);
-            hit.t[i] = h.t;
-            hit.prim[i] = h.prim;
+        const uint32_t end = min(base + chunk, count);
+        for (uint32_t b = base; b < end; b += 64) {
+            const uint32_t i = b + lane_id();
+            if (i < end) {
+                if (q.pix[i] == kDeadRay) {
+                    hit.prim[i] = -1;
+                    continue;
+                }
+                const TRay r = make_tray(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
+                const Hit h = traverse<false, COUNT>(sc, r, INFINITY, stk, w);
+                hit.t[i] = h.t;
+                hit.prim[i] = h.prim;
+            }
         }
     }
     flush_work<COUNT>(w, work_out);
 }
 
-// Persistent any-hit kernel over the shadow queue; adds the contribution of
-// each unblocked light to its pixel.
+// Any-hit over the shadow queue; adds the contribution of each unblocked light
+// to its pixel.
 template <bool COUNT>
 __global__ __launch_bounds__(256) void k_shadow(DevScene sc, ShadowQ s, const uint32_t* count_p, uint32_t* cursor,
-                                                uint32_t cap, float* acc, unsigned long long* work_out) {
-    extern __shared__ int32_t smem[];
-    LdsStack stk = lds_stack(smem, sc.stack_size);
+                                                uint32_t cap, uint32_t chunk, float* acc, int32_t* overflow,
+                                                unsigned long long* work_out) {
+    __shared__ int32_t smem[4 * kSplitLds * 64];
+    SplitStack stk = split_stack(smem, overflow);
     const uint32_t count = min(*count_p, cap);
     Work w{0, 0, 0};
     for (;;) {
         uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(cursor, 64u);
+        if (lane_id() == 0) base = atomicAdd(cursor, chunk);
         base = __shfl(base, 0, 64);
         if (base >= count) break;
-        const uint32_t i = base + lane_id();
-        if (i < count) {
-            const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
-            const Hit h = traverse<true, COUNT>(sc, r, s.tmax[i], stk, w);
-            if (h.prim < 0) {
-                const uint32_t p = s.pix[i];
-                atomicAdd(acc + 3 * p + 0, s.cr[i]);
-                atomicAdd(acc + 3 * p + 1, s.cg[i]);
-                atomicAdd(acc + 3 * p + 2, s.cb[i]);
+        const uint32_t end = min(base + chunk, count);
+        for (uint32_t b = base; b < end; b += 64) {
+            const uint32_t i = b + lane_id();
+            if (i < end) {
+                const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
+                const Hit h = traverse<true, COUNT>(sc, r, s.tmax[i], stk, w);
+                if (h.prim < 0) {
+                    const uint32_t p = s.pix[i];
+                    atomicAdd(acc + 3 * p + 0, s.cr[i]);
+                    atomicAdd(acc + 3 * p + 1, s.cg[i]);
+                    atomicAdd(acc + 3 * p + 2, s.cb[i]);
+                }
             }
         }
     }
@@ -277,25 +336,98 @@ __device__ __forceinline__ float pow_spec(float x, float n) {
     return powf(x, n);
 }
 
+// Block-wide reservation: each wave passes its total, one atomic per block and
+// queue; returns the wave's base slot.  All threads of the block must call.
+__device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, uint32_t* tail, uint32_t* lds4) {
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0) lds4[wave] = wave_total;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t t0 = lds4[0], t1 = lds4[1], t2 = lds4[2], t3 = lds4[3];
+        const uint32_t tot = t0 + t1 + t2 + t3;
+        const uint32_t base = tot ? atomicAdd(tail, tot) : 0u;
+        lds4[0] = base;
+        lds4[1] = base + t0;
+        lds4[2] = base + t0 + t1;
+        lds4[3] = base + t0 + t1 + t2;
+    }
+    __syncthreads();
+    const uint32_t r = lds4[wave];
+    __syncthreads();
+    return r;
+}
+
+struct LightTerm {
+    float cr, cg, cb;
+    bool emit;
+};
+
+// Phong light term (without visibility) of light L at x with facing normal nf.
+__device__ __forceinline__ LightTerm light_term(const DevLight& L, V3 x, V3 nf, V3 d, V3 alb, float kd, float ks,
+                                                float shin) {
+    LightTerm t{0.0f, 0.0f, 0.0f, false};
+    V3 lv = xyz(L.pos) - x;
+    lv = lv * (1.0f / sqrtf(dot(lv, lv)));
+    const float ndl = dot(nf, lv);
+    if (ndl <= 0.0f) return t;
+    const V3 rr = (2.0f * ndl) * nf - lv;
+    const float rv = fmaxf(0.0f, -dot(rr, d));
+    const float spec = ks * pow_spec(rv, shin);
+    const V3 I = xyz(L.intensity);
+    t.cr = I.x * (kd * alb.x * ndl + spec);
+    t.cg = I.y * (kd * alb.y * ndl + spec);
+    t.cb = I.z * (kd * alb.z * ndl + spec);
+    t.emit = fmaxf(t.cr, fmaxf(t.cg, t.cb)) > 0.0f;
+    return t;
+}
+
+__device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, uint32_t cap, uint32_t* ctr, V3 xs,
+                                             const DevLight& L, V3 w, const LightTerm& lt, uint32_t pix) {
+    if (slot >= cap) {
+        atomicOr(ctr + kCtrStatus, 2u);
+        return;
+    }
+    V3 sd = xyz(L.pos) - xs;
+    const float dist = sqrtf(dot(sd, sd));
+    sd = sd * (1.0f / dist);
+    sq.ox[slot] = xs.x;
+    sq.oy[slot] = xs.y;
+    sq.oz[slot] = xs.z;
+    sq.dx[slot] = sd.x;
+    sq.dy[slot] = sd.y;
+    sq.dz[slot] = sd.z;
+    sq.tmax[slot] = dist;
+    sq.cr[slot] = w.x * lt.cr;
+    sq.cg[slot] = w.y * lt.cg;
+    sq.cb[slot] = w.z * lt.cb;
+    sq.pix[slot] = pix;
+}
+
 // Shading of one depth: Phong local terms (ambient now, light terms deferred to
-// the shadow kernel), reflected / refracted rays into the next queue, with
-// wave-wide compaction (one atomic per wave and queue).
+// the shadow kernel), reflected / refracted rays into the next queue.  Queue
+// slots are reserved with one atomic per block and queue; shadow rays are laid
+// out light-major inside each wave (consecutive entries go to the same light)
+// so the shadow kernel's waves traverse coherently.
 __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ qin, HitQ hit, uint32_t* ctr, int depth,
                                                RayQ qout, ShadowQ sq, float* acc, int32_t* out_ids) {
+    __shared__ uint32_t lds_res[4];
     const uint32_t count = min(ctr[kCtrRays + depth], c.qcap);
     const uint32_t stride = gridDim.x * blockDim.x;
-    const uint32_t wave_base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
-    for (uint32_t wb = wave_base0; wb < count; wb += stride) {
-        const uint32_t i = wb + lane_id();
-        const bool active = i < count;
+    const bool light_major = sc.n_lights <= 32;
+    for (uint32_t bb = blockIdx.x * blockDim.x; bb < count; bb += stride) {   // block-uniform loop
+        const uint32_t i = bb + threadIdx.x;
+        bool active = i < count;
         int prim = -1;
         uint32_t pix = 0, meta = 0;
         V3 o = v3(0, 0, 0), d = v3(0, 0, 1), w = v3(0, 0, 0);
         float t = 0.0f;
         if (active) {
+            pix = qin.pix[i];
+            active = pix != kDeadRay;
+        }
+        if (active) {
             prim = hit.prim[i];
             t = hit.t[i];
-            pix = qin.pix[i];
             meta = qin.meta[i];
             o = v3(qin.ox[i], qin.oy[i], qin.oz[i]);
             d = v3(qin.dx[i], qin.dy[i], qin.dz[i]);
@@ -348,65 +480,47 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
             atomicAdd(acc + 3 * pix + 1, w.y * ka * alb.y);
             atomicAdd(acc + 3 * pix + 2, w.z * ka * alb.z);
         }
-        // shadow rays: count, reserve, then write
-        uint32_t n_sh = 0;
+        // ---- shadow rays: decide per light, reserve, then write
+        uint32_t emit_mask = 0, n_sh = 0;
         if (shade) {
             for (int l = 0; l < sc.n_lights; ++l) {
-                const DevLight L = sc.lights[l];
-                V3 lv = xyz(L.pos) - x;
-                lv = lv * (1.0f / sqrtf(dot(lv, lv)));
-                const float ndl = dot(nf, lv);
-                if (ndl <= 0.0f) continue;
-                const V3 rr = (2.0f * ndl) * nf - lv;
-                const float rv = fmaxf(0.0f, -dot(rr, d));
-                const float spec = ks * pow_spec(rv, shin);
-                const V3 I = xyz(L.intensity);
-                const float cr = I.x * (kd * alb.x * ndl + spec), cg = I.y * (kd * alb.y * ndl + spec),
-                            cb = I.z * (kd * alb.z * ndl + spec);
-                if (fmaxf(cr, fmaxf(cg, cb)) > 0.0f) n_sh++;
-            }
-        }
-        uint32_t sslot = wave_reserve(n_sh, ctr + kCtrShadow + depth);
-        if (n_sh) {
-            for (int l = 0; l < sc.n_lights; ++l) {
-                const DevLight L = sc.lights[l];
-                V3 lv = xyz(L.pos) - x;
-                lv = lv * (1.0f / sqrtf(dot(lv, lv)));
-                const float ndl = dot(nf, lv);
-                if (ndl <= 0.0f) continue;
-                const V3 rr = (2.0f * ndl) * nf - lv;
-                const float rv = fmaxf(0.0f, -dot(rr, d));
-                const float spec = ks * pow_spec(rv, shin);
-                const V3 I = xyz(L.intensity);
-                const float cr = I.x * (kd * alb.x * ndl + spec), cg = I.y * (kd * alb.y * ndl + spec),
-                            cb = I.z * (kd * alb.z * ndl + spec);
-                if (!(fmaxf(cr, fmaxf(cg, cb)) > 0.0f)) continue;
-                if (sslot >= c.scap) {
-                    atomicOr(ctr + kCtrStatus, 2u);
-                    break;
+                const LightTerm lt = light_term(sc.lights[l], x, nf, d, alb, kd, ks, shin);
+                if (lt.emit) {
+                    n_sh++;
+                    if (l < 32) emit_mask |= 1u << l;
                 }
-                V3 sd = xyz(L.pos) - xs;
-                const float dist = sqrtf(dot(sd, sd));
-                sd = sd * (1.0f / dist);
-                sq.ox[sslot] = xs.x;
-                sq.oy[sslot] = xs.y;
-                sq.oz[sslot] = xs.z;
-                sq.dx[sslot] = sd.x;
-                sq.dy[sslot] = sd.y;
-                sq.dz[sslot] = sd.z;
-                sq.tmax[sslot] = dist;
-                sq.cr[sslot] = w.x * cr;
-                sq.cg[sslot] = w.y * cg;
-                sq.cb[sslot] = w.z * cb;
-                sq.pix[sslot] = pix;
-                sslot++;
             }
         }
-        // secondary rays
+        uint32_t wave_tot;
+        const uint32_t lane_off = wave_scan(n_sh, wave_tot);
+        const uint32_t wave_base = block_reserve(wave_tot, ctr + kCtrShadow + depth, lds_res);
+        if (light_major) {
+            // light-major: for each light, the wave's emitting lanes take consecutive slots
+            uint32_t run = wave_base;
+            for (int l = 0; l < sc.n_lights; ++l) {   // wave-uniform loop
+                const bool e = (emit_mask >> l) & 1u;
+                const uint64_t bal = __ballot(e);
+                if (e) {
+                    const uint32_t slot = run + __builtin_amdgcn_mbcnt_hi(
+                                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                    const LightTerm lt = light_term(sc.lights[l], x, nf, d, alb, kd, ks, shin);
+                    write_shadow(sq, slot, c.scap, ctr, xs, sc.lights[l], w, lt, pix);
+                }
+                run += (uint32_t)__popcll(bal);
+            }
+        } else if (n_sh) {
+            uint32_t slot = wave_base + lane_off;   // lane-major (more than 32 lights)
+            for (int l = 0; l < sc.n_lights; ++l) {
+                const LightTerm lt = light_term(sc.lights[l], x, nf, d, alb, kd, ks, shin);
+                if (!lt.emit) continue;
+                write_shadow(sq, slot++, c.scap, ctr, xs, sc.lights[l], w, lt, pix);
+            }
+        }
+        // ---- secondary rays
         bool want_r = false, want_t = false;
         float wr_s = 0.0f, wt_s = 0.0f;
         V3 dr = v3(0, 0, 0), dt = v3(0, 0, 0);
-        const float cosi = -dn * (entering ? 1.0f : -1.0f);   // = -d.nf > 0
+        const float cosi = entering ? -dn : dn;   // = -d.nf >= 0
         if (shade && depth < c.max_depth) {
             dr = d + (2.0f * cosi) * nf;
             dr = dr * (1.0f / sqrtf(dot(dr, dr)));
@@ -433,7 +547,9 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
             }
         }
         const uint32_t nsec = (want_r ? 1u : 0u) + (want_t ? 1u : 0u);
-        uint32_t qslot = wave_reserve(nsec, ctr + kCtrRays + depth + 1);
+        uint32_t sec_tot;
+        const uint32_t sec_off = wave_scan(nsec, sec_tot);
+        uint32_t qslot = block_reserve(sec_tot, ctr + kCtrRays + depth + 1, lds_res) + sec_off;
         const uint32_t meta_next = (meta & ~15u) | (uint32_t)(depth + 1);
         if (want_r) {
             if (qslot < c.qcap) {
@@ -486,7 +602,7 @@ __global__ void k_stats(const uint32_t* ctr, rt_stats* st, int max_depth) {
     st->status |= ctr[kCtrStatus];
     st->passes += 1;
     for (int k = 0; k <= max_depth && k < RT_STATS_MAX_DEPTH; ++k) {
-        st->rays[k] += (uint64_t)min(ctr[kCtrRays + k], 0xFFFFFFFFu);
+        st->rays[k] += (uint64_t)ctr[kCtrRays + k] - (k == 0 ? (uint64_t)ctr[kCtrDead] : 0ull);
         st->shadow[k] += (uint64_t)ctr[kCtrShadow + k];
     }
 }
@@ -585,8 +701,12 @@ struct Plan {
     int spp_pass = 1, passes = 1;
     int64_t n_primary = 0;   // rays of a full pass
     uint32_t qcap = 0, scap = 0;
-    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, total = 0;
+    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_stack = 0, total = 0;
 };
+
+// persistent traversal grids are capped at this many threads; each owns a
+// column of the stack overflow region
+constexpr uint32_t kMaxPersistentThreads = 1u << 20;
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -608,12 +728,13 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
         why = "too many pixels";
         return false;
     }
-    const int64_t target = 8 << 20;   // primary rays per pass when chosen automatically
+    const int64_t target = 32 << 20;   // primary rays per pass when chosen automatically
     int spp_pass = p.samples_per_pass > 0 ? std::min(p.samples_per_pass, p.spp)
                                            : (int)std::max<int64_t>(1, std::min<int64_t>(p.spp, target / pl.npix));
     pl.spp_pass = spp_pass;
     pl.passes = (p.spp + spp_pass - 1) / spp_pass;
-    pl.n_primary = pl.npix * spp_pass;
+    // ray slots of a full pass: every 8x8 tile is padded to 64 slots
+    pl.n_primary = (int64_t)((cam.width + 7) / 8) * ((cam.height + 7) / 8) * 64 * spp_pass;
     const double qf = p.queue_factor > 0.0f ? std::max(1.0f, p.queue_factor) : 2.0;
     const double qcap = std::ceil(pl.n_primary * qf);
     const double scap = qcap * std::max(1, s.n_lights);
@@ -641,6 +762,8 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     off = a256(off + 2 * 4 * (size_t)pl.qcap + 2 * 256);
     pl.off_s = off;
     off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
+    pl.off_stack = off;
+    off = a256(off + 4 * (size_t)kMaxPersistentThreads * std::max(0, s.stack_size - kSplitLds));
     pl.total = off;
     return true;
 }
@@ -763,15 +886,17 @@ struct FrameArgs {
     int gx, gs, shade_blocks;   // grid sizes, computed outside any capture
     size_t lds;
     bool time_kernels;
+    uint32_t chunk;             // queue entries per fetch of a persistent traversal wave
 };
 
 static rt_status frame_grids(FrameArgs& A) {
-    A.lds = (size_t)A.sc.stack_size * 64 * 4 * 4;
-    rt_status s1 = A.count_work ? persistent_grid(k_extend<true>, A.lds, A.gx)
-                                : persistent_grid(k_extend<false>, A.lds, A.gx);
+    A.lds = 0;   // the split stack's LDS part is static
+    rt_status s1 = A.count_work ? persistent_grid(k_extend<true>, 0, A.gx) : persistent_grid(k_extend<false>, 0, A.gx);
     if (s1 != RT_OK) return s1;
-    s1 = A.count_work ? persistent_grid(k_shadow<true>, A.lds, A.gs) : persistent_grid(k_shadow<false>, A.lds, A.gs);
+    s1 = A.count_work ? persistent_grid(k_shadow<true>, 0, A.gs) : persistent_grid(k_shadow<false>, 0, A.gs);
     if (s1 != RT_OK) return s1;
+    A.gx = std::min<int>(A.gx, (int)(kMaxPersistentThreads / 256));
+    A.gs = std::min<int>(A.gs, (int)(kMaxPersistentThreads / 256));
     DevInfo di;
     s1 = device_info(di);
     if (s1 != RT_OK) return s1;
@@ -786,6 +911,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
     HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
     ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap);
+    int32_t* overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack);
     const size_t lds = A.lds;
     const int gx = A.gx, gs = A.gs, shade_blocks = A.shade_blocks;
     unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
@@ -798,9 +924,9 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
         const int s0 = pass * pl.spp_pass;
         const int ns = std::min(pl.spp_pass, A.spp - s0);
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
-        const int64_t nthreads = (int64_t)tiles_x * tiles_y * ns * 64;
-        hipLaunchKernelGGL(k_raygen, dim3((unsigned)((nthreads + 255) / 256)), dim3(256), 0, st, A.cam, s0, ns,
-                           tiles_x, nthreads, q[0], ctr, pl.qcap, A.shc.per_sample);
+        const uint32_t nthreads = (uint32_t)((int64_t)tiles_x * tiles_y * ns * 64);
+        hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, s0, ns, tiles_x,
+                           nthreads, q[0], ctr, pl.qcap, A.shc.per_sample);
         for (int k = 0; k <= A.shc.max_depth; ++k) {
             RayQ& qi = q[k & 1];
             RayQ& qo = q[(k + 1) & 1];
@@ -808,10 +934,10 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
             KernelTimer kt(A.time_kernels, st, 0);
             if (A.count_work)
                 hipLaunchKernelGGL(k_extend<true>, dim3(gx), dim3(256), lds, st, A.sc, qi, hq, ctr + kCtrRays + k,
-                                   ctr + kCtrRayCur + k, pl.qcap, work);
+                                   ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             else
                 hipLaunchKernelGGL(k_extend<false>, dim3(gx), dim3(256), lds, st, A.sc, qi, hq, ctr + kCtrRays + k,
-                                   ctr + kCtrRayCur + k, pl.qcap, work);
+                                   ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             }
             {
             KernelTimer kt(A.time_kernels, st, 1);
@@ -822,10 +948,10 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
             KernelTimer kt(A.time_kernels, st, 2);
             if (A.count_work)
                 hipLaunchKernelGGL(k_shadow<true>, dim3(gs), dim3(256), lds, st, A.sc, sq, ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, acc, swork);
+                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow, swork);
             else
                 hipLaunchKernelGGL(k_shadow<false>, dim3(gs), dim3(256), lds, st, A.sc, sq, ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, acc, swork);
+                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow, swork);
             }
         }
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth);
@@ -875,6 +1001,7 @@ static rt_status launch_frame(const FrameArgs& A, hipStream_t st, bool use_graph
     put(key.bytes, A.gx);
     put(key.bytes, A.gs);
     put(key.bytes, A.shade_blocks);
+    put(key.bytes, A.chunk);
     std::lock_guard<std::mutex> g(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
@@ -966,10 +1093,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
         set_error("rt_render: device pointers must be 256-byte aligned");
         return RT_ERR_INVALID_ARG;
     }
-    if ((size_t)h.stack_size * 64 * 4 * 4 > 65536) {
-        set_error("rt_render: BVH too deep for the LDS traversal stack");
-        return RT_ERR_BVH_DEPTH;
-    }
+
     FrameArgs A;
     std::memset(&A, 0, sizeof A);
     A.sc = h.dev_view();
@@ -989,6 +1113,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.count_work = (p.flags & RT_FLAG_COUNT_WORK) != 0;
     A.spp = p.spp;
     A.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
+    A.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
     rt_status rs = frame_grids(A);
     if (rs != RT_OK) return rs;
     hipStream_t st = static_cast<hipStream_t>(p.stream);

@@ -62,7 +62,7 @@ class ParamsC(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("jitter", C.c_int32), ("frame", C.c_uint32),
                 ("seed", C.c_uint64), ("bg", C.c_float * 3), ("eps", C.c_float),
                 ("samples_per_pass", C.c_int32), ("flags", C.c_int32), ("queue_factor", C.c_float),
-                ("reserved", C.c_int32), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("queue_chunk", C.c_int32), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stats", C.c_void_p), ("stream", C.c_void_p)]
 
 
@@ -216,7 +216,7 @@ def camera_c(cam) -> CameraC:
     return c
 
 
-def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0) -> ParamsC:
+def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0, queue_chunk=0) -> ParamsC:
     q = ParamsC()
     q.spp, q.max_depth, q.jitter, q.frame = int(p.spp), int(p.max_depth), int(p.jitter), int(p.frame)
     q.seed = int(p.seed) & (2 ** 64 - 1)
@@ -225,6 +225,7 @@ def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0) -> ParamsC:
     q.samples_per_pass = int(samples_per_pass)
     q.flags = int(flags)
     q.queue_factor = float(queue_factor)
+    q.queue_chunk = int(queue_chunk)
     return q
 
 
@@ -242,7 +243,7 @@ class Renderer:
     """Owns the device workspace, outputs and stats for repeated frames of one scene/camera."""
 
     def __init__(self, scene: Scene, camera, params, device="cuda", with_ids=True, samples_per_pass=0,
-                 queue_factor=0.0, graph=True, per_sample=False):
+                 queue_factor=0.0, graph=True, per_sample=False, queue_chunk=0):
         import torch
         if scene.blob is None:
             scene.upload(device)
@@ -250,6 +251,7 @@ class Renderer:
         self.device = device
         self.samples_per_pass, self.queue_factor, self.graph = samples_per_pass, queue_factor, graph
         self.base_flags = FLAG_PER_SAMPLE if per_sample else 0
+        self.queue_chunk = queue_chunk
         self.cam_c = camera_c(camera)
         self._alloc(with_ids)
 
@@ -272,7 +274,8 @@ class Renderer:
             self.stats.zero_()
         if not self.graph:
             flags |= FLAG_NO_GRAPH
-        p = params_c(self.params, flags | self.base_flags, self.samples_per_pass, self.queue_factor)
+        p = params_c(self.params, flags | self.base_flags, self.samples_per_pass, self.queue_factor,
+                     self.queue_chunk)
         p.workspace, p.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
         p.stats = self.stats.data_ptr()
         p.stream = _stream_ptr(stream)
