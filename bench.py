@@ -66,6 +66,62 @@ def cpu_baseline(w, budget_s: float, seed: int = 5):
                       f"{elapsed:.1f} s, FP64 brute force over every primitive, no BVH)"}
 
 
+def build_scenes(ws, rt, threads=16):
+    import concurrent.futures as cf
+    with cf.ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(lambda w: rt.Scene(w.scene), ws))
+
+
+def bench_batch(args):
+    """256 uneven scenes: one batched wavefront vs 256 sequential single-scene frames."""
+    import torch
+    from paper_1504_03151_amd import rt, scenes
+    t0 = time.perf_counter()
+    ws = scenes.config3(args.n_scenes)
+    log(f"generated {len(ws)} scenes in {time.perf_counter() - t0:.1f} s: "
+        f"{sum(len(w.scene.tris) for w in ws)} triangles, {sum(w.camera.n_pixels for w in ws)} pixels")
+    t0 = time.perf_counter()
+    scs = build_scenes(ws, rt)
+    log(f"built {len(scs)} BVHs in {time.perf_counter() - t0:.1f} s")
+    for sc in scs:
+        sc.upload()
+    br = rt.BatchRenderer(scs, [w.camera for w in ws], [w.params for w in ws], queue_chunk=args.queue_chunk)
+    log(f"batch workspace {br.ws_bytes / 2 ** 30:.2f} GiB")
+    br.render(rt.FLAG_SYNC)
+    st = br.read_stats()
+    assert st["status"] == 0, st
+    rays, shadow = sum(st["rays"]), sum(st["shadow"])
+    for _ in range(args.warmup):
+        br.render()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        br.render()
+    torch.cuda.synchronize()
+    batched_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # sequential baseline: one single-scene frame after another on the same stream (graphs cached)
+    rs = [rt.Renderer(sc, w.camera, w.params, queue_chunk=args.queue_chunk) for sc, w in zip(scs, ws)]
+    for r in rs:
+        r.render()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for r in rs:
+            r.render()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    value = (rays + shadow) / (batched_ms / 1e3) / 1e6
+    log(f"batched {batched_ms:.2f} ms, sequential {seq_ms:.2f} ms ({seq_ms / batched_ms:.2f}x), {value:.0f} Mrays/s")
+    print(json.dumps({
+        "metric": "Mrays/s of one batched frame of 256 uneven scenes", "value": round(value, 2), "unit": "Mrays/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(batched_ms, 3),
+        "sequential_ms": round(seq_ms, 3), "speedup_vs_sequential": round(seq_ms / batched_ms, 3),
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"c3_batch_{len(ws)}_scenes", "rays": rays, "shadow_rays": shadow,
+                   "triangles": sum(len(w.scene.tris) for w in ws),
+                   "pixels": sum(w.camera.n_pixels for w in ws)}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +133,7 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time graph replays (no per-kernel events)")
     ap.add_argument("--samples-per-pass", type=int, default=0, help="0 = chosen by the library")
     ap.add_argument("--queue-chunk", type=int, default=0, help="0 = library default")
+    ap.add_argument("--n-scenes", type=int, default=256, help="scenes of the c3 batch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -99,6 +156,8 @@ def main():
     from paper_1504_03151_amd import rt
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     rt.lib()
+    if args.workload == "c3":
+        return bench_batch(args)
     w = workload(args.workload)
     log(f"workload {w.name}: {len(w.scene.spheres)} spheres, {len(w.scene.tris)} triangles, "
         f"{len(w.scene.planes)} planes, {len(w.scene.lights)} lights")

@@ -47,6 +47,7 @@ struct RayQ {
 struct ShadowQ {
     float *ox, *oy, *oz, *dx, *dy, *dz, *tmax, *cr, *cg, *cb;
     uint32_t* pix;
+    uint32_t* sid;   // scene of each entry (batched frames only)
 };
 struct HitQ {
     float* t;
@@ -76,8 +77,31 @@ struct ShadeConst {
     int max_depth;
     int spp;
     uint32_t qcap, scap;
-    int per_sample;   // accumulation slot = pixel * spp + sample instead of pixel
+    int per_sample;     // accumulation slot = pixel * spp + sample instead of pixel
+    uint32_t acc_off;   // first accumulation slot of the scene
+    int32_t* out_ids;   // [H][W][spp] or NULL
 };
+
+// One scene of a batched frame (device table, one entry per scene).
+struct BatchScene {
+    DevScene sc;
+    ShadeConst shc;
+    CamConst cam;
+    uint32_t ray_off, n_rays;   // primary-ray slots [ray_off, ray_off + n_rays)
+    uint32_t n_acc;             // accumulation slots [shc.acc_off, shc.acc_off + n_acc)
+    int tiles_x;
+    float inv_spp;
+    float* out_rgb;
+};
+
+template <bool BATCH>
+__device__ __forceinline__ const DevScene& scene_of(const DevScene& single, const BatchScene* tab, uint32_t sid) {
+    return BATCH ? tab[sid].sc : single;
+}
+template <bool BATCH>
+__device__ __forceinline__ const ShadeConst& shade_of(const ShadeConst& single, const BatchScene* tab, uint32_t sid) {
+    return BATCH ? tab[sid].shc : single;
+}
 
 // ---------------------------------------------------------------------------
 // wave helpers (wave64)
@@ -200,28 +224,21 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
 // once to FP32.
 constexpr uint32_t kDeadRay = 0xFFFFFFFFu;
 
-__global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, int tiles_x, uint32_t n_threads,
-                                                RayQ q, uint32_t* ctr, uint32_t cap, int per_sample) {
-    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g == 0) {
-        ctr[kCtrRays] = n_threads;
-        if (n_threads > cap) atomicOr(ctr + kCtrStatus, 1u);
-    }
-    if (g >= n_threads || g >= cap) return;
-    const uint32_t lane = threadIdx.x & 63u;
+// Primary ray for slot `slot` = local thread index `g` of a pass over one
+// scene (8x8 tiles, samples s0 .. s0 + ns - 1).  Returns false for a dead
+// padding slot.
+__device__ __forceinline__ bool gen_ray(const CamConst& cam, int s0, int ns, int tiles_x, uint32_t g, int per_sample,
+                                        uint32_t acc_off, uint32_t meta_hi, RayQ q, uint32_t slot) {
+    const uint32_t lane = g & 63u;
     const uint32_t tile_sample = g >> 6;
     const uint32_t tile = tile_sample / (uint32_t)ns;
     const int s = s0 + (int)(tile_sample - tile * (uint32_t)ns);
     const uint32_t ty = tile / (uint32_t)tiles_x;
     const int px = (int)(tile - ty * (uint32_t)tiles_x) * 8 + (int)(lane & 7u);
     const int py = (int)ty * 8 + (int)(lane >> 3);
-    const bool dead = px >= cam.W || py >= cam.H;
-    const uint64_t dead_mask = __ballot(dead);
-    if (dead_mask && lane == (uint32_t)(__ffsll((unsigned long long)dead_mask) - 1))
-        atomicAdd(ctr + kCtrDead, (uint32_t)__popcll(dead_mask));
-    if (dead) {
-        q.pix[g] = kDeadRay;
-        return;
+    if (px >= cam.W || py >= cam.H) {
+        q.pix[slot] = kDeadRay;
+        return false;
     }
     const uint32_t pixel = (uint32_t)py * cam.W + px;
     double jx = 0.5, jy = 0.5, xi0 = 0.5, xi1 = 0.5;
@@ -241,26 +258,66 @@ __global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, in
     double d[3];
     for (int i = 0; i < 3; ++i) d[i] = cam.f[i] + X * cam.r[i] + Y * cam.u[i];
     const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    q.ox[g] = (float)cam.eye[0];
-    q.oy[g] = (float)cam.eye[1];
-    q.oz[g] = (float)cam.eye[2];
-    q.dx[g] = (float)(d[0] * inv);
-    q.dy[g] = (float)(d[1] * inv);
-    q.dz[g] = (float)(d[2] * inv);
-    q.wr[g] = 1.0f;
-    q.wg[g] = 1.0f;
-    q.wb[g] = 1.0f;
-    q.pix[g] = per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel;
-    q.meta[g] = ((uint32_t)s << 4);
+    q.ox[slot] = (float)cam.eye[0];
+    q.oy[slot] = (float)cam.eye[1];
+    q.oz[slot] = (float)cam.eye[2];
+    q.dx[slot] = (float)(d[0] * inv);
+    q.dy[slot] = (float)(d[1] * inv);
+    q.dz[slot] = (float)(d[2] * inv);
+    q.wr[slot] = 1.0f;
+    q.wg[slot] = 1.0f;
+    q.wb[slot] = 1.0f;
+    q.pix[slot] = acc_off + (per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel);
+    q.meta[slot] = meta_hi | ((uint32_t)s << 4);
+    return true;
+}
+
+__device__ __forceinline__ void count_dead(bool dead, uint32_t* ctr) {
+    const uint64_t m = __ballot(dead);
+    if (m && (threadIdx.x & 63u) == (uint32_t)(__ffsll((unsigned long long)m) - 1))
+        atomicAdd(ctr + kCtrDead, (uint32_t)__popcll(m));
+}
+
+__global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, int tiles_x, uint32_t n_threads,
+                                                RayQ q, uint32_t* ctr, uint32_t cap, int per_sample) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) {
+        ctr[kCtrRays] = min(n_threads, cap);
+        if (n_threads > cap) atomicOr(ctr + kCtrStatus, 1u);
+    }
+    if (g >= n_threads || g >= cap) return;
+    count_dead(!gen_ray(cam, s0, ns, tiles_x, g, per_sample, 0u, 0u, q, g), ctr);
+}
+
+// Batched frames: one global slot space over all scenes; each thread finds
+// its scene by binary search over the scenes' first slots.
+__global__ __launch_bounds__(256) void k_raygen_batch(const BatchScene* tab, int n_scenes, uint32_t n_threads,
+                                                      RayQ q, uint32_t* ctr, uint32_t cap) {
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g == 0) {
+        ctr[kCtrRays] = min(n_threads, cap);
+        if (n_threads > cap) atomicOr(ctr + kCtrStatus, 1u);
+    }
+    if (g >= n_threads || g >= cap) return;
+    int lo = 0, hi = n_scenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].ray_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchScene& B = tab[lo];
+    const bool live = gen_ray(B.cam, 0, B.shc.spp, B.tiles_x, g - B.ray_off, B.shc.per_sample, B.shc.acc_off,
+                              (uint32_t)lo << 20, q, g);
+    count_dead(!live, ctr);
 }
 
 // Persistent traversal kernels: each wave takes `chunk` consecutive queue
 // entries per atomic on the fetch cursor (a multiple of 64) and traces them 64
 // at a time until the queue is drained.
-template <bool COUNT>
-__global__ __launch_bounds__(256) void k_extend(DevScene sc, RayQ q, HitQ hit, const uint32_t* count_p,
-                                                uint32_t* cursor, uint32_t cap, uint32_t chunk, int32_t* overflow,
-                                                unsigned long long* work_out) {
+template <bool COUNT, bool BATCH>
+__global__ __launch_bounds__(256) void k_extend(DevScene sc, const BatchScene* tab, RayQ q, HitQ hit,
+                                                const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
+                                                uint32_t chunk, int32_t* overflow, unsigned long long* work_out) {
     __shared__ int32_t smem[4 * kSplitLds * 64];
     SplitStack stk = split_stack(smem, overflow);
     const uint32_t count = min(*count_p, cap);   // a producer that overflowed still bumped the tail
@@ -278,8 +335,9 @@ __global__ __launch_bounds__(256) void k_extend(DevScene sc, RayQ q, HitQ hit, c
                     hit.prim[i] = -1;
                     continue;
                 }
+                const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? (q.meta[i] >> 20) : 0u);
                 const TRay r = make_tray(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
-                const Hit h = traverse<false, COUNT>(sc, r, INFINITY, stk, w);
+                const Hit h = traverse<false, COUNT>(S, r, INFINITY, stk, w);
                 hit.t[i] = h.t;
                 hit.prim[i] = h.prim;
             }
@@ -290,9 +348,10 @@ __global__ __launch_bounds__(256) void k_extend(DevScene sc, RayQ q, HitQ hit, c
 
 // Any-hit over the shadow queue; adds the contribution of each unblocked light
 // to its pixel.
-template <bool COUNT>
-__global__ __launch_bounds__(256) void k_shadow(DevScene sc, ShadowQ s, const uint32_t* count_p, uint32_t* cursor,
-                                                uint32_t cap, uint32_t chunk, float* acc, int32_t* overflow,
+template <bool COUNT, bool BATCH>
+__global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* tab, ShadowQ s,
+                                                const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
+                                                uint32_t chunk, float* acc, int32_t* overflow,
                                                 unsigned long long* work_out) {
     __shared__ int32_t smem[4 * kSplitLds * 64];
     SplitStack stk = split_stack(smem, overflow);
@@ -307,8 +366,9 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, ShadowQ s, const ui
         for (uint32_t b = base; b < end; b += 64) {
             const uint32_t i = b + lane_id();
             if (i < end) {
+                const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? s.sid[i] : 0u);
                 const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
-                const Hit h = traverse<true, COUNT>(sc, r, s.tmax[i], stk, w);
+                const Hit h = traverse<true, COUNT>(S, r, s.tmax[i], stk, w);
                 if (h.prim < 0) {
                     const uint32_t p = s.pix[i];
                     atomicAdd(acc + 3 * p + 0, s.cr[i]);
@@ -382,7 +442,8 @@ __device__ __forceinline__ LightTerm light_term(const DevLight& L, V3 x, V3 nf, 
 }
 
 __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, uint32_t cap, uint32_t* ctr, V3 xs,
-                                             const DevLight& L, V3 w, const LightTerm& lt, uint32_t pix) {
+                                             const DevLight& L, V3 w, const LightTerm& lt, uint32_t pix,
+                                             uint32_t sid) {
     if (slot >= cap) {
         atomicOr(ctr + kCtrStatus, 2u);
         return;
@@ -401,6 +462,7 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
     sq.cg[slot] = w.y * lt.cg;
     sq.cb[slot] = w.z * lt.cb;
     sq.pix[slot] = pix;
+    if (sq.sid) sq.sid[slot] = sid;
 }
 
 // Shading of one depth: Phong local terms (ambient now, light terms deferred to
@@ -408,12 +470,14 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
 // slots are reserved with one atomic per block and queue; shadow rays are laid
 // out light-major inside each wave (consecutive entries go to the same light)
 // so the shadow kernel's waves traverse coherently.
-__global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ qin, HitQ hit, uint32_t* ctr, int depth,
-                                               RayQ qout, ShadowQ sq, float* acc, int32_t* out_ids) {
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const BatchScene* tab, RayQ qin, HitQ hit,
+                                               uint32_t* ctr, int depth, RayQ qout, ShadowQ sq, float* acc) {
     __shared__ uint32_t lds_res[4];
-    const uint32_t count = min(ctr[kCtrRays + depth], c.qcap);
+    const uint32_t qcap = c0.qcap, scap = c0.scap;
+    const uint32_t count = min(ctr[kCtrRays + depth], qcap);
     const uint32_t stride = gridDim.x * blockDim.x;
-    const bool light_major = sc.n_lights <= 32;
+    const bool light_major = !BATCH && sc.n_lights <= 32;
     for (uint32_t bb = blockIdx.x * blockDim.x; bb < count; bb += stride) {   // block-uniform loop
         const uint32_t i = bb + threadIdx.x;
         bool active = i < count;
@@ -432,48 +496,52 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
             o = v3(qin.ox[i], qin.oy[i], qin.oz[i]);
             d = v3(qin.dx[i], qin.dy[i], qin.dz[i]);
             w = v3(qin.wr[i], qin.wg[i], qin.wb[i]);
-            if (depth == 0 && out_ids) {
-                int oid = -1;
-                if (prim >= sc.n_bvh) oid = prim;
-                else if (prim >= 0) oid = as_int_f(sc.prims[3 * prim].w);
-                out_ids[c.per_sample ? (size_t)pix : (size_t)pix * c.spp + ((meta >> 4) & 0xFFFFu)] = oid;
-            }
+        }
+        const uint32_t sid = BATCH ? (meta >> 20) : 0u;
+        const DevScene& S = scene_of<BATCH>(sc, tab, sid);
+        const ShadeConst& C = shade_of<BATCH>(c0, tab, sid);
+        if (active && depth == 0 && C.out_ids) {
+            int oid = -1;
+            if (prim >= S.n_bvh) oid = prim;
+            else if (prim >= 0) oid = as_int_f(S.prims[3 * prim].w);
+            const uint32_t local = pix - C.acc_off;
+            C.out_ids[C.per_sample ? (size_t)local : (size_t)local * C.spp + ((meta >> 4) & 0xFFFFu)] = oid;
         }
         const bool shade = active && prim >= 0;
         if (active && prim < 0) {
-            atomicAdd(acc + 3 * pix + 0, w.x * c.bg[0]);
-            atomicAdd(acc + 3 * pix + 1, w.y * c.bg[1]);
-            atomicAdd(acc + 3 * pix + 2, w.z * c.bg[2]);
+            atomicAdd(acc + 3 * pix + 0, w.x * C.bg[0]);
+            atomicAdd(acc + 3 * pix + 1, w.y * C.bg[1]);
+            atomicAdd(acc + 3 * pix + 2, w.z * C.bg[2]);
         }
         // hit point, geometric normal, material
         V3 x = v3(0, 0, 0), ng = v3(0, 0, 1);
         int mat = 0;
         if (shade) {
             x = v3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
-            if (prim >= sc.n_bvh) {
-                const float4 pl = sc.planes[prim - sc.n_bvh];
+            if (prim >= S.n_bvh) {
+                const float4 pl = S.planes[prim - S.n_bvh];
                 ng = xyz(pl);
-                mat = sc.plane_mat[prim - sc.n_bvh];
+                mat = S.plane_mat[prim - S.n_bvh];
             } else {
-                const float4 p0 = sc.prims[3 * prim];
-                const float4 p1 = sc.prims[3 * prim + 1];
+                const float4 p0 = S.prims[3 * prim];
+                const float4 p1 = S.prims[3 * prim + 1];
                 mat = as_int_f(p1.w);
-                if (as_int_f(p0.w) < sc.n_spheres) {
+                if (as_int_f(p0.w) < S.n_spheres) {
                     ng = (x - xyz(p0)) * p1.z;
                     ng = ng * (1.0f / sqrtf(dot(ng, ng)));
                 } else {
-                    ng = xyz(sc.normals[prim]);
+                    ng = xyz(S.normals[prim]);
                 }
             }
         }
         const float dn = dot(d, ng);
         const bool entering = dn < 0.0f;
         const V3 nf = entering ? ng : -ng;
-        const DevMaterial M = sc.mats[mat];
+        const DevMaterial M = S.mats[mat];
         const V3 alb = xyz(M.a);
         const float ka = M.a.w, kd = M.b.x, ks = M.b.y, shin = M.b.z, kr = M.b.w, ior = M.c.x;
         const int type = (int)M.c.y;
-        const float eps_s = c.eps * fmaxf(1.0f, maxabs(x));
+        const float eps_s = C.eps * fmaxf(1.0f, maxabs(x));
         const V3 xs = x + eps_s * nf;
         if (shade && ka > 0.0f) {
             atomicAdd(acc + 3 * pix + 0, w.x * ka * alb.x);
@@ -483,8 +551,8 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
         // ---- shadow rays: decide per light, reserve, then write
         uint32_t emit_mask = 0, n_sh = 0;
         if (shade) {
-            for (int l = 0; l < sc.n_lights; ++l) {
-                const LightTerm lt = light_term(sc.lights[l], x, nf, d, alb, kd, ks, shin);
+            for (int l = 0; l < S.n_lights; ++l) {
+                const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
                 if (lt.emit) {
                     n_sh++;
                     if (l < 32) emit_mask |= 1u << l;
@@ -497,23 +565,23 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
         if (light_major) {
             // light-major: for each light, the wave's emitting lanes take consecutive slots
             uint32_t run = wave_base;
-            for (int l = 0; l < sc.n_lights; ++l) {   // wave-uniform loop
+            for (int l = 0; l < S.n_lights; ++l) {   // wave-uniform loop
                 const bool e = (emit_mask >> l) & 1u;
                 const uint64_t bal = __ballot(e);
                 if (e) {
                     const uint32_t slot = run + __builtin_amdgcn_mbcnt_hi(
                                                     (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    const LightTerm lt = light_term(sc.lights[l], x, nf, d, alb, kd, ks, shin);
-                    write_shadow(sq, slot, c.scap, ctr, xs, sc.lights[l], w, lt, pix);
+                    const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
+                    write_shadow(sq, slot, scap, ctr, xs, S.lights[l], w, lt, pix, sid);
                 }
                 run += (uint32_t)__popcll(bal);
             }
         } else if (n_sh) {
             uint32_t slot = wave_base + lane_off;   // lane-major (more than 32 lights)
-            for (int l = 0; l < sc.n_lights; ++l) {
-                const LightTerm lt = light_term(sc.lights[l], x, nf, d, alb, kd, ks, shin);
+            for (int l = 0; l < S.n_lights; ++l) {
+                const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
                 if (!lt.emit) continue;
-                write_shadow(sq, slot++, c.scap, ctr, xs, sc.lights[l], w, lt, pix);
+                write_shadow(sq, slot++, scap, ctr, xs, S.lights[l], w, lt, pix, sid);
             }
         }
         // ---- secondary rays
@@ -521,7 +589,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
         float wr_s = 0.0f, wt_s = 0.0f;
         V3 dr = v3(0, 0, 0), dt = v3(0, 0, 0);
         const float cosi = entering ? -dn : dn;   // = -d.nf >= 0
-        if (shade && depth < c.max_depth) {
+        if (shade && depth < C.max_depth) {
             dr = d + (2.0f * cosi) * nf;
             dr = dr * (1.0f / sqrtf(dot(dr, dr)));
             if (type == RT_MAT_DIELECTRIC) {
@@ -552,7 +620,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
         uint32_t qslot = block_reserve(sec_tot, ctr + kCtrRays + depth + 1, lds_res) + sec_off;
         const uint32_t meta_next = (meta & ~15u) | (uint32_t)(depth + 1);
         if (want_r) {
-            if (qslot < c.qcap) {
+            if (qslot < qcap) {
                 qout.ox[qslot] = xs.x;
                 qout.oy[qslot] = xs.y;
                 qout.oz[qslot] = xs.z;
@@ -570,7 +638,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
             qslot++;
         }
         if (want_t) {
-            if (qslot < c.qcap) {
+            if (qslot < qcap) {
                 const V3 xt = x - eps_s * nf;
                 qout.ox[qslot] = xt.x;
                 qout.oy[qslot] = xt.y;
@@ -588,6 +656,21 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c, RayQ q
             }
         }
     }
+}
+
+// Batched resolve: each accumulation float goes to its scene's output.
+__global__ void k_resolve_batch(const BatchScene* tab, int n_scenes, const float* acc, uint64_t n3) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    const uint32_t slot = (uint32_t)(i / 3);
+    int lo = 0, hi = n_scenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].shc.acc_off <= slot) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchScene& B = tab[lo];
+    B.out_rgb[(size_t)(slot - B.shc.acc_off) * 3 + (i - (uint64_t)slot * 3)] = acc[i] * B.inv_spp;
 }
 
 __global__ void k_resolve(const float* acc, float* out, int64_t n3, float inv_spp) {
@@ -777,12 +860,14 @@ static RayQ ray_queue(uint8_t* base, uint32_t cap) {
     return q;
 }
 
-static ShadowQ shadow_queue(uint8_t* base, uint32_t cap) {
+// 11 arrays (12 with the scene ids of a batched frame)
+static ShadowQ shadow_queue(uint8_t* base, uint32_t cap, bool with_sid) {
     const size_t stride = a256(4 * (size_t)cap);
     float* f[10];
     for (int k = 0; k < 10; ++k) f[k] = reinterpret_cast<float*>(base + k * stride);
     ShadowQ s{f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], f[9],
-              reinterpret_cast<uint32_t*>(base + 10 * stride)};
+              reinterpret_cast<uint32_t*>(base + 10 * stride),
+              with_sid ? reinterpret_cast<uint32_t*>(base + 11 * stride) : nullptr};
     return s;
 }
 
@@ -891,9 +976,11 @@ struct FrameArgs {
 
 static rt_status frame_grids(FrameArgs& A) {
     A.lds = 0;   // the split stack's LDS part is static
-    rt_status s1 = A.count_work ? persistent_grid(k_extend<true>, 0, A.gx) : persistent_grid(k_extend<false>, 0, A.gx);
+    rt_status s1 = A.count_work ? persistent_grid(k_extend<true, false>, 0, A.gx)
+                                : persistent_grid(k_extend<false, false>, 0, A.gx);
     if (s1 != RT_OK) return s1;
-    s1 = A.count_work ? persistent_grid(k_shadow<true>, 0, A.gs) : persistent_grid(k_shadow<false>, 0, A.gs);
+    s1 = A.count_work ? persistent_grid(k_shadow<true, false>, 0, A.gs)
+                      : persistent_grid(k_shadow<false, false>, 0, A.gs);
     if (s1 != RT_OK) return s1;
     A.gx = std::min<int>(A.gx, (int)(kMaxPersistentThreads / 256));
     A.gs = std::min<int>(A.gs, (int)(kMaxPersistentThreads / 256));
@@ -910,7 +997,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     float* acc = reinterpret_cast<float*>(A.ws + pl.off_acc);
     RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
     HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
-    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap);
+    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap, false);
     int32_t* overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack);
     const size_t lds = A.lds;
     const int gx = A.gx, gs = A.gs, shade_blocks = A.shade_blocks;
@@ -933,24 +1020,28 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
             {
             KernelTimer kt(A.time_kernels, st, 0);
             if (A.count_work)
-                hipLaunchKernelGGL(k_extend<true>, dim3(gx), dim3(256), lds, st, A.sc, qi, hq, ctr + kCtrRays + k,
+                hipLaunchKernelGGL((k_extend<true, false>), dim3(gx), dim3(256), lds, st, A.sc, nullptr, qi, hq,
+                                   ctr + kCtrRays + k,
                                    ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             else
-                hipLaunchKernelGGL(k_extend<false>, dim3(gx), dim3(256), lds, st, A.sc, qi, hq, ctr + kCtrRays + k,
+                hipLaunchKernelGGL((k_extend<false, false>), dim3(gx), dim3(256), lds, st, A.sc, nullptr, qi, hq,
+                                   ctr + kCtrRays + k,
                                    ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             }
             {
             KernelTimer kt(A.time_kernels, st, 1);
-            hipLaunchKernelGGL(k_shade, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, qi, hq, ctr, k, qo, sq,
-                               acc, A.out_ids);
+            hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr, qi, hq,
+                               ctr, k, qo, sq, acc);
             }
             {
             KernelTimer kt(A.time_kernels, st, 2);
             if (A.count_work)
-                hipLaunchKernelGGL(k_shadow<true>, dim3(gs), dim3(256), lds, st, A.sc, sq, ctr + kCtrShadow + k,
+                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sq,
+                                   ctr + kCtrShadow + k,
                                    ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow, swork);
             else
-                hipLaunchKernelGGL(k_shadow<false>, dim3(gs), dim3(256), lds, st, A.sc, sq, ctr + kCtrShadow + k,
+                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sq,
+                                   ctr + kCtrShadow + k,
                                    ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow, swork);
             }
         }
@@ -1031,6 +1122,259 @@ static rt_status launch_frame(const FrameArgs& A, hipStream_t st, bool use_graph
     return RT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batched frames: many scenes in one wavefront
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+    int n = 0;
+    uint32_t n_rays = 0;        // primary slots of all scenes (every sample in one pass)
+    uint64_t n_acc = 0;
+    uint32_t qcap = 0, scap = 0;
+    int dmax = 0, stack_max = 0;
+    size_t off_tab = 0, off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_stack = 0, total = 0;
+};
+
+static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params, int32_t n,
+                            float* const* out_rgb, int32_t* const* out_ids, BatchPlan& bp,
+                            std::vector<BatchScene>* table, std::string& why) {
+    std::memset(&bp, 0, sizeof bp);
+    if (!scenes || !cams || !params || n <= 0 || n > 4096) {
+        why = "need 1..4096 scenes and non-NULL scenes, cams, params";
+        return false;
+    }
+    const rt_params& p0 = params[0];
+    const bool per_sample = (p0.flags & RT_FLAG_PER_SAMPLE) != 0;
+    uint64_t rays = 0, acc = 0;
+    int max_lights = 1;
+    if (table) table->resize(n);
+    for (int i = 0; i < n; ++i) {
+        const rt_scene* sc = scenes[i];
+        const rt_camera& cam = cams[i];
+        const rt_params& p = params[i];
+        if (!sc) {
+            why = "scene " + std::to_string(i) + " is NULL";
+            return false;
+        }
+        if (cam.width <= 0 || cam.height <= 0 || p.spp < 1 || p.spp > 65535 || p.max_depth < 0 ||
+            p.max_depth > RT_STATS_MAX_DEPTH - 2 || !(cam.vfov_deg > 0.0f && cam.vfov_deg < 180.0f) ||
+            !std::isfinite(p.eps) || p.eps < 0.0f) {
+            why = "invalid camera or parameters of scene " + std::to_string(i);
+            return false;
+        }
+        const SceneHost& h = sc->h;
+        const int tiles_x = (cam.width + 7) / 8, tiles_y = (cam.height + 7) / 8;
+        const uint64_t nr = (uint64_t)tiles_x * tiles_y * 64 * p.spp;
+        const uint64_t npix = (uint64_t)cam.width * cam.height;
+        const uint64_t na = per_sample ? npix * p.spp : npix;
+        if (table) {
+            if (!h.dev) {
+                why = "scene " + std::to_string(i) + " is not uploaded";
+                return false;
+            }
+            if (!out_rgb[i]) {
+                why = "out_rgb[" + std::to_string(i) + "] is NULL";
+                return false;
+            }
+            BatchScene& B = (*table)[i];
+            std::memset(&B, 0, sizeof B);
+            B.sc = h.dev_view();
+            for (int c = 0; c < 3; ++c) B.shc.bg[c] = p.bg[c];
+            B.shc.eps = p.eps;
+            B.shc.max_depth = p.max_depth;
+            B.shc.spp = p.spp;
+            B.shc.per_sample = per_sample ? 1 : 0;
+            B.shc.acc_off = (uint32_t)acc;
+            B.shc.out_ids = out_ids ? out_ids[i] : nullptr;
+            camera_consts(cam, p, B.cam);
+            B.ray_off = (uint32_t)rays;
+            B.n_rays = (uint32_t)nr;
+            B.n_acc = (uint32_t)na;
+            B.tiles_x = tiles_x;
+            B.inv_spp = per_sample ? 1.0f : 1.0f / (float)p.spp;
+            B.out_rgb = out_rgb[i];
+        }
+        rays += nr;
+        acc += na;
+        bp.dmax = std::max(bp.dmax, p.max_depth);
+        bp.stack_max = std::max(bp.stack_max, h.stack_size);
+        max_lights = std::max(max_lights, h.n_lights);
+    }
+    const double qf = p0.queue_factor > 0.0f ? std::max(1.0f, p0.queue_factor) : 2.0;
+    const double qcap = std::ceil((double)rays * qf), scap = qcap * max_lights;
+    if (rays >= (1ull << 32) || acc >= (1ull << 32) || qcap > 4.0e9 || scap > 4.0e9) {
+        why = "batch too large for one wavefront (more than 2^32 rays or queue entries)";
+        return false;
+    }
+    bp.n = n;
+    bp.n_rays = (uint32_t)rays;
+    bp.n_acc = acc;
+    bp.qcap = (uint32_t)qcap;
+    bp.scap = (uint32_t)scap;
+    size_t off = 0;
+    bp.off_tab = off;
+    off = a256(off + sizeof(BatchScene) * n);
+    bp.off_ctr = off;
+    off = a256(off + 4 * kCtrWords);
+    bp.off_acc = off;
+    off = a256(off + 12 * (size_t)acc);
+    for (int b = 0; b < 2; ++b) {
+        bp.off_q[b] = off;
+        off = a256(off + 11 * (a256(4 * (size_t)bp.qcap)));
+    }
+    bp.off_hit = off;
+    off = a256(off + 2 * a256(4 * (size_t)bp.qcap));
+    bp.off_s = off;
+    off = a256(off + 12 * a256(4 * (size_t)bp.scap));
+    bp.off_stack = off;
+    off = a256(off + 4 * (size_t)kMaxPersistentThreads * std::max(0, bp.stack_max - kSplitLds));
+    bp.total = off;
+    return true;
+}
+
+struct BatchArgs {
+    BatchPlan pl;
+    uint8_t* ws;
+    rt_stats* stats;
+    bool count_work, time_kernels;
+    uint32_t chunk;
+    int gx, gs, shade_blocks;
+};
+
+static rt_status batch_grids(BatchArgs& B) {
+    rt_status s1 = B.count_work ? persistent_grid(k_extend<true, true>, 0, B.gx)
+                                : persistent_grid(k_extend<false, true>, 0, B.gx);
+    if (s1 != RT_OK) return s1;
+    s1 = B.count_work ? persistent_grid(k_shadow<true, true>, 0, B.gs) : persistent_grid(k_shadow<false, true>, 0, B.gs);
+    if (s1 != RT_OK) return s1;
+    B.gx = std::min<int>(B.gx, (int)(kMaxPersistentThreads / 256));
+    B.gs = std::min<int>(B.gs, (int)(kMaxPersistentThreads / 256));
+    DevInfo di;
+    s1 = device_info(di);
+    if (s1 != RT_OK) return s1;
+    B.shade_blocks = (int)std::max<int64_t>(1, std::min<int64_t>((B.pl.qcap + 255) / 256, (int64_t)di.cus * 16));
+    return RT_OK;
+}
+
+// The scene table goes through a pinned staging buffer; the previous upload
+// must have completed before the buffer is rewritten.
+static std::mutex g_stage_mu;
+static void* g_stage = nullptr;
+static size_t g_stage_bytes = 0;
+static hipEvent_t g_stage_done = nullptr;
+
+static rt_status upload_table(const std::vector<BatchScene>& table, uint8_t* dst, hipStream_t st) {
+    std::lock_guard<std::mutex> g(g_stage_mu);
+    const size_t bytes = sizeof(BatchScene) * table.size();
+    if (g_stage_done) HIP_TRY(hipEventSynchronize(g_stage_done));
+    else HIP_TRY(hipEventCreateWithFlags(&g_stage_done, hipEventDisableTiming));
+    if (g_stage_bytes < bytes) {
+        if (g_stage) HIP_TRY(hipHostFree(g_stage));
+        g_stage = nullptr;
+        g_stage_bytes = 0;
+        HIP_TRY(hipHostMalloc(&g_stage, bytes, hipHostMallocDefault));
+        g_stage_bytes = bytes;
+    }
+    std::memcpy(g_stage, table.data(), bytes);
+    HIP_TRY(hipMemcpyAsync(dst, g_stage, bytes, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(g_stage_done, st));
+    return RT_OK;
+}
+
+static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
+    const BatchPlan& pl = B.pl;
+    const BatchScene* tab = reinterpret_cast<const BatchScene*>(B.ws + pl.off_tab);
+    uint32_t* ctr = reinterpret_cast<uint32_t*>(B.ws + pl.off_ctr);
+    float* acc = reinterpret_cast<float*>(B.ws + pl.off_acc);
+    RayQ q[2] = {ray_queue(B.ws + pl.off_q[0], pl.qcap), ray_queue(B.ws + pl.off_q[1], pl.qcap)};
+    HitQ hq = hit_queue(B.ws + pl.off_hit, pl.qcap);
+    ShadowQ sq = shadow_queue(B.ws + pl.off_s, pl.scap, true);
+    int32_t* overflow = reinterpret_cast<int32_t*>(B.ws + pl.off_stack);
+    unsigned long long* work = B.stats ? reinterpret_cast<unsigned long long*>(&B.stats->node_visits) : nullptr;
+    unsigned long long* swork = B.stats ? reinterpret_cast<unsigned long long*>(&B.stats->shadow_node_visits) : nullptr;
+    DevScene none;
+    std::memset(&none, 0, sizeof none);
+    ShadeConst c0;
+    std::memset(&c0, 0, sizeof c0);
+    c0.qcap = pl.qcap;
+    c0.scap = pl.scap;
+    const uint64_t n3 = 3 * pl.n_acc;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, (int64_t)n3, 0.0f);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+    hipLaunchKernelGGL(k_raygen_batch, dim3((pl.n_rays + 255) / 256), dim3(256), 0, st, tab, pl.n, pl.n_rays, q[0], ctr,
+                       pl.qcap);
+    for (int k = 0; k <= pl.dmax; ++k) {
+        RayQ& qi = q[k & 1];
+        RayQ& qo = q[(k + 1) & 1];
+        {
+            KernelTimer kt(B.time_kernels, st, 0);
+            if (B.count_work)
+                hipLaunchKernelGGL((k_extend<true, true>), dim3(B.gx), dim3(256), 0, st, none, tab, qi, hq,
+                                   ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, B.chunk, overflow, work);
+            else
+                hipLaunchKernelGGL((k_extend<false, true>), dim3(B.gx), dim3(256), 0, st, none, tab, qi, hq,
+                                   ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, B.chunk, overflow, work);
+        }
+        {
+            KernelTimer kt(B.time_kernels, st, 1);
+            hipLaunchKernelGGL(k_shade<true>, dim3(B.shade_blocks), dim3(256), 0, st, none, c0, tab, qi, hq, ctr, k,
+                               qo, sq, acc);
+        }
+        {
+            KernelTimer kt(B.time_kernels, st, 2);
+            if (B.count_work)
+                hipLaunchKernelGGL((k_shadow<true, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
+                                   ctr + kCtrShadow + k, ctr + kCtrShadowCur + k, pl.scap, B.chunk, acc, overflow,
+                                   swork);
+            else
+                hipLaunchKernelGGL((k_shadow<false, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
+                                   ctr + kCtrShadow + k, ctr + kCtrShadowCur + k, pl.scap, B.chunk, acc, overflow,
+                                   swork);
+        }
+    }
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, B.stats, pl.dmax);
+    hipLaunchKernelGGL(k_resolve_batch, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, tab, pl.n, acc, n3);
+    HIP_TRY(hipGetLastError());
+    return RT_OK;
+}
+
+static rt_status launch_batch(const BatchArgs& B, hipStream_t st, bool use_graph) {
+    if (!use_graph) return enqueue_batch(B, st);
+    GraphKey key;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const uint32_t tag = 0xBA7C4u;
+    put(key.bytes, tag);
+    put(key.bytes, dev);
+    put(key.bytes, B.pl);
+    put(key.bytes, B.ws);
+    put(key.bytes, B.stats);
+    put(key.bytes, B.count_work);
+    put(key.bytes, B.chunk);
+    put(key.bytes, B.gx);
+    put(key.bytes, B.gs);
+    put(key.bytes, B.shade_blocks);
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        GraphEntry e;
+        HIP_TRY(hipStreamCreateWithFlags(&e.cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(e.cap_stream, hipStreamCaptureModeThreadLocal));
+        rt_status rs = enqueue_batch(B, e.cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(e.cap_stream, &graph);
+        if (rs != RT_OK) return rs;
+        if (ee != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+            return RT_ERR_HIP;
+        }
+        HIP_TRY(hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphDestroy(graph));
+        it = g_graphs.emplace(key, e).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.exec, st));
+    return RT_OK;
+}
+
 }  // namespace mirt
 
 using namespace mirt;
@@ -1105,6 +1449,8 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.shc.qcap = pl.qcap;
     A.shc.scap = pl.scap;
     A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
+    A.shc.acc_off = 0;
+    A.shc.out_ids = out_hit_ids;
     A.pl = pl;
     A.ws = static_cast<uint8_t*>(p.workspace);
     A.stats = static_cast<rt_stats*>(p.stats);
@@ -1202,24 +1548,67 @@ rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset) {
 
 size_t rt_render_batch_workspace_bytes(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params,
                                        int32_t n) {
-    (void)scenes;
-    (void)cams;
-    (void)params;
-    (void)n;
-    set_error("rt_render_batch_workspace_bytes: batched rendering is not built yet");
-    return 0;
+    BatchPlan bp;
+    std::string why;
+    if (!make_batch_plan(scenes, cams, params, n, nullptr, nullptr, bp, nullptr, why)) {
+        set_error("rt_render_batch_workspace_bytes: " + why);
+        return 0;
+    }
+    return bp.total;
 }
 
 rt_status rt_render_batch(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params, int32_t n,
                           float* const* out_rgb, int32_t* const* out_hit_ids) {
-    (void)scenes;
-    (void)cams;
-    (void)params;
-    (void)n;
-    (void)out_rgb;
-    (void)out_hit_ids;
-    set_error("rt_render_batch: batched rendering is not built yet");
-    return RT_ERR_UNSUPPORTED;
+    if (!out_rgb) {
+        set_error("rt_render_batch: NULL out_rgb");
+        return RT_ERR_INVALID_ARG;
+    }
+    BatchPlan bp;
+    std::string why;
+    std::vector<BatchScene> table;
+    if (!make_batch_plan(scenes, cams, params, n, out_rgb, out_hit_ids, bp, &table, why)) {
+        set_error("rt_render_batch: " + why);
+        return RT_ERR_INVALID_ARG;
+    }
+    const rt_params& p = params[0];
+    if (!p.workspace || p.workspace_bytes < bp.total) {
+        set_error("rt_render_batch: workspace missing or smaller than rt_render_batch_workspace_bytes (" +
+                  std::to_string(bp.total) + ")");
+        return RT_ERR_CAPACITY;
+    }
+    if (reinterpret_cast<uintptr_t>(p.workspace) & 255) {
+        set_error("rt_render_batch: workspace must be 256-byte aligned");
+        return RT_ERR_INVALID_ARG;
+    }
+    BatchArgs B;
+    std::memset(&B, 0, sizeof B);
+    B.pl = bp;
+    B.ws = static_cast<uint8_t*>(p.workspace);
+    B.stats = static_cast<rt_stats*>(p.stats);
+    B.count_work = (p.flags & RT_FLAG_COUNT_WORK) != 0;
+    B.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
+    B.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
+    rt_status rs = batch_grids(B);
+    if (rs != RT_OK) return rs;
+    hipStream_t st = static_cast<hipStream_t>(p.stream);
+    rs = upload_table(table, B.ws + bp.off_tab, st);
+    if (rs != RT_OK) return rs;
+    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
+    rs = launch_batch(B, st, graph);
+    if (rs != RT_OK) return rs;
+    if (p.flags & RT_FLAG_SYNC) {
+        HIP_TRY(hipStreamSynchronize(st));
+        if (B.stats) {
+            uint32_t status = 0;
+            HIP_TRY(hipMemcpy(&status, &B.stats->status, 4, hipMemcpyDeviceToHost));
+            if (status) {
+                set_error("rt_render_batch: ray queue overflow (status " + std::to_string(status) +
+                          "); raise queue_factor");
+                return RT_ERR_CAPACITY;
+            }
+        }
+    }
+    return RT_OK;
 }
 
 }  // extern "C"

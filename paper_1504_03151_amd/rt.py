@@ -287,6 +287,57 @@ class Renderer:
         return stats_dict(self.stats)
 
 
+class BatchRenderer:
+    """Many scenes in one batched wavefront (rt_render_batch): one queue, one graph."""
+
+    def __init__(self, scenes: Sequence[Scene], cameras, params, device="cuda", with_ids=True, queue_factor=0.0,
+                 queue_chunk=0, graph=True, per_sample=False):
+        import torch
+        n = len(scenes)
+        assert n == len(cameras) == len(params) and n > 0
+        for s in scenes:
+            if s.blob is None:
+                s.upload(device)
+        self.scenes, self.cameras, self.params = list(scenes), list(cameras), list(params)
+        self.device, self.graph = device, graph
+        self.base_flags = FLAG_PER_SAMPLE if per_sample else 0
+        self.queue_factor, self.queue_chunk = queue_factor, queue_chunk
+        self._h = (C.c_void_p * n)(*[s.handle.value for s in scenes])
+        self._cams = (CameraC * n)(*[camera_c(c) for c in cameras])
+        self._params = (ParamsC * n)(*[params_c(p, self.base_flags, 0, queue_factor, queue_chunk) for p in params])
+        nb = lib().rt_render_batch_workspace_bytes(self._h, self._cams, self._params, n)
+        if nb == 0:
+            raise RTError(-1, "rt_render_batch_workspace_bytes", lib().rt_last_error().decode())
+        self.ws_bytes = int(nb)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.rgb, self.ids = [], []
+        for c, p in zip(cameras, params):
+            shape = (c.height, c.width, p.spp, 3) if per_sample else (c.height, c.width, 3)
+            self.rgb.append(torch.empty(shape, dtype=torch.float32, device=device))
+            self.ids.append(torch.empty((c.height, c.width, p.spp), dtype=torch.int32, device=device)
+                            if with_ids else None)
+        self._rgb_p = (C.c_void_p * n)(*[t.data_ptr() for t in self.rgb])
+        self._ids_p = (C.c_void_p * n)(*[(t.data_ptr() if t is not None else None) for t in self.ids])
+        self.stats = torch.zeros(C.sizeof(Stats) + 64, dtype=torch.uint8, device=device)
+
+    def render(self, flags=0, stream=None, reset_stats=True):
+        if reset_stats:
+            self.stats.zero_()
+        if not self.graph:
+            flags |= FLAG_NO_GRAPH
+        p0 = self._params[0]
+        p0.flags = flags | self.base_flags
+        p0.workspace, p0.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
+        p0.stats = self.stats.data_ptr()
+        p0.stream = _stream_ptr(stream)
+        _check(lib().rt_render_batch(self._h, self._cams, self._params, len(self.scenes), self._rgb_p, self._ids_p),
+               "rt_render_batch")
+        return self.rgb, self.ids
+
+    def read_stats(self) -> dict:
+        return stats_dict(self.stats)
+
+
 def render(scene: Scene, camera, params, flags=FLAG_SYNC, **kw):
     """One frame: returns (rgb [H,W,3] f32, ids [H,W,spp] i32, stats dict) as torch device tensors."""
     r = Renderer(scene, camera, params, **kw)

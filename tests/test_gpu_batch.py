@@ -1,0 +1,76 @@
+"""Batched wavefront (many scenes in one queue) against sequential single-scene
+frames and against the oracle."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_1504_03151_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_03151_amd import rt as _rt
+    _rt.lib()
+    return _rt
+
+
+def _mixed_batch():
+    ws = [S.random_tiny(s, size=20 + 7 * s, depth=2 + s % 4) for s in range(6)]
+    ws[2].camera.height = 13                         # ragged tiles
+    ws.append(S.config0())
+    w1 = S.one_sphere(plane_y=-3.0, size=31)
+    w1.params.max_depth = 1
+    ws.append(w1)
+    ws[3].params.spp, ws[3].params.jitter, ws[3].params.seed = 4, 1, 9
+    return ws
+
+
+def test_batch_equals_sequential_frames(rt):
+    ws = _mixed_batch()
+    scs = [rt.Scene(w.scene).upload() for w in ws]
+    br = rt.BatchRenderer(scs, [w.camera for w in ws], [w.params for w in ws])
+    for rep in range(2):                             # eager-captured graph, then a replay
+        rgb_b, ids_b = br.render(rt.FLAG_SYNC)
+        torch.cuda.synchronize()
+        assert br.read_stats()["status"] == 0
+        for w, sc, rb, ib in zip(ws, scs, rgb_b, ids_b):
+            rgb, ids, _ = rt.render(sc, w.camera, w.params)
+            torch.cuda.synchronize()
+            assert torch.equal(ids, ib), w.name
+            assert torch.allclose(rgb, rb, rtol=1e-5, atol=1e-6), (w.name, (rgb - rb).abs().max().item())
+
+
+def test_batch_matches_oracle(rt):
+    ws = _mixed_batch()[:4]
+    scs = [rt.Scene(w.scene).upload() for w in ws]
+    br = rt.BatchRenderer(scs, [w.camera for w in ws], [w.params for w in ws])
+    rgb_b, ids_b = br.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    for w, rb, ib in zip(ws, rgb_b, ids_b):
+        ref = oracle.render(w.scene, w.camera, w.params)
+        rob = ref["margin"] > 1e-4
+        assert rob.mean() > 0.93
+        g_ids = ib.reshape(-1, w.params.spp).cpu().numpy()
+        assert (g_ids[rob] == ref["ids"][rob]).all()
+        err = np.abs(rb.reshape(-1, 3).double().cpu().numpy() - ref["rgb"]).max(axis=1)
+        assert err[rob].max() <= 1e-3
+
+
+def test_batch_of_config3_scenes_runs_and_matches_sequential(rt):
+    ws = [S.config3_scene(b) for b in range(12)]
+    scs = [rt.Scene(w.scene).upload() for w in ws]
+    br = rt.BatchRenderer(scs, [w.camera for w in ws], [w.params for w in ws])
+    rgb_b, ids_b = br.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    st = br.read_stats()
+    assert st["status"] == 0 and st["rays"][0] == sum(w.camera.n_pixels for w in ws)
+    for w, sc, rb, ib in zip(ws, scs, rgb_b, ids_b):
+        rgb, ids, _ = rt.render(sc, w.camera, w.params)
+        assert torch.equal(ids, ib)
+        assert torch.allclose(rgb, rb, rtol=1e-5, atol=1e-6)

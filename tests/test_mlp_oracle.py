@@ -1,0 +1,112 @@
+"""Pins of the FP64 radiance-cache network oracle (oracle/mlp.py).
+
+Expected values come from calculus (central finite differences), closed forms
+(Adam's first step, the encoding at chosen points, BF16 tie rounding) and
+special cases (zero weights, identity weights), never from the oracle itself.
+"""
+import numpy as np
+
+from oracle import mlp
+
+
+def _rand_problem(seed, n=24):
+    rng = np.random.default_rng(seed)
+    ws = mlp.init_weights(seed)
+    feats = rng.normal(size=(n, mlp.WIDTH))
+    feats[:, mlp.N_IN:] = 0.0
+    target = rng.uniform(0, 2, size=(n, 3))
+    return ws, feats, target
+
+
+def test_backward_matches_central_differences():
+    ws, feats, target = _rand_problem(1)
+    ws = [w.astype(np.float64) for w in ws]
+    loss, grads, y = mlp.loss_and_grads(ws, feats, target, rounding=False)
+    rng = np.random.default_rng(2)
+    h = 1e-6
+    for l in range(6):
+        for _ in range(6):
+            i, j = rng.integers(ws[l].shape[0]), rng.integers(mlp.N_IN if l == 0 else mlp.WIDTH)
+            wp = [w.copy() for w in ws]
+            wm = [w.copy() for w in ws]
+            wp[l][i, j] += h
+            wm[l][i, j] -= h
+
+            # the loss's denominator is a stop-gradient: hold it at the unperturbed y
+            def frozen(wx):
+                yx, _ = mlp.forward(wx, feats, rounding=False)
+                return np.mean((yx - target) ** 2 / (y * y + 0.01))
+
+            num = (frozen(wp) - frozen(wm)) / (2 * h)
+            assert abs(num - grads[l][i, j]) <= 1e-6 * max(1e-3, abs(num)), (l, i, j, num, grads[l][i, j])
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    g = np.array([3.0, -0.5, 1e-3, 0.0])
+    w, m, v = mlp.adam_step(np.zeros(4), np.zeros(4), np.zeros(4), g, t=1, lr=1e-3, eps=1e-8)
+    # m^ = g, v^ = g^2  ->  step = -lr g / (|g| + eps)
+    np.testing.assert_allclose(w, -1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+    np.testing.assert_allclose(m, 0.1 * g, rtol=1e-15)
+    np.testing.assert_allclose(v, 0.001 * g * g, rtol=1e-12)
+
+
+def test_zero_weights_give_zero_output_and_identity_weights_pass_relu_through():
+    feats = np.random.default_rng(3).normal(size=(10, 64))
+    zeros = [np.zeros((64, 64))] * 5 + [np.zeros((3, 64))]
+    y, _ = mlp.forward(zeros, feats, rounding=True)
+    assert (y == 0).all()
+    eye = [np.eye(64)] * 5 + [np.eye(64)[:3] * np.array([[1.0], [2.0], [-1.0]])]
+    y, _ = mlp.forward(eye, feats, rounding=False)
+    relu = np.maximum(feats, 0.0)
+    np.testing.assert_allclose(y, relu[:, :3] * [1.0, 2.0, -1.0], rtol=0, atol=0)
+
+
+def test_loss_is_zero_at_the_target():
+    ws, feats, _ = _rand_problem(4)
+    y, _ = mlp.forward(ws, feats)
+    loss, grads, _ = mlp.loss_and_grads(ws, feats, y)
+    assert loss == 0.0 and all((g == 0).all() for g in grads)
+
+
+def test_bf16_rounding_ties_to_even():
+    x = np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -8 + 2 ** -20, -(1.0 + 2 ** -9), 0.0, 3.0])
+    np.testing.assert_array_equal(mlp.bf16_round(x),
+                                  [1.0, 1.0 + 4 * 2 ** -8, 1.0 + 2 ** -7, -1.0, 0.0, 3.0])
+    # idempotent, and within half an ulp (2^-9 relative)
+    r = np.random.default_rng(0).normal(size=1000)
+    b = mlp.bf16_round(r)
+    assert (mlp.bf16_round(b) == b).all()
+    assert (np.abs(b - r) <= np.abs(r) * 2 ** -8 + 1e-300).all()
+
+
+def test_encoding_closed_form():
+    lo, hi = np.array([-2.0, 0.0, 10.0]), np.array([2.0, 4.0, 30.0])
+    x = np.array([[0.0, 2.0, 20.0], [1.0, 3.0, 25.0]])       # x~ = (0,0,0) and (0.5,0.5,0.5)
+    nf = np.array([[0, 0, 1.0], [0, 1.0, 0]])
+    v = np.array([[1.0, 0, 0], [0, 0, -1.0]])
+    f = mlp.encode(x, nf, v, lo, hi)
+    for c in range(3):
+        for j in range(6):
+            assert abs(f[0, 12 * c + 2 * j]) < 1e-15 and f[0, 12 * c + 2 * j + 1] == 1.0
+    # x~ = 1/2: sin(2^j pi / 2) = 1, 0, 0, ... ; cos = 0, -1, 1, 1, ...
+    np.testing.assert_allclose(f[1, 0:12], [1, 0, 0, -1, 0, 1, 0, 1, 0, 1, 0, 1], atol=1e-14)
+    np.testing.assert_array_equal(f[:, 36:39], nf)
+    np.testing.assert_array_equal(f[:, 39:42], v)
+    assert (f[:, 42:] == 0).all()
+
+
+def test_training_reduces_the_loss():
+    rng = np.random.default_rng(5)
+    ws = [w.astype(np.float64) for w in mlp.init_weights(5)]
+    feats = rng.uniform(-1, 1, size=(256, 64))
+    feats[:, 42:] = 0.0
+    target = np.abs(np.sin(3 * feats[:, :3])) + 0.2
+    m = [np.zeros_like(w) for w in ws]
+    v = [np.zeros_like(w) for w in ws]
+    first = None
+    for t in range(1, 201):
+        loss, grads, _ = mlp.loss_and_grads(ws, feats, target)
+        first = loss if first is None else first
+        for l in range(6):
+            ws[l], m[l], v[l] = mlp.adam_step(ws[l], m[l], v[l], grads[l], t, lr=1e-3)
+    assert loss < 0.3 * first
