@@ -15,9 +15,11 @@ states, step by step and in FP64, what the GPU network computes:
             the BF16 rounding of FP32 master weights.  The cache adds max(y, 0).
   loss      mean over samples and channels of (y - T)^2 / (sg(y)^2 + 0.01)
             (relative L2, sg = stop-gradient).
-  backward  g_y = 2 (y - T) / (y^2 + 0.01) / (3 N); g_h5 = W_6^T g_y;
+  backward  g_y = bf16(2 (y - T) / (y^2 + 0.01) / (3 N)); g_h5 = W_6^T g_y;
             g_z_l = bf16(g_h_l * [z_l > 0]); dW_l = g_z_l^T h_{l-1};
-            g_h_{l-1} = W_l^T g_z_l.  dW_6 = g_y^T h_5 (g_y not rounded).
+            g_h_{l-1} = W_l^T g_z_l; dW_6 = g_y^T h_5.  (Every operand of a
+            product is BF16, as on the matrix cores; sums are FP64 here, FP32
+            there.)
   Adam      m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
             w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)
             on FP32 master weights (here FP64).
@@ -102,7 +104,7 @@ def loss_and_grads(ws, feats, target, rounding=True):
     n = len(y)
     den = y * y + 0.01
     loss = float(np.mean((y - target) ** 2 / den))
-    gy = 2.0 * (y - target) / den / (N_OUT * n)
+    gy = _r(2.0 * (y - target) / den / (N_OUT * n), rounding)
     grads = [None] * (N_HIDDEN + 1)
     grads[N_HIDDEN] = gy.T @ h[N_HIDDEN]
     gh = gy @ W[N_HIDDEN]
