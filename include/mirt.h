@@ -212,6 +212,30 @@ rt_status rt_host_trace(const rt_scene* scene, const float* rays, int64_t n, int
  * clears the totals after reading. */
 rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset);
 
+/* ---- radiance-cache network (BF16 operands on the matrix cores, FP32 accumulation) ----
+ * A small MLP that stands in for the radiance of rays below bounce 2 (the
+ * learned form of the recursive step).  Input: 64 features (the 36 sin/cos
+ * frequency encodings of the hit position normalised to the scene bounds,
+ * the facing normal and the view direction, zero-padded from 42); five hidden
+ * layers of 64 with ReLU; 3 outputs; no biases.  Weights are row-major
+ * (out, in): W1..W5 [64][64] then W6 [3][64] = rt_mlp_num_params() values.
+ * Every pointer below is a device pointer; BF16 values are uint16 bit patterns. */
+int32_t rt_mlp_num_params(void);
+/* y [n][3] = network(x_bf16 [n][64]). */
+rt_status rt_mlp_forward(const uint16_t* w_bf16, const uint16_t* x_bf16, int64_t n, float* y, void* stream);
+/* Relative-L2 loss mean((y - t)^2 / (y^2 + 0.01)) over n_total samples: adds
+ * this batch's weight gradients into dw [num_params] (FP32) and its summed
+ * per-sample loss terms into loss_sum [1]. */
+rt_status rt_mlp_grad(const uint16_t* w_bf16, const uint16_t* x_bf16, const float* target, int64_t n,
+                      int64_t n_total, float* dw, float* loss_sum, void* stream);
+/* One Adam step (step >= 1, bias-corrected) on FP32 master weights w; refreshes
+ * w_bf16 and clears grad. */
+rt_status rt_mlp_adam(float* w, uint16_t* w_bf16, float* m, float* v, float* grad, int32_t step, float lr,
+                      float b1, float b2, float eps, void* stream);
+/* Diagnostic: d [32][32] = a [32][16] x b [16][32] (BF16 in, FP32 out) on one
+ * matrix-core instruction, for checking the operand layout the kernels use. */
+rt_status rt_mlp_mfma_probe(const uint16_t* a, const uint16_t* b, float* d, void* stream);
+
 const char* rt_last_error(void);
 const char* rt_version(void);
 

@@ -1,0 +1,463 @@
+// mlp.cpp -- the radiance-cache network on gfx950 matrix cores (BF16 operands,
+// FP32 accumulation): fused forward, fused forward+backward (weight
+// gradients), Adam, and the cache inference used by the renderer.
+//
+// Network: 64-wide input (42 features, zero padded), five hidden layers of 64
+// with ReLU, 3 outputs, no biases.  Weights are stored row-major (out, in):
+// W1..W5 (64 x 64) then W6 (3 x 64), 20672 values.
+//
+// Tiling: one wave owns 32 samples and computes H^T = W X^T with
+// v_mfma_f32_32x32x16_bf16 (M = output features, N = samples, K = input
+// features).  Operand layouts (lane l, h = l / 32):
+//   A (32 x 16): lane holds A[l % 32][8h .. 8h + 7]
+//   B (16 x 32): lane holds B[8h .. 8h + 7][l % 32]
+//   D (32 x 32): lane holds D[8 (i / 4) + 4 h + i % 4][l % 32], i = 0..15
+// A layer's D registers are fed to the next layer as its B operand as they
+// are: B k-slot kappa = 16 ks + 8 h + j then holds hidden unit sigma(kappa),
+// sigma = swap of bits 2 and 3.  The weights of layers 2..6 are staged into
+// LDS with their input columns permuted by sigma, so no activation moves.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "mirt_internal.h"
+
+namespace mirt {
+
+#define HIP_TRY_M(x)                                                       \
+    do {                                                                   \
+        hipError_t err_ = (x);                                             \
+        if (err_ != hipSuccess) {                                          \
+            set_error(std::string(#x) + ": " + hipGetErrorString(err_));  \
+            return RT_ERR_HIP;                                             \
+        }                                                                  \
+    } while (0)
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short short8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kW = 64;                     // width
+constexpr int kLayerElems = kW * kW;
+constexpr int kParams = 5 * kLayerElems + 3 * kW;   // 20672
+
+// float -> bf16 bits, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+__device__ __forceinline__ int swap23(int k) { return (k & ~12) | ((k & 4) << 1) | ((k & 8) >> 1); }
+
+__device__ __forceinline__ f32x16 mfma(short8 a, short8 b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+__device__ __forceinline__ short8 lds8(const uint16_t* p) { return *reinterpret_cast<const short8*>(p); }
+
+__device__ __forceinline__ f32x16 zero16() {
+    f32x16 z;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) z[i] = 0.0f;
+    return z;
+}
+
+// ----------------------------------------------------------------------------
+// layout probe: D = A B for one 32x32x16 tile (A [32][16], B [16][32] bf16)
+// ----------------------------------------------------------------------------
+__global__ void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* D) {
+    const int l = threadIdx.x & 63, h = l >> 5, r = l & 31;
+    short8 a, b;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        a[j] = (short)A[r * 16 + 8 * h + j];
+        b[j] = (short)B[(8 * h + j) * 32 + r];
+    }
+    const f32x16 d = mfma(a, b, zero16());
+#pragma unroll
+    for (int i = 0; i < 16; ++i) D[(8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r] = d[i];
+}
+
+// ----------------------------------------------------------------------------
+// weight staging into LDS
+// ----------------------------------------------------------------------------
+// Forward weights: Wf[layer][out m][k-slot kappa], layers 0..4 (64 rows) and
+// the output layer (32 rows, rows >= 3 zero).  Layer 0 takes the input
+// features in natural order; later layers read their inputs through sigma.
+struct MlpLds {
+    uint16_t wf[5 * kLayerElems + 32 * kW];
+};
+
+__device__ void stage_forward(const uint16_t* __restrict__ w, uint16_t* wf) {
+    for (int e = threadIdx.x; e < 5 * kLayerElems + 32 * kW; e += blockDim.x) {
+        const int layer = e / kLayerElems;
+        const int rem = e - layer * kLayerElems;
+        const int m = rem / kW, kap = rem % kW;
+        uint16_t v;
+        if (layer < 5) {
+            v = w[layer * kLayerElems + m * kW + (layer == 0 ? kap : swap23(kap))];
+        } else {
+            v = m < 3 ? w[5 * kLayerElems + m * kW + swap23(kap)] : (uint16_t)0;
+        }
+        wf[e] = v;
+    }
+}
+
+// Backward weights: Wb[l][in m][k-slot kappa] = W_{l+1}[sigma(kappa)][m] for
+// layers 1..4 (the products g_h_{l} = W_{l+1}^T g_z_{l+1}), and the output
+// layer's transpose Wb6[m][k] = W6[k][m] (k < 3, 16 columns).
+__device__ void stage_backward(const uint16_t* __restrict__ w, uint16_t* wb, uint16_t* wb6) {
+    for (int e = threadIdx.x; e < 4 * kLayerElems; e += blockDim.x) {
+        const int li = e / kLayerElems;          // 0..3 -> weight layer 2..5 (index 1..4)
+        const int rem = e - li * kLayerElems;
+        const int m = rem / kW, kap = rem % kW;
+        wb[e] = w[(li + 1) * kLayerElems + swap23(kap) * kW + m];
+    }
+    for (int e = threadIdx.x; e < kW * 16; e += blockDim.x) {
+        const int m = e / 16, k = e % 16;
+        wb6[e] = k < 3 ? w[5 * kLayerElems + k * kW + m] : (uint16_t)0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// forward through the hidden layers for one wave's 32 samples
+// ----------------------------------------------------------------------------
+// b[ks] (ks = 0..3) is the B operand (this lane's sample, k-slots 16ks+8h..+7).
+// Layer output D (two 32-row tiles) is rounded to BF16 after ReLU and packed
+// back into b as bop[ks][j] = D[ks / 2][8 (ks % 2) + j].
+__device__ __forceinline__ void hidden_layer(const uint16_t* wl, short8 (&b)[4], int l) {
+    const int h = l >> 5, r = l & 31;
+    f32x16 d0 = zero16(), d1 = zero16();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        d0 = mfma(lds8(wl + r * kW + 16 * ks + 8 * h), b[ks], d0);
+        d1 = mfma(lds8(wl + (32 + r) * kW + 16 * ks + 8 * h), b[ks], d1);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        b[0][j] = (short)f2bf(fmaxf(d0[j], 0.0f));
+        b[1][j] = (short)f2bf(fmaxf(d0[8 + j], 0.0f));
+        b[2][j] = (short)f2bf(fmaxf(d1[j], 0.0f));
+        b[3][j] = (short)f2bf(fmaxf(d1[8 + j], 0.0f));
+    }
+}
+
+__device__ __forceinline__ f32x16 output_layer(const uint16_t* w6, const short8 (&b)[4], int l) {
+    const int h = l >> 5, r = l & 31;
+    f32x16 d = zero16();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) d = mfma(lds8(w6 + r * kW + 16 * ks + 8 * h), b[ks], d);
+    return d;   // lanes 0..31: d[0..2] = y of sample (l % 32)
+}
+
+__device__ __forceinline__ void load_input(const uint16_t* __restrict__ x, int64_t sample, bool valid, int l,
+                                           short8 (&b)[4]) {
+    const int h = l >> 5;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        if (valid) {
+            b[ks] = *reinterpret_cast<const short8*>(x + sample * kW + 16 * ks + 8 * h);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) b[ks][j] = 0;
+        }
+    }
+}
+
+// mode 0: y [n][3]; mode 1: acc[3 pix + c] += w_c * max(y_c, 0) (cache inference)
+template <int MODE>
+__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t* __restrict__ w, const uint16_t* __restrict__ x,
+                                                     int64_t n, float* __restrict__ y, const uint32_t* count_p,
+                                                     const uint32_t* __restrict__ pix, const float* __restrict__ wt,
+                                                     float* __restrict__ acc) {
+    __shared__ __attribute__((aligned(16))) MlpLds S;
+    stage_forward(w, S.wf);
+    __syncthreads();
+    if (count_p) n = min((int64_t)*count_p, n);
+    const int l = threadIdx.x & 63;
+    const int64_t tiles = (n + 31) / 32;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < tiles; t += (int64_t)gridDim.x * 4) {
+        const int64_t s = t * 32 + (l & 31);
+        const bool valid = s < n;
+        short8 b[4];
+        load_input(x, s, valid, l, b);
+        for (int layer = 0; layer < 5; ++layer) hidden_layer(S.wf + layer * kLayerElems, b, l);
+        const f32x16 d = output_layer(S.wf + 5 * kLayerElems, b, l);
+        if (l < 32 && valid) {
+            if (MODE == 0) {
+                y[s * 3 + 0] = d[0];
+                y[s * 3 + 1] = d[1];
+                y[s * 3 + 2] = d[2];
+            } else {
+                const uint32_t p = pix[s];
+                atomicAdd(acc + 3 * p + 0, wt[3 * s + 0] * fmaxf(d[0], 0.0f));
+                atomicAdd(acc + 3 * p + 1, wt[3 * s + 1] * fmaxf(d[1], 0.0f));
+                atomicAdd(acc + 3 * p + 2, wt[3 * s + 2] * fmaxf(d[2], 0.0f));
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// forward + backward: accumulates dW (FP32, natural layout) and the loss sum
+// ----------------------------------------------------------------------------
+constexpr int kGradWaves = 2;   // waves per block of the training kernel (LDS budget)
+
+struct GradLds {
+    uint16_t wf[5 * kLayerElems + 32 * kW];
+    uint16_t wb[4 * kLayerElems];
+    uint16_t wb6[kW * 16];
+    short8 act[kGradWaves][6][4][64];      // per wave, per layer: each lane's packed operand (input, h_1..h_5)
+    uint16_t gy[kGradWaves][32 * 32];      // per wave: [channel (32 rows, 3 used)][sample]
+    uint16_t gz[kGradWaves][kW * 32];      // per wave: [feature][sample]
+    uint16_t ht[kGradWaves][kW * 32];      // per wave: [feature][sample]
+};
+
+// D-layout value (tile mt, index i) of a packed operand b[2 mt + i / 8][i % 8]
+__device__ __forceinline__ float unpack_d(const short8 (&b)[4], int mt, int i) {
+    return bf2f((uint16_t)b[2 * mt + (i >> 3)][i & 7]);
+}
+
+// write a packed D-layout activation block to LDS as [feature][sample]
+__device__ __forceinline__ void store_dlayout(uint16_t* dst, const short8 (&b)[4], int l) {
+    const int h = l >> 5, r = l & 31;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int f = 32 * mt + 8 * (i >> 2) + 4 * h + (i & 3);
+            dst[f * 32 + r] = (uint16_t)b[2 * mt + (i >> 3)][i & 7];
+        }
+}
+
+// write the input operand (natural k-slots) to LDS as [feature][sample]
+__device__ __forceinline__ void store_input(uint16_t* dst, const short8 (&b)[4], int l) {
+    const int h = l >> 5, r = l & 31;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) dst[(16 * ks + 8 * h + j) * 32 + r] = (uint16_t)b[ks][j];
+}
+
+// dW[m][n] += sum over the wave's 32 samples of A[m][s] B[n][s]  (A rows m_rows, B rows 64)
+__device__ __noinline__ void accumulate_dw(const uint16_t* a_fs, int m_rows, const uint16_t* b_fs, float* dw,
+                                           int dw_rows, int l) {
+    const int h = l >> 5, r = l & 31;
+    for (int mt = 0; mt * 32 < m_rows; ++mt)
+        for (int nt = 0; nt < 2; ++nt) {
+            f32x16 d = zero16();
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks)
+                d = mfma(lds8(a_fs + (32 * mt + r) * 32 + 16 * ks + 8 * h),
+                         lds8(b_fs + (32 * nt + r) * 32 + 16 * ks + 8 * h), d);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 32 * mt + 8 * (i >> 2) + 4 * h + (i & 3);
+                if (m < dw_rows) atomicAdd(dw + m * kW + 32 * nt + r, d[i]);
+            }
+        }
+}
+
+__device__ __forceinline__ void load_act(const GradLds& S, int wave, int layer, int l, short8 (&b)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b[q] = S.act[wave][layer][q][l];
+}
+
+__global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __restrict__ w,
+                                                              const uint16_t* __restrict__ x,
+                                                              const float* __restrict__ target, int64_t n,
+                                                              float inv_3n, const uint32_t* count_p,
+                                                              float* __restrict__ dw, float* __restrict__ loss_sum) {
+    __shared__ __attribute__((aligned(16))) GradLds S;
+    stage_forward(w, S.wf);
+    stage_backward(w, S.wb, S.wb6);
+    const int wave = threadIdx.x >> 6;
+    for (int e = threadIdx.x & 63; e < 32 * 32; e += 64) S.gy[wave][e] = 0;
+    __syncthreads();
+    if (count_p) n = min((int64_t)*count_p, n);
+    const int l = threadIdx.x & 63, h = l >> 5, r = l & 31;
+    const int64_t tiles = (n + 31) / 32;
+    const int64_t groups = (tiles + kGradWaves - 1) / kGradWaves;
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {   // block-uniform loop
+        const int64_t t = g * kGradWaves + wave;
+        const int64_t s = t * 32 + r;
+        const bool valid = s < n;
+        // forward, keeping every layer's operand in this lane's LDS slots
+        short8 b[4];
+        load_input(x, s, valid, l, b);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S.act[wave][0][q][l] = b[q];
+        for (int k = 1; k < 6; ++k) {
+            hidden_layer(S.wf + (k - 1) * kLayerElems, b, l);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) S.act[wave][k][q][l] = b[q];
+        }
+        const f32x16 d = output_layer(S.wf + 5 * kLayerElems, b, l);
+        // loss and g_y on lanes 0..31 (this lane's sample); g_y is BF16 like every product operand
+        float gyv[3] = {0.0f, 0.0f, 0.0f};
+        float lsum = 0.0f;
+        if (h == 0 && valid) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float yv = d[c], tv = target[3 * s + c];
+                const float den = yv * yv + 0.01f;
+                const float e = yv - tv;
+                lsum += e * e / den;
+                gyv[c] = bf2f(f2bf(2.0f * e / den * inv_3n));
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+        if (l == 0 && lsum != 0.0f) atomicAdd(loss_sum, lsum);
+        // dW6 = g_y^T h5
+        if (h == 0)
+            for (int c = 0; c < 3; ++c) S.gy[wave][c * 32 + r] = f2bf(gyv[c]);
+        store_dlayout(S.ht[wave], b, l);
+        __syncthreads();
+        accumulate_dw(S.gy[wave], 32, S.ht[wave], dw + 5 * kLayerElems, 3, l);
+        // g_h5 = W6^T g_y  (K = channels, padded to 16)
+        short8 bgy;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bgy[j] = (short)(h == 0 && j < 3 ? f2bf(gyv[j]) : 0);
+        f32x16 gh0 = mfma(lds8(S.wb6 + r * 16 + 8 * h), bgy, zero16());
+        f32x16 gh1 = mfma(lds8(S.wb6 + (32 + r) * 16 + 8 * h), bgy, zero16());
+        for (int L = 5; L >= 1; --L) {
+            // g_z_L = bf16(g_h_L * [h_L > 0]), packed like the forward activations
+            short8 hl[4], gz[4];
+            load_act(S, wave, L, l, hl);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                gz[i >> 3][i & 7] = (short)(unpack_d(hl, 0, i) > 0.0f ? f2bf(gh0[i]) : 0);
+                gz[2 + (i >> 3)][i & 7] = (short)(unpack_d(hl, 1, i) > 0.0f ? f2bf(gh1[i]) : 0);
+            }
+            __syncthreads();
+            store_dlayout(S.gz[wave], gz, l);
+            short8 hp[4];
+            load_act(S, wave, L - 1, l, hp);
+            if (L - 1 >= 1) store_dlayout(S.ht[wave], hp, l);
+            else store_input(S.ht[wave], hp, l);
+            __syncthreads();
+            accumulate_dw(S.gz[wave], 64, S.ht[wave], dw + (L - 1) * kLayerElems, 64, l);
+            if (L > 1) {
+                const uint16_t* wbl = S.wb + (L - 2) * kLayerElems;
+                gh0 = zero16();
+                gh1 = zero16();
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    gh0 = mfma(lds8(wbl + r * kW + 16 * ks + 8 * h), gz[ks], gh0);
+                    gh1 = mfma(lds8(wbl + (32 + r) * kW + 16 * ks + 8 * h), gz[ks], gh1);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Adam on FP32 master weights; refreshes the BF16 copy and clears the gradient.
+__global__ void k_mlp_adam(float* __restrict__ w, uint16_t* __restrict__ wb, float* __restrict__ m,
+                           float* __restrict__ v, float* __restrict__ g, int n, float lr, float b1, float b2,
+                           float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+    g[i] = 0.0f;
+}
+
+static int grid_for(int64_t tiles, int per_block) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    const int64_t need = (tiles + per_block - 1) / per_block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * 4));
+}
+
+// internal launchers used by the renderer's cache frames
+rt_status mlp_infer_launch(const uint16_t* w, const uint16_t* x, int64_t cap, const uint32_t* count, const uint32_t* pix,
+                           const float* wt, float* acc, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_forward<1>, dim3(grid_for((cap + 31) / 32, 4)), dim3(256), 0, st, w, x, cap, nullptr, count,
+                       pix, wt, acc);
+    HIP_TRY_M(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status mlp_grad_launch(const uint16_t* w, const uint16_t* x, const float* target, int64_t n, int64_t n_total,
+                          const uint32_t* count, float* dw, float* loss, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid_for((n + 31) / 32, kGradWaves)), dim3(64 * kGradWaves), 0, st, w, x,
+                       target, n,
+                       1.0f / (3.0f * (float)n_total), count, dw, loss);
+    HIP_TRY_M(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status mlp_adam_launch(float* w, uint16_t* wb, float* m, float* v, float* g, int32_t t, float lr, float b1, float b2,
+                          float eps, hipStream_t st) {
+    const float c1 = 1.0f / (1.0f - powf(b1, (float)t)), c2 = 1.0f / (1.0f - powf(b2, (float)t));
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, st, w, wb, m, v, g, kParams, lr, b1, b2,
+                       eps, c1, c2);
+    HIP_TRY_M(hipGetLastError());
+    return RT_OK;
+}
+
+}  // namespace mirt
+
+using namespace mirt;
+
+extern "C" {
+
+int32_t rt_mlp_num_params(void) { return kParams; }
+
+rt_status rt_mlp_forward(const uint16_t* w_bf16, const uint16_t* x_bf16, int64_t n, float* y, void* stream) {
+    if (n < 0 || (n > 0 && (!w_bf16 || !x_bf16 || !y))) {
+        set_error("rt_mlp_forward: invalid argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    if (n == 0) return RT_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_mlp_forward<0>, dim3(grid_for((n + 31) / 32, 4)), dim3(256), 0, st, w_bf16, x_bf16, n, y,
+                       nullptr, nullptr, nullptr, nullptr);
+    HIP_TRY_M(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_mlp_grad(const uint16_t* w_bf16, const uint16_t* x_bf16, const float* target, int64_t n, int64_t n_total,
+                      float* dw, float* loss_sum, void* stream) {
+    if (n < 0 || n_total <= 0 || (n > 0 && (!w_bf16 || !x_bf16 || !target || !dw || !loss_sum))) {
+        set_error("rt_mlp_grad: invalid argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    if (n == 0) return RT_OK;
+    return mlp_grad_launch(w_bf16, x_bf16, target, n, n_total, nullptr, dw, loss_sum, static_cast<hipStream_t>(stream));
+}
+
+rt_status rt_mlp_adam(float* w, uint16_t* w_bf16, float* m, float* v, float* grad, int32_t step, float lr, float b1,
+                      float b2, float eps, void* stream) {
+    if (!w || !w_bf16 || !m || !v || !grad || step < 1) {
+        set_error("rt_mlp_adam: invalid argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    return mlp_adam_launch(w, w_bf16, m, v, grad, step, lr, b1, b2, eps, static_cast<hipStream_t>(stream));
+}
+
+rt_status rt_mlp_mfma_probe(const uint16_t* a, const uint16_t* b, float* d, void* stream) {
+    if (!a || !b || !d) {
+        set_error("rt_mlp_mfma_probe: NULL argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), a, b, d);
+    HIP_TRY_M(hipGetLastError());
+    return RT_OK;
+}
+
+}  // extern "C"

@@ -96,6 +96,11 @@ SIGNATURES = {
     "rt_occluded": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P]),
     "rt_host_trace": (C.c_int32, [_P, _P, C.c_int64, C.c_int32, _P, _P, _P, C.c_int32]),
     "rt_kernel_times": (C.c_int32, [_P, _P, C.c_int32]),
+    "rt_mlp_num_params": (C.c_int32, []),
+    "rt_mlp_forward": (C.c_int32, [_P, _P, C.c_int64, _P, _P]),
+    "rt_mlp_grad": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P]),
+    "rt_mlp_adam": (C.c_int32, [_P, _P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
+    "rt_mlp_mfma_probe": (C.c_int32, [_P, _P, _P, _P]),
     "rt_last_error": (C.c_char_p, []),
     "rt_version": (C.c_char_p, []),
 }
@@ -396,3 +401,49 @@ def make_rays(o, d, tmax=None) -> np.ndarray:
     if tmax is not None:
         R[:, 7] = np.broadcast_to(np.asarray(tmax, np.float64), (len(o),))
     return R
+
+
+# ---------------------------------------------------------------------------- radiance-cache network
+
+def bf16_bits(t):
+    """float32 tensor -> BF16 bit patterns (round to nearest even) as int16 tensor (same device)."""
+    import torch
+    return t.to(torch.bfloat16).view(torch.int16)
+
+
+def bf16_to_f32(bits):
+    import torch
+    return bits.view(torch.bfloat16).to(torch.float32)
+
+
+def mlp_num_params() -> int:
+    return int(lib().rt_mlp_num_params())
+
+
+def mlp_forward(w_bf16, x_bf16, stream=None):
+    """y [n,3] f32 for features x_bf16 [n,64] (int16 BF16 bits) and weights w_bf16 [num_params]."""
+    import torch
+    n = x_bf16.shape[0]
+    y = torch.empty((n, 3), dtype=torch.float32, device=x_bf16.device)
+    _check(lib().rt_mlp_forward(w_bf16.data_ptr(), x_bf16.data_ptr(), n, y.data_ptr(), _stream_ptr(stream)),
+           "rt_mlp_forward")
+    return y
+
+
+def mlp_grad(w_bf16, x_bf16, target, dw, loss_sum, n_total=None, stream=None):
+    n = x_bf16.shape[0]
+    _check(lib().rt_mlp_grad(w_bf16.data_ptr(), x_bf16.data_ptr(), target.data_ptr(), n, n_total or n,
+                             dw.data_ptr(), loss_sum.data_ptr(), _stream_ptr(stream)), "rt_mlp_grad")
+
+
+def mlp_adam(w, w_bf16, m, v, grad, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+    _check(lib().rt_mlp_adam(w.data_ptr(), w_bf16.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(), int(step),
+                             lr, b1, b2, eps, _stream_ptr(stream)), "rt_mlp_adam")
+
+
+def mfma_probe(a_bits, b_bits, stream=None):
+    import torch
+    d = torch.empty((32, 32), dtype=torch.float32, device=a_bits.device)
+    _check(lib().rt_mlp_mfma_probe(a_bits.data_ptr(), b_bits.data_ptr(), d.data_ptr(), _stream_ptr(stream)),
+           "rt_mlp_mfma_probe")
+    return d
