@@ -131,7 +131,7 @@ typedef struct {
 #define RT_STATS_MAX_DEPTH 16
 /* Device-side counters, accumulated by rt_render (caller zeroes them). */
 typedef struct {
-    uint32_t status;          /* bit 0: ray queue overflow; bit 1: shadow queue overflow */
+    uint32_t status;          /* bit 0: ray queue overflow; bit 1: shadow queue overflow; bit 2: cache records */
     uint32_t passes;
     uint64_t rays[RT_STATS_MAX_DEPTH];    /* closest-hit queries issued per depth */
     uint64_t shadow[RT_STATS_MAX_DEPTH];  /* shadow (any-hit) queries issued per depth */
@@ -207,9 +207,10 @@ rt_status rt_host_trace(const rt_scene* scene, const float* rays, int64_t n, int
 
 /* Kernel timings recorded by frames rendered with RT_FLAG_TIME_KERNELS since
  * the last reset: total milliseconds and launch counts of the closest-hit
- * (index 0), shading (1) and shadow any-hit (2) kernels.  Waits for the
- * recorded events.  ms [3] and launches [3] are host arrays; reset != 0
- * clears the totals after reading. */
+ * (index 0), shading (1) and shadow any-hit (2) kernels, the cache inference
+ * (3) and a learned frame's whole training part (4).  Waits for the recorded
+ * events.  ms [5] and launches [5] are host arrays; reset != 0 clears the
+ * totals after reading. */
 rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset);
 
 /* ---- radiance-cache network (BF16 operands on the matrix cores, FP32 accumulation) ----
@@ -235,6 +236,47 @@ rt_status rt_mlp_adam(float* w, uint16_t* w_bf16, float* m, float* v, float* gra
 /* Diagnostic: d [32][32] = a [32][16] x b [16][32] (BF16 in, FP32 out) on one
  * matrix-core instruction, for checking the operand layout the kernels use. */
 rt_status rt_mlp_mfma_probe(const uint16_t* a, const uint16_t* b, float* d, void* stream);
+
+/* ---- learned form: frames whose recursion below `depth` is answered by the network ----
+ * At depth `depth`, a ray that misses returns the background and a ray that
+ * hits adds w * max(network(features(x, N_f, V)), 0) instead of its local
+ * shading and recursion.  With RT_CACHE_TRAIN the frame also picks up to
+ * train_samples of these queries (stratified, random per-frame offset), traces
+ * their rays on to full_depth with the plain tracer (the training targets)
+ * and takes train_steps Adam steps on the relative-L2 loss.  The image uses
+ * the weights from before the frame's training. */
+enum { RT_CACHE_INFER = 1, RT_CACHE_TRAIN = 2 };
+typedef struct {
+    int32_t mode;              /* RT_CACHE_INFER or RT_CACHE_TRAIN */
+    int32_t depth;             /* [2] depth whose hits query the network (>= 1) */
+    int32_t full_depth;        /* [8] recursion depth of the training targets */
+    int32_t train_samples;     /* [65536] queries trained on per frame (<= the state's capacity) */
+    int32_t train_steps;       /* [4] Adam steps per frame, on equal slices of the samples */
+    float lr, b1, b2, eps;     /* [1e-3, 0.9, 0.999, 1e-8] */
+    float bounds_lo[3], bounds_hi[3];   /* encoding bounds; all zero: the scene's bounds */
+    void* state;               /* device, rt_cache_state_bytes(capacity) bytes, set up by rt_cache_init */
+} rt_cache;
+
+/* Byte offsets inside the cache state.  counters (uint32): [0] Adam steps
+ * taken, [1] training samples of the last frame, [2..17] the last frame's
+ * per-step loss sums (float bits; divide by 3 x slice size).  The last
+ * frame's training batch: train_rays [cap][6] (o, d at the cache depth),
+ * train_feats [cap][64] BF16, train_targets [cap][3], train_pix [cap]
+ * (accumulation slot of each sample's pixel). */
+typedef struct {
+    size_t w_master, w_bf16, m, v, grad, counters, train_rays, train_feats, train_targets, train_pix, total;
+    int32_t capacity;
+} rt_cache_layout;
+rt_status rt_cache_state_layout(int32_t capacity, rt_cache_layout* out);
+size_t rt_cache_state_bytes(int32_t capacity);
+/* Initialise a state: FP32 master weights from w_host [rt_mlp_num_params()] (host), their
+ * BF16 copy, zero moments, gradients and counters. */
+rt_status rt_cache_init(void* state, int32_t capacity, const float* w_host, void* stream);
+size_t rt_render_cached_workspace_bytes(const rt_scene* scene, const rt_camera* cam, const rt_params* params,
+                                        const rt_cache* cache);
+/* One learned-form frame (all samples in one pass); arguments as rt_render. */
+rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt_params* params,
+                           const rt_cache* cache, float* out_rgb, int32_t* out_hit_ids);
 
 const char* rt_last_error(void);
 const char* rt_version(void);

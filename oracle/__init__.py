@@ -81,6 +81,13 @@ def lib():
             L.or_ray_tree.restype = C.c_int64
             L.or_ray_tree.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Params), C.c_int64,
                                       C.c_int32, C.c_void_p, C.c_int64, C.c_void_p]
+            L.or_render_cache.restype = C.c_int64
+            L.or_render_cache.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_Params), C.c_void_p,
+                                          C.c_int64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                          C.c_int64]
+            L.or_radiance.restype = C.c_int
+            L.or_radiance.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.c_void_p, C.c_int64, C.c_int32,
+                                      C.c_int32, C.c_void_p, C.c_void_p]
             L.or_pcg.restype = C.c_uint32
             L.or_pcg.argtypes = [C.c_uint32]
             L.or_jitter.restype = C.c_double
@@ -249,3 +256,40 @@ def jitter(seed: int, frame: int, pixel: int, s: int, dim: int) -> float:
 
 
 ROBUST = 1e-4
+
+
+def render_cache(scene, camera, params, cache_depth: int, pixels=None, nthreads: int = 0, cap: int = 1 << 22):
+    """Learned-form render without the cache terms: dict(rgb [n,3], margin [n], records [m,13]).
+
+    Each record (list index, x[3], N_f[3], V[3], w[3]) is a hit at cache_depth whose
+    radiance the cache supplies: pixel += w * max(cache(x, N_f, V), 0) / spp.
+    """
+    L = lib()
+    if pixels is None:
+        pixels = np.arange(camera.width * camera.height, dtype=np.int64)
+    pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+    n = len(pixels)
+    rgb = np.zeros((n, 3), np.float64)
+    margin = np.zeros((n,), np.float64)
+    rec = np.zeros((cap, 13), np.float64)
+    sc, cam, p = OScene(scene), _camera(camera), _params(params)
+    m = L.or_render_cache(C.byref(sc.c), C.byref(cam), C.byref(p), pixels.ctypes.data, n, int(cache_depth), nthreads,
+                          rgb.ctypes.data, margin.ctypes.data, rec.ctypes.data, cap)
+    if m < 0 or m > cap:
+        raise ValueError(f"or_render_cache failed ({m})")
+    return dict(rgb=rgb, margin=margin, records=rec[:m].copy(), pixels=pixels)
+
+
+def radiance(scene, params, o, d, start_depth: int, so=0.0, sd=0.0, nthreads: int = 0):
+    """Radiance of rays starting at recursion depth start_depth: (L [n,3], margin [n])."""
+    Lb = lib()
+    R = _rays9(o, d, None, so, sd)
+    n = len(R)
+    out = np.zeros((n, 3), np.float64)
+    m = np.zeros(n, np.float64)
+    sc, p = OScene(scene), _params(params)
+    rc = Lb.or_radiance(C.byref(sc.c), C.byref(p), R.ctypes.data, n, int(start_depth), nthreads, out.ctypes.data,
+                        m.ctypes.data)
+    if rc != 0:
+        raise ValueError(f"or_radiance failed ({rc})")
+    return out, m

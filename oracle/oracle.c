@@ -520,6 +520,11 @@ typedef struct {
     int64_t rec_n, rec_cap;
     double lloc;       /* bound on any surface's local radiance */
     double ignored;    /* worst-case RGB effect of decisions left out of the margin */
+    int cache_depth;   /* < 0: off; else hits at this depth are recorded, not shaded */
+    double* cache_rec; /* [cap][13]: list index, x[3], N_f[3], V[3], w[3] */
+    int64_t* cache_n;  /* shared record counter */
+    int64_t cache_cap;
+    int64_t list_index;
 } pctx;
 
 /* A decision whose worst-case effect on the sample's radiance is at most
@@ -631,6 +636,22 @@ static void trace(pctx* P, const oray* ray, int kind, int k, const double* w, do
     const double sn = geom_normal(sc, h.id, x, ex, ng);
     const double dn = dot3(ray->d, ng);
     const int entering = dn < 0.0;
+    if (k == P->cache_depth) {
+        /* learned form: the hit's radiance comes from the cache; record its query */
+        const int64_t slot = __atomic_fetch_add(P->cache_n, 1, __ATOMIC_RELAXED);
+        if (slot < P->cache_cap) {
+            double* q = P->cache_rec + 13 * slot;
+            q[0] = (double)P->list_index;
+            for (int i = 0; i < 3; ++i) {
+                q[1 + i] = x[i];
+                q[4 + i] = entering ? ng[i] : -ng[i];
+                q[7 + i] = -ray->d[i];
+                q[10 + i] = w[i];
+            }
+        }
+        out[0] = out[1] = out[2] = 0.0;
+        return;
+    }
     /* which side faces the ray is a discrete decision (two-sided shading) */
     note_margin(P, fmin(fabs(dn), 1e-4 * fabs(dn) / (ray->sd + sn + EA)), wmax * radiance_bound(P, k));
     for (int i = 0; i < 3; ++i) {
@@ -785,6 +806,10 @@ typedef struct {
     int32_t* counts;
     double* rgb_s;      /* [n][spp][3] per-sample radiance, or NULL */
     double* margin_s;   /* [n][spp] per-sample margin, or NULL */
+    int cache_depth;
+    double* cache_rec;
+    int64_t* cache_n;
+    int64_t cache_cap;
 } render_job;
 
 static void render_one(void* vctx, int64_t i) {
@@ -792,7 +817,8 @@ static void render_one(void* vctx, int64_t i) {
     const int D = J->p->max_depth;
     int32_t local_counts[2 * 64];
     memset(local_counts, 0, sizeof local_counts);
-    pctx P = {J->S, J->sc, J->p, MARGIN_CAP, local_counts, NULL, 0, 0, local_bound(J->sc), 0.0};
+    pctx P = {J->S, J->sc, J->p, MARGIN_CAP, local_counts, NULL, 0, 0, local_bound(J->sc), 0.0,
+              J->cache_depth, J->cache_rec, J->cache_n, J->cache_cap, i};
     const double one[3] = {1.0, 1.0, 1.0};
     double acc[3] = {0, 0, 0};
     const int64_t pix = J->pixels[i];
@@ -829,7 +855,7 @@ int or_render(const or_scene* sc, const or_camera* cam, const or_params* p, cons
     if (p->max_depth < 0 || p->max_depth > 63 || p->spp < 1) return -1;
     oscene S;
     if (oscene_init(&S, sc) != 0) return -2;
-    render_job J = {&S, sc, cam, p, pixels, rgb, ids, margin, counts, rgb_s, margin_s};
+    render_job J = {&S, sc, cam, p, pixels, rgb, ids, margin, counts, rgb_s, margin_s, -1, NULL, NULL, 0};
     run_parallel(n, nthreads, render_one, &J);
     oscene_free(&S);
     return 0;
@@ -903,7 +929,7 @@ int64_t or_ray_tree(const or_scene* sc, const or_camera* cam, const or_params* p
     if (oscene_init(&S, sc) != 0) return -2;
     int32_t counts[2 * 64];
     memset(counts, 0, sizeof counts);
-    pctx P = {&S, sc, p, MARGIN_CAP, counts, rec, 0, cap, local_bound(sc), 0.0};
+    pctx P = {&S, sc, p, MARGIN_CAP, counts, rec, 0, cap, local_bound(sc), 0.0, -1, NULL, NULL, 0, 0};
     const double one[3] = {1.0, 1.0, 1.0};
     oray r;
     or_camera_ray(cam, p, pixel, sample, r.o, r.d);
@@ -914,4 +940,58 @@ int64_t or_ray_tree(const or_scene* sc, const or_camera* cam, const or_params* p
     trace(&P, &r, 0, 0, one, rgb, &pid);
     oscene_free(&S);
     return P.rec_n;
+}
+
+/* Learned form: trace pixels with the recursion cut at cache_depth.  Hits at
+ * that depth add nothing; each is recorded as (list index, x, N_f, V,
+ * throughput w) in rec [cap][13] so that the caller adds w * max(cache(x, N_f,
+ * V), 0).  Misses at that depth still return the background.  rgb [n][3] is
+ * the radiance without the cache terms, margin [n] as or_render.  Returns the
+ * number of records (may exceed cap; only cap are written). */
+int64_t or_render_cache(const or_scene* sc, const or_camera* cam, const or_params* p, const int64_t* pixels,
+                        int64_t n, int32_t cache_depth, int32_t nthreads, double* rgb, double* margin, double* rec,
+                        int64_t cap) {
+    if (p->max_depth < 0 || p->max_depth > 63 || p->spp < 1 || cache_depth < 0) return -1;
+    oscene S;
+    if (oscene_init(&S, sc) != 0) return -2;
+    int64_t count = 0;
+    render_job J = {&S, sc, cam, p, pixels, rgb, NULL, margin, NULL, NULL, NULL, cache_depth, rec, &count, cap};
+    run_parallel(n, nthreads, render_one, &J);
+    oscene_free(&S);
+    return count;
+}
+
+typedef struct {
+    const oscene* S;
+    const or_params* p;
+    const double* rays;
+    int start_depth;
+    double* L;
+    double* margin;
+} radiance_job;
+
+static void radiance_one(void* vctx, int64_t i) {
+    radiance_job* J = (radiance_job*)vctx;
+    int32_t counts[2 * 64];
+    memset(counts, 0, sizeof counts);
+    pctx P = {J->S, J->S->in, J->p, MARGIN_CAP, counts, NULL, 0, 0, local_bound(J->S->in), 0.0, -1, NULL, NULL, 0, 0};
+    oray r;
+    load_ray(J->rays + 9 * i, &r);
+    const double one[3] = {1.0, 1.0, 1.0};
+    trace(&P, &r, 0, J->start_depth, one, J->L + 3 * i, NULL);
+    J->margin[i] = P.margin;
+}
+
+/* Radiance L(ray) of n rays that start at recursion depth start_depth (so
+ * secondary rays spawn while depth < max_depth): the training targets of the
+ * learned form.  rays [n][9] as or_closest; L [n][3]; margin [n]. */
+int or_radiance(const or_scene* sc, const or_params* p, const double* rays, int64_t n, int32_t start_depth,
+                int32_t nthreads, double* L, double* margin) {
+    if (p->max_depth < 0 || p->max_depth > 63 || start_depth < 0 || start_depth > p->max_depth) return -1;
+    oscene S;
+    if (oscene_init(&S, sc) != 0) return -2;
+    radiance_job J = {&S, p, rays, start_depth, L, margin};
+    run_parallel(n, nthreads, radiance_one, &J);
+    oscene_free(&S);
+    return 0;
 }

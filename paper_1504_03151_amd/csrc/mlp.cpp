@@ -271,14 +271,16 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __
                                                               const uint16_t* __restrict__ x,
                                                               const float* __restrict__ target, int64_t n,
                                                               float inv_3n, const uint32_t* count_p,
-                                                              float* __restrict__ dw, float* __restrict__ loss_sum) {
+                                                              int64_t count_base, float* __restrict__ dw,
+                                                              float* __restrict__ loss_sum) {
     __shared__ __attribute__((aligned(16))) GradLds S;
     stage_forward(w, S.wf);
     stage_backward(w, S.wb, S.wb6);
     const int wave = threadIdx.x >> 6;
     for (int e = threadIdx.x & 63; e < 32 * 32; e += 64) S.gy[wave][e] = 0;
     __syncthreads();
-    if (count_p) n = min((int64_t)*count_p, n);
+    // samples [count_base, count_base + n) of a batch whose valid size is *count_p
+    if (count_p) n = min(n, max((int64_t)0, (int64_t)*count_p - count_base));
     const int l = threadIdx.x & 63, h = l >> 5, r = l & 31;
     const int64_t tiles = (n + 31) / 32;
     const int64_t groups = (tiles + kGradWaves - 1) / kGradWaves;
@@ -356,6 +358,31 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __
     }
 }
 
+// Adam with the step count in device memory (*step_p holds the steps already
+// taken); k_mlp_step_inc advances it afterwards.  For frames replayed from a
+// captured graph.
+__global__ void k_mlp_adam_dev(float* __restrict__ w, uint16_t* __restrict__ wb, float* __restrict__ m,
+                               float* __restrict__ v, float* __restrict__ g, int n, float lr, float b1, float b2,
+                               float eps, const uint32_t* step_p) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float t = (float)(*step_p + 1u);
+    const float c1 = 1.0f / (1.0f - powf(b1, t)), c2 = 1.0f / (1.0f - powf(b2, t));
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    w[i] = wi;
+    wb[i] = f2bf(wi);
+    g[i] = 0.0f;
+}
+
+__global__ void k_mlp_step_inc(uint32_t* step_p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *step_p += 1u;
+}
+
 // Adam on FP32 master weights; refreshes the BF16 copy and clears the gradient.
 __global__ void k_mlp_adam(float* __restrict__ w, uint16_t* __restrict__ wb, float* __restrict__ m,
                            float* __restrict__ v, float* __restrict__ g, int n, float lr, float b1, float b2,
@@ -393,10 +420,18 @@ rt_status mlp_infer_launch(const uint16_t* w, const uint16_t* x, int64_t cap, co
 }
 
 rt_status mlp_grad_launch(const uint16_t* w, const uint16_t* x, const float* target, int64_t n, int64_t n_total,
-                          const uint32_t* count, float* dw, float* loss, hipStream_t st) {
+                          const uint32_t* count, int64_t count_base, float* dw, float* loss, hipStream_t st) {
     hipLaunchKernelGGL(k_mlp_grad, dim3(grid_for((n + 31) / 32, kGradWaves)), dim3(64 * kGradWaves), 0, st, w, x,
-                       target, n,
-                       1.0f / (3.0f * (float)n_total), count, dw, loss);
+                       target, n, 1.0f / (3.0f * (float)n_total), count, count_base, dw, loss);
+    HIP_TRY_M(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status mlp_adam_dev_launch(float* w, uint16_t* wb, float* m, float* v, float* g, const uint32_t* step_p, float lr,
+                              float b1, float b2, float eps, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_adam_dev, dim3((kParams + 255) / 256), dim3(256), 0, st, w, wb, m, v, g, kParams, lr, b1,
+                       b2, eps, step_p);
+    hipLaunchKernelGGL(k_mlp_step_inc, dim3(1), dim3(64), 0, st, const_cast<uint32_t*>(step_p));
     HIP_TRY_M(hipGetLastError());
     return RT_OK;
 }
@@ -438,7 +473,8 @@ rt_status rt_mlp_grad(const uint16_t* w_bf16, const uint16_t* x_bf16, const floa
         return RT_ERR_INVALID_ARG;
     }
     if (n == 0) return RT_OK;
-    return mlp_grad_launch(w_bf16, x_bf16, target, n, n_total, nullptr, dw, loss_sum, static_cast<hipStream_t>(stream));
+    return mlp_grad_launch(w_bf16, x_bf16, target, n, n_total, nullptr, 0, dw, loss_sum,
+                           static_cast<hipStream_t>(stream));
 }
 
 rt_status rt_mlp_adam(float* w, uint16_t* w_bf16, float* m, float* v, float* grad, int32_t step, float lr, float b1,

@@ -61,7 +61,10 @@ constexpr int kCtrShadow = 32;    // [16] shadow rays queued at depth k
 constexpr int kCtrShadowCur = 48; // [16] shadow fetch cursors
 constexpr int kCtrStatus = 64;    // overflow flags
 constexpr int kCtrDead = 65;      // padding slots of ragged tiles in the primary queue
-constexpr int kCtrWords = 128;
+constexpr int kCtrWords = 128;     // words cleared at the start of every pass
+constexpr int kCtrFrame = 128;     // frame number, written by the host before each launch
+constexpr int kCtrRec = 129;       // learned form: cache queries recorded this frame (cleared per frame)
+constexpr int kCtrTotal = 256;
 
 struct CamConst {
     double eye[3], f[3], r[3], u[3];
@@ -227,8 +230,8 @@ constexpr uint32_t kDeadRay = 0xFFFFFFFFu;
 // Primary ray for slot `slot` = local thread index `g` of a pass over one
 // scene (8x8 tiles, samples s0 .. s0 + ns - 1).  Returns false for a dead
 // padding slot.
-__device__ __forceinline__ bool gen_ray(const CamConst& cam, int s0, int ns, int tiles_x, uint32_t g, int per_sample,
-                                        uint32_t acc_off, uint32_t meta_hi, RayQ q, uint32_t slot) {
+__device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int s0, int ns, int tiles_x, uint32_t g,
+                                        int per_sample, uint32_t acc_off, uint32_t meta_hi, RayQ q, uint32_t slot) {
     const uint32_t lane = g & 63u;
     const uint32_t tile_sample = g >> 6;
     const uint32_t tile = tile_sample / (uint32_t)ns;
@@ -243,8 +246,8 @@ __device__ __forceinline__ bool gen_ray(const CamConst& cam, int s0, int ns, int
     const uint32_t pixel = (uint32_t)py * cam.W + px;
     double jx = 0.5, jy = 0.5, xi0 = 0.5, xi1 = 0.5;
     if (cam.jitter) {
-        xi0 = jitter01(cam.seed, cam.frame, pixel, (uint32_t)s, 0);
-        xi1 = jitter01(cam.seed, cam.frame, pixel, (uint32_t)s, 1);
+        xi0 = jitter01(cam.seed, frame, pixel, (uint32_t)s, 0);
+        xi1 = jitter01(cam.seed, frame, pixel, (uint32_t)s, 1);
     }
     if (cam.m > 0) {
         jx = ((double)(s % cam.m) + xi0) / cam.m;
@@ -286,7 +289,7 @@ __global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, in
         if (n_threads > cap) atomicOr(ctr + kCtrStatus, 1u);
     }
     if (g >= n_threads || g >= cap) return;
-    count_dead(!gen_ray(cam, s0, ns, tiles_x, g, per_sample, 0u, 0u, q, g), ctr);
+    count_dead(!gen_ray(cam, ctr[kCtrFrame], s0, ns, tiles_x, g, per_sample, 0u, 0u, q, g), ctr);
 }
 
 // Batched frames: one global slot space over all scenes; each thread finds
@@ -306,8 +309,8 @@ __global__ __launch_bounds__(256) void k_raygen_batch(const BatchScene* tab, int
         else hi = mid - 1;
     }
     const BatchScene& B = tab[lo];
-    const bool live = gen_ray(B.cam, 0, B.shc.spp, B.tiles_x, g - B.ray_off, B.shc.per_sample, B.shc.acc_off,
-                              (uint32_t)lo << 20, q, g);
+    const bool live = gen_ray(B.cam, B.cam.frame, 0, B.shc.spp, B.tiles_x, g - B.ray_off, B.shc.per_sample,
+                              B.shc.acc_off, (uint32_t)lo << 20, q, g);
     count_dead(!live, ctr);
 }
 
@@ -673,6 +676,177 @@ __global__ void k_resolve_batch(const BatchScene* tab, int n_scenes, const float
     B.out_rgb[(size_t)(slot - B.shc.acc_off) * 3 + (i - (uint64_t)slot * 3)] = acc[i] * B.inv_spp;
 }
 
+
+// ---------------------------------------------------------------------------
+// learned form: radiance cache below depth D_c
+// ---------------------------------------------------------------------------
+// Feature layout of one cache query (BF16, 64 values): for axis c and
+// frequency j, [12 c + 2 j] = sin(2^j pi x~_c), [12 c + 2 j + 1] = cos(...),
+// x~ = 2 (x - lo) / (hi - lo) - 1; [36..38] facing normal; [39..41] view
+// direction; [42..63] zero.
+struct CacheRec {
+    uint16_t* feats;     // [cap][64]
+    uint32_t* pix;       // [cap] accumulation slot
+    float* w;            // [cap][3] throughput
+    uint32_t* src;       // [cap] queue index of the ray at the cache depth
+    uint32_t cap;
+};
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ void write_features(uint16_t* f, V3 x, V3 nf, V3 v, const float* lo, const float* inv_ext) {
+    const float xt[3] = {2.0f * (x.x - lo[0]) * inv_ext[0] - 1.0f, 2.0f * (x.y - lo[1]) * inv_ext[1] - 1.0f,
+                         2.0f * (x.z - lo[2]) * inv_ext[2] - 1.0f};
+    uint16_t tmp[64];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float sc = 1.0f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            tmp[12 * c + 2 * j] = to_bf16(sinpif(sc * xt[c]));
+            tmp[12 * c + 2 * j + 1] = to_bf16(cospif(sc * xt[c]));
+            sc *= 2.0f;
+        }
+    }
+    tmp[36] = to_bf16(nf.x);
+    tmp[37] = to_bf16(nf.y);
+    tmp[38] = to_bf16(nf.z);
+    tmp[39] = to_bf16(v.x);
+    tmp[40] = to_bf16(v.y);
+    tmp[41] = to_bf16(v.z);
+#pragma unroll
+    for (int k = 42; k < 64; ++k) tmp[k] = 0;
+    uint4* dst = reinterpret_cast<uint4*>(f);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint4 u;
+        u.x = (uint32_t)tmp[8 * q + 0] | ((uint32_t)tmp[8 * q + 1] << 16);
+        u.y = (uint32_t)tmp[8 * q + 2] | ((uint32_t)tmp[8 * q + 3] << 16);
+        u.z = (uint32_t)tmp[8 * q + 4] | ((uint32_t)tmp[8 * q + 5] << 16);
+        u.w = (uint32_t)tmp[8 * q + 6] | ((uint32_t)tmp[8 * q + 7] << 16);
+        dst[q] = u;
+    }
+}
+
+// Shading at the cache depth: misses add the background; hits become cache
+// queries (features, accumulation slot, throughput, source ray).
+__global__ __launch_bounds__(256) void k_cache_shade(DevScene sc, ShadeConst c, RayQ qin, HitQ hit, uint32_t* ctr,
+                                                     int depth, CacheRec rec, float lo0, float lo1, float lo2,
+                                                     float ie0, float ie1, float ie2, float* acc) {
+    __shared__ uint32_t lds_res[4];
+    const uint32_t count = min(ctr[kCtrRays + depth], c.qcap);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const float lo[3] = {lo0, lo1, lo2}, ie[3] = {ie0, ie1, ie2};
+    for (uint32_t bb = blockIdx.x * blockDim.x; bb < count; bb += stride) {   // block-uniform loop
+        const uint32_t i = bb + threadIdx.x;
+        bool active = i < count;
+        uint32_t pix = 0, meta = 0;
+        int prim = -1;
+        if (active) {
+            pix = qin.pix[i];
+            active = pix != kDeadRay;
+        }
+        V3 w = v3(0, 0, 0);
+        if (active) {
+            prim = hit.prim[i];
+            meta = qin.meta[i];
+            w = v3(qin.wr[i], qin.wg[i], qin.wb[i]);
+            if (depth == 0 && c.out_ids) {
+                int oid = -1;
+                if (prim >= sc.n_bvh) oid = prim;
+                else if (prim >= 0) oid = as_int_f(sc.prims[3 * prim].w);
+                c.out_ids[c.per_sample ? (size_t)pix : (size_t)pix * c.spp + ((meta >> 4) & 0xFFFFu)] = oid;
+            }
+            if (prim < 0) {
+                atomicAdd(acc + 3 * pix + 0, w.x * c.bg[0]);
+                atomicAdd(acc + 3 * pix + 1, w.y * c.bg[1]);
+                atomicAdd(acc + 3 * pix + 2, w.z * c.bg[2]);
+            }
+        }
+        const bool query = active && prim >= 0;
+        uint32_t tot;
+        const uint32_t off = wave_scan(query ? 1u : 0u, tot);
+        const uint32_t slot = block_reserve(tot, ctr + kCtrRec, lds_res) + off;
+        if (query) {
+            if (slot >= rec.cap) {
+                atomicOr(ctr + kCtrStatus, 4u);
+                continue;
+            }
+            const V3 o = v3(qin.ox[i], qin.oy[i], qin.oz[i]);
+            const V3 d = v3(qin.dx[i], qin.dy[i], qin.dz[i]);
+            const float t = hit.t[i];
+            const V3 x = v3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
+            V3 ng;
+            if (prim >= sc.n_bvh) {
+                ng = xyz(sc.planes[prim - sc.n_bvh]);
+            } else {
+                const float4 p0 = sc.prims[3 * prim];
+                if (as_int_f(p0.w) < sc.n_spheres) {
+                    ng = (x - xyz(p0)) * sc.prims[3 * prim + 1].z;
+                    ng = ng * (1.0f / sqrtf(dot(ng, ng)));
+                } else {
+                    ng = xyz(sc.normals[prim]);
+                }
+            }
+            const V3 nf = dot(d, ng) < 0.0f ? ng : -ng;
+            write_features(rec.feats + (size_t)slot * 64, x, nf, -d, lo, ie);
+            rec.pix[slot] = pix;
+            rec.w[3 * slot + 0] = w.x;
+            rec.w[3 * slot + 1] = w.y;
+            rec.w[3 * slot + 2] = w.z;
+            rec.src[slot] = i;
+        }
+    }
+}
+
+// Training batch of this frame: n_train = min(queries, train_samples) queries
+// chosen on a stratified grid with a per-frame random offset.  Their rays (at
+// the cache depth) start the target wavefront; their features and rays are
+// kept in the cache state.
+__global__ void k_cache_select(const uint32_t* ctr, CacheRec rec, RayQ qsrc, uint32_t train_samples, int depth,
+                               RayQ qt, uint32_t* ctr_t, uint32_t* n_train_out, uint16_t* t_feats, float* t_rays,
+                               uint32_t* t_pix) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t queries = min(ctr[kCtrRec], rec.cap);
+    const uint32_t n_train = min(queries, train_samples);
+    if (j == 0) {
+        *n_train_out = n_train;
+        ctr_t[kCtrRays + depth] = n_train;
+    }
+    if (j >= n_train) return;
+    const uint32_t frame = ctr[kCtrFrame];
+    const double u = (double)(pcg_hash(pcg_hash(frame ^ 0x9e3779b9u)) >> 8) * (1.0 / 16777216.0);
+    uint32_t src = (uint32_t)(((double)j + u) * (double)queries / (double)n_train);
+    src = min(src, queries - 1u);
+    const uint32_t i = rec.src[src];
+    qt.ox[j] = qsrc.ox[i];
+    qt.oy[j] = qsrc.oy[i];
+    qt.oz[j] = qsrc.oz[i];
+    qt.dx[j] = qsrc.dx[i];
+    qt.dy[j] = qsrc.dy[i];
+    qt.dz[j] = qsrc.dz[i];
+    qt.wr[j] = 1.0f;
+    qt.wg[j] = 1.0f;
+    qt.wb[j] = 1.0f;
+    qt.pix[j] = j;
+    qt.meta[j] = (uint32_t)depth;
+    const uint4* fs = reinterpret_cast<const uint4*>(rec.feats + (size_t)src * 64);
+    uint4* fd = reinterpret_cast<uint4*>(t_feats + (size_t)j * 64);
+    for (int q = 0; q < 8; ++q) fd[q] = fs[q];
+    t_rays[6 * j + 0] = qsrc.ox[i];
+    t_rays[6 * j + 1] = qsrc.oy[i];
+    t_rays[6 * j + 2] = qsrc.oz[i];
+    t_rays[6 * j + 3] = qsrc.dx[i];
+    t_rays[6 * j + 4] = qsrc.dy[i];
+    t_rays[6 * j + 5] = qsrc.dz[i];
+    t_pix[j] = rec.pix[src];
+}
+
 __global__ void k_resolve(const float* acc, float* out, int64_t n3, float inv_spp) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n3) out[i] = acc[i] * inv_spp;
@@ -829,7 +1003,7 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     pl.scap = (uint32_t)scap;
     size_t off = 0;
     pl.off_ctr = off;
-    off = a256(off + 4 * kCtrWords);
+    off = a256(off + 4 * kCtrTotal);
     pl.nacc = (p.flags & RT_FLAG_PER_SAMPLE) ? pl.npix * p.spp : pl.npix;
     if (pl.nacc >= ((int64_t)1 << 32)) {
         why = "too many accumulation slots (pixels x spp) for per-sample output";
@@ -918,8 +1092,8 @@ struct EventPair {
 static std::mutex g_time_mu;
 static std::vector<EventPair> g_pending;
 static std::vector<hipEvent_t> g_event_pool;
-static double g_time_ms[3] = {0, 0, 0};
-static int64_t g_time_n[3] = {0, 0, 0};
+static double g_time_ms[5] = {0, 0, 0, 0, 0};
+static int64_t g_time_n[5] = {0, 0, 0, 0, 0};
 
 static hipEvent_t take_event() {
     if (!g_event_pool.empty()) {
@@ -1214,7 +1388,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
     bp.off_tab = off;
     off = a256(off + sizeof(BatchScene) * n);
     bp.off_ctr = off;
-    off = a256(off + 4 * kCtrWords);
+    off = a256(off + 4 * kCtrTotal);
     bp.off_acc = off;
     off = a256(off + 12 * (size_t)acc);
     for (int b = 0; b < 2; ++b) {
@@ -1375,6 +1549,307 @@ static rt_status launch_batch(const BatchArgs& B, hipStream_t st, bool use_graph
     return RT_OK;
 }
 
+// ---------------------------------------------------------------------------
+// learned form: host side
+// ---------------------------------------------------------------------------
+rt_status mlp_infer_launch(const uint16_t* w, const uint16_t* x, int64_t cap, const uint32_t* count, const uint32_t* pix,
+                           const float* wt, float* acc, hipStream_t st);
+rt_status mlp_grad_launch(const uint16_t* w, const uint16_t* x, const float* target, int64_t n, int64_t n_total,
+                          const uint32_t* count, int64_t count_base, float* dw, float* loss, hipStream_t st);
+rt_status mlp_adam_dev_launch(float* w, uint16_t* wb, float* m, float* v, float* g, const uint32_t* step_p, float lr,
+                              float b1, float b2, float eps, hipStream_t st);
+
+constexpr int kMlpParams = 5 * 64 * 64 + 3 * 64;
+constexpr int kTargetGrowth = 4;    // target-wavefront queue capacity per training sample
+
+static bool cache_layout(int32_t cap, rt_cache_layout& L) {
+    if (cap <= 0 || cap > (1 << 24)) return false;
+    std::memset(&L, 0, sizeof L);
+    size_t off = 0;
+    L.w_master = off;
+    off = a256(off + 4 * (size_t)kMlpParams);
+    L.w_bf16 = off;
+    off = a256(off + 2 * (size_t)kMlpParams);
+    L.m = off;
+    off = a256(off + 4 * (size_t)kMlpParams);
+    L.v = off;
+    off = a256(off + 4 * (size_t)kMlpParams);
+    L.grad = off;
+    off = a256(off + 4 * (size_t)kMlpParams);
+    L.counters = off;
+    off = a256(off + 4 * 64);
+    L.train_rays = off;
+    off = a256(off + 24 * (size_t)cap);
+    L.train_feats = off;
+    off = a256(off + 128 * (size_t)cap);
+    L.train_targets = off;
+    off = a256(off + 12 * (size_t)cap);
+    L.train_pix = off;
+    off = a256(off + 4 * (size_t)cap);
+    L.total = off;
+    L.capacity = cap;
+    return true;
+}
+
+struct CachePlan {
+    Plan base;
+    rt_cache c;            // defaults filled in
+    rt_cache_layout L;
+    uint32_t rec_cap = 0, tcap = 0, tscap = 0;
+    size_t off_rec = 0, off_tq[2] = {0, 0}, off_thit = 0, off_ts = 0, off_tctr = 0, total = 0;
+};
+
+static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_params& p, const rt_cache* cache,
+                            CachePlan& cp, std::string& why) {
+    std::memset(&cp, 0, sizeof cp);
+    if (!cache || !cache->state) {
+        why = "cache and cache->state are required";
+        return false;
+    }
+    rt_cache c = *cache;
+    if (c.mode != RT_CACHE_INFER && c.mode != RT_CACHE_TRAIN) {
+        why = "cache mode must be RT_CACHE_INFER or RT_CACHE_TRAIN";
+        return false;
+    }
+    if (c.depth <= 0) c.depth = 2;
+    if (c.full_depth <= 0) c.full_depth = 8;
+    if (c.train_samples <= 0) c.train_samples = 65536;
+    if (c.train_steps <= 0) c.train_steps = 4;
+    if (!(c.lr > 0.0f)) c.lr = 1e-3f;
+    if (!(c.b1 > 0.0f)) c.b1 = 0.9f;
+    if (!(c.b2 > 0.0f)) c.b2 = 0.999f;
+    if (!(c.eps > 0.0f)) c.eps = 1e-8f;
+    if (c.depth > RT_STATS_MAX_DEPTH - 2 || c.full_depth > RT_STATS_MAX_DEPTH - 2 || c.full_depth < c.depth ||
+        c.train_steps > 16) {
+        why = "cache depth / full_depth must be in [1, 14] with full_depth >= depth; train_steps <= 16";
+        return false;
+    }
+    bool zero = true;
+    for (int k = 0; k < 3; ++k) zero = zero && c.bounds_lo[k] == 0.0f && c.bounds_hi[k] == 0.0f;
+    if (zero)
+        for (int k = 0; k < 3; ++k) {
+            c.bounds_lo[k] = h.info.bounds_lo[k];
+            c.bounds_hi[k] = h.info.bounds_hi[k];
+        }
+    for (int k = 0; k < 3; ++k)
+        if (!(c.bounds_hi[k] > c.bounds_lo[k])) c.bounds_hi[k] = c.bounds_lo[k] + 1.0f;
+    rt_params q = p;
+    q.samples_per_pass = p.spp;   // cache frames trace every sample in one pass
+    if (!make_plan(h, cam, q, cp.base, why)) return false;
+    cp.c = c;
+    if (!cache_layout(c.train_samples, cp.L)) {
+        why = "train_samples must be in [1, 2^24]";
+        return false;
+    }
+    const Plan& pl = cp.base;
+    cp.rec_cap = pl.qcap;
+    cp.tcap = (uint32_t)std::min<uint64_t>(4000000000ull, (uint64_t)c.train_samples * kTargetGrowth);
+    cp.tscap = (uint32_t)std::min<uint64_t>(4000000000ull, (uint64_t)cp.tcap * std::max(1, h.n_lights));
+    size_t off = pl.total;
+    cp.off_rec = off;
+    off = a256(off + (size_t)cp.rec_cap * (128 + 4 + 12 + 4) + 4 * 256);
+    for (int b = 0; b < 2; ++b) {
+        cp.off_tq[b] = off;
+        off = a256(off + 11 * a256(4 * (size_t)cp.tcap));
+    }
+    cp.off_thit = off;
+    off = a256(off + 2 * a256(4 * (size_t)cp.tcap));
+    cp.off_ts = off;
+    off = a256(off + 11 * a256(4 * (size_t)cp.tscap));
+    cp.off_tctr = off;
+    off = a256(off + 4 * kCtrTotal);
+    cp.total = off;
+    return true;
+}
+
+static CacheRec cache_records(uint8_t* base, uint32_t cap) {
+    CacheRec r;
+    r.feats = reinterpret_cast<uint16_t*>(base);
+    size_t off = a256((size_t)cap * 128);
+    r.pix = reinterpret_cast<uint32_t*>(base + off);
+    off = a256(off + 4 * (size_t)cap);
+    r.w = reinterpret_cast<float*>(base + off);
+    off = a256(off + 12 * (size_t)cap);
+    r.src = reinterpret_cast<uint32_t*>(base + off);
+    r.cap = cap;
+    return r;
+}
+
+struct CacheArgs {
+    FrameArgs F;
+    CachePlan cp;
+    uint8_t* state;
+};
+
+static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
+    const FrameArgs& A = C.F;
+    const Plan& pl = A.pl;
+    const CachePlan& cp = C.cp;
+    const rt_cache& cc = cp.c;
+    uint32_t* ctr = reinterpret_cast<uint32_t*>(A.ws + pl.off_ctr);
+    float* acc = reinterpret_cast<float*>(A.ws + pl.off_acc);
+    RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
+    HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
+    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap, false);
+    int32_t* overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack);
+    const CacheRec rec = cache_records(A.ws + cp.off_rec, cp.rec_cap);
+    uint8_t* S = C.state;
+    const rt_cache_layout& L = cp.L;
+    const uint16_t* w_bf16 = reinterpret_cast<const uint16_t*>(S + L.w_bf16);
+    uint32_t* counters = reinterpret_cast<uint32_t*>(S + L.counters);
+    unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
+    unsigned long long* swork = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->shadow_node_visits) : nullptr;
+    const int cd = cc.depth;
+
+    // one bounce of the wavefront over queue set (qs, hit, shadow) with counters c_
+    auto bounce = [&](RayQ& qi, RayQ& qo, HitQ& h, ShadowQ& sh, uint32_t* c_, const ShadeConst& shc, float* acc_,
+                      int k) {
+        {
+            KernelTimer kt(A.time_kernels, st, 0);
+            if (A.count_work)
+                hipLaunchKernelGGL((k_extend<true, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, qi, h,
+                                   c_ + kCtrRays + k, c_ + kCtrRayCur + k, shc.qcap, A.chunk, overflow, work);
+            else
+                hipLaunchKernelGGL((k_extend<false, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, qi, h,
+                                   c_ + kCtrRays + k, c_ + kCtrRayCur + k, shc.qcap, A.chunk, overflow, work);
+        }
+        {
+            KernelTimer kt(A.time_kernels, st, 1);
+            hipLaunchKernelGGL(k_shade<false>, dim3(A.shade_blocks), dim3(256), 0, st, A.sc, shc, nullptr, qi, h, c_, k,
+                               qo, sh, acc_);
+        }
+        {
+            KernelTimer kt(A.time_kernels, st, 2);
+            if (A.count_work)
+                hipLaunchKernelGGL((k_shadow<true, false>), dim3(A.gs), dim3(256), 0, st, A.sc, nullptr, sh,
+                                   c_ + kCtrShadow + k, c_ + kCtrShadowCur + k, shc.scap, A.chunk, acc_, overflow,
+                                   swork);
+            else
+                hipLaunchKernelGGL((k_shadow<false, false>), dim3(A.gs), dim3(256), 0, st, A.sc, nullptr, sh,
+                                   c_ + kCtrShadow + k, c_ + kCtrShadowCur + k, shc.scap, A.chunk, acc_, overflow,
+                                   swork);
+        }
+    };
+
+    const int64_t n3 = 3 * pl.nacc;
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ctr + kCtrRec, 1);
+    const int tiles_x = (A.cam.W + 7) / 8, tiles_y = (A.cam.H + 7) / 8;
+    const uint32_t nthreads = (uint32_t)((int64_t)tiles_x * tiles_y * A.spp * 64);
+    hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, 0, A.spp, tiles_x, nthreads,
+                       q[0], ctr, pl.qcap, A.shc.per_sample);
+    for (int k = 0; k < cd; ++k) bounce(q[k & 1], q[(k + 1) & 1], hq, sq, ctr, A.shc, acc, k);
+    // depth cd: closest hits, then cache queries instead of shading
+    {
+        KernelTimer kt(A.time_kernels, st, 0);
+        hipLaunchKernelGGL((k_extend<false, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, q[cd & 1], hq,
+                           ctr + kCtrRays + cd, ctr + kCtrRayCur + cd, pl.qcap, A.chunk, overflow, nullptr);
+    }
+    const float ie[3] = {1.0f / (cc.bounds_hi[0] - cc.bounds_lo[0]), 1.0f / (cc.bounds_hi[1] - cc.bounds_lo[1]),
+                         1.0f / (cc.bounds_hi[2] - cc.bounds_lo[2])};
+    hipLaunchKernelGGL(k_cache_shade, dim3(A.shade_blocks), dim3(256), 0, st, A.sc, A.shc, q[cd & 1], hq, ctr, cd, rec,
+                       cc.bounds_lo[0], cc.bounds_lo[1], cc.bounds_lo[2], ie[0], ie[1], ie[2], acc);
+    {
+        KernelTimer kt(A.time_kernels, st, 3);
+        rt_status rs = mlp_infer_launch(w_bf16, rec.feats, rec.cap, ctr + kCtrRec, rec.pix, rec.w, acc, st);
+        if (rs != RT_OK) return rs;
+    }
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, cd);
+
+    if (cc.mode == RT_CACHE_TRAIN) {
+        KernelTimer kt(A.time_kernels, st, 4);
+        uint32_t* tctr = reinterpret_cast<uint32_t*>(A.ws + cp.off_tctr);
+        RayQ tq[2] = {ray_queue(A.ws + cp.off_tq[0], cp.tcap), ray_queue(A.ws + cp.off_tq[1], cp.tcap)};
+        HitQ th = hit_queue(A.ws + cp.off_thit, cp.tcap);
+        ShadowQ ts = shadow_queue(A.ws + cp.off_ts, cp.tscap, false);
+        float* targets = reinterpret_cast<float*>(S + L.train_targets);
+        uint16_t* t_feats = reinterpret_cast<uint16_t*>(S + L.train_feats);
+        float* t_rays = reinterpret_cast<float*>(S + L.train_rays);
+        const uint32_t T = (uint32_t)cc.train_samples;
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, tctr, kCtrWords);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counters + 2, 16);
+        hipLaunchKernelGGL(k_fill_f32, dim3((3 * T + 255) / 256), dim3(256), 0, st, targets, (int64_t)3 * T, 0.0f);
+        hipLaunchKernelGGL(k_cache_select, dim3((T + 255) / 256), dim3(256), 0, st, ctr, rec, q[cd & 1], T, cd,
+                           tq[cd & 1], tctr, counters + 1, t_feats, t_rays,
+                           reinterpret_cast<uint32_t*>(S + L.train_pix));
+        ShadeConst tc = A.shc;
+        tc.max_depth = cc.full_depth;
+        tc.spp = 1;
+        tc.per_sample = 0;
+        tc.acc_off = 0;
+        tc.out_ids = nullptr;
+        tc.qcap = cp.tcap;
+        tc.scap = cp.tscap;
+        for (int k = cd; k <= cc.full_depth; ++k) bounce(tq[k & 1], tq[(k + 1) & 1], th, ts, tctr, tc, targets, k);
+        hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, tctr, A.stats, cc.full_depth);
+        const int64_t bs = (T + cc.train_steps - 1) / cc.train_steps;
+        float* wm = reinterpret_cast<float*>(S + L.w_master);
+        uint16_t* wb = reinterpret_cast<uint16_t*>(S + L.w_bf16);
+        float* m = reinterpret_cast<float*>(S + L.m);
+        float* v = reinterpret_cast<float*>(S + L.v);
+        float* g = reinterpret_cast<float*>(S + L.grad);
+        for (int step = 0; step < cc.train_steps; ++step) {
+            rt_status rs = mlp_grad_launch(wb, t_feats + (size_t)step * bs * 64, targets + (size_t)step * bs * 3, bs, bs,
+                                           counters + 1, step * bs, g, reinterpret_cast<float*>(counters + 2 + step),
+                                           st);
+            if (rs != RT_OK) return rs;
+            rs = mlp_adam_dev_launch(wm, wb, m, v, g, counters + 0, cc.lr, cc.b1, cc.b2, cc.eps, st);
+            if (rs != RT_OK) return rs;
+        }
+    }
+    hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
+                       A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp);
+    HIP_TRY(hipGetLastError());
+    return RT_OK;
+}
+
+static rt_status launch_cached(const CacheArgs& C, hipStream_t st, bool use_graph, uint64_t uid) {
+    if (!use_graph) return enqueue_cached(C, st);
+    GraphKey key;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    const uint32_t tag = 0xCAC4Eu;
+    put(key.bytes, tag);
+    put(key.bytes, dev);
+    put(key.bytes, uid);
+    put(key.bytes, C.F.sc);
+    put(key.bytes, C.F.cam);
+    put(key.bytes, C.F.shc);
+    put(key.bytes, C.F.pl);
+    put(key.bytes, C.F.ws);
+    put(key.bytes, C.F.stats);
+    put(key.bytes, C.F.out_rgb);
+    put(key.bytes, C.F.count_work);
+    put(key.bytes, C.F.spp);
+    put(key.bytes, C.F.gx);
+    put(key.bytes, C.F.gs);
+    put(key.bytes, C.F.shade_blocks);
+    put(key.bytes, C.F.chunk);
+    put(key.bytes, C.cp);
+    put(key.bytes, C.state);
+    std::lock_guard<std::mutex> g(g_graph_mu);
+    auto it = g_graphs.find(key);
+    if (it == g_graphs.end()) {
+        GraphEntry e;
+        HIP_TRY(hipStreamCreateWithFlags(&e.cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(e.cap_stream, hipStreamCaptureModeThreadLocal));
+        rt_status rs = enqueue_cached(C, e.cap_stream);
+        hipGraph_t graph = nullptr;
+        hipError_t ee = hipStreamEndCapture(e.cap_stream, &graph);
+        if (rs != RT_OK) return rs;
+        if (ee != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ee));
+            return RT_ERR_HIP;
+        }
+        HIP_TRY(hipGraphInstantiate(&e.exec, graph, nullptr, nullptr, 0));
+        HIP_TRY(hipGraphDestroy(graph));
+        it = g_graphs.emplace(key, e).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second.exec, st));
+    return RT_OK;
+}
+
 }  // namespace mirt
 
 using namespace mirt;
@@ -1442,6 +1917,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     std::memset(&A, 0, sizeof A);
     A.sc = h.dev_view();
     camera_consts(*cam, p, A.cam);
+    A.cam.frame = 0;   // the frame number is read from the workspace, not baked into a captured graph
     for (int i = 0; i < 3; ++i) A.shc.bg[i] = p.bg[i];
     A.shc.eps = p.eps;
     A.shc.max_depth = p.max_depth;
@@ -1464,6 +1940,8 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     if (rs != RT_OK) return rs;
     hipStream_t st = static_cast<hipStream_t>(p.stream);
     const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
+    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + pl.off_ctr + 4 * kCtrFrame), (int)p.frame, 1,
+                              st));
     rs = launch_frame(A, st, graph, h.uid);
     if (rs != RT_OK) return rs;
     if (p.flags & RT_FLAG_SYNC) {
@@ -1523,6 +2001,148 @@ rt_status rt_occluded(const rt_scene* scene, const float* rays, int64_t n, uint8
     return trace_rays(scene, rays, n, nullptr, nullptr, occluded, workspace, stream, true);
 }
 
+
+rt_status rt_cache_state_layout(int32_t capacity, rt_cache_layout* out) {
+    if (!out || !cache_layout(capacity, *out)) {
+        set_error("rt_cache_state_layout: capacity must be in [1, 2^24]");
+        return RT_ERR_INVALID_ARG;
+    }
+    return RT_OK;
+}
+
+size_t rt_cache_state_bytes(int32_t capacity) {
+    rt_cache_layout L;
+    if (!cache_layout(capacity, L)) {
+        set_error("rt_cache_state_bytes: capacity must be in [1, 2^24]");
+        return 0;
+    }
+    return L.total;
+}
+
+rt_status rt_cache_init(void* state, int32_t capacity, const float* w_host, void* stream) {
+    rt_cache_layout L;
+    if (!state || !w_host || !cache_layout(capacity, L)) {
+        set_error("rt_cache_init: invalid argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    for (int i = 0; i < kMlpParams; ++i)
+        if (!std::isfinite(w_host[i])) {
+            set_error("rt_cache_init: non-finite weight");
+            return RT_ERR_INVALID_ARG;
+        }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint8_t* S = static_cast<uint8_t*>(state);
+    std::vector<uint16_t> wb(kMlpParams);
+    for (int i = 0; i < kMlpParams; ++i) {
+        uint32_t u;
+        std::memcpy(&u, &w_host[i], 4);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        wb[i] = (uint16_t)(u >> 16);
+    }
+    HIP_TRY(hipMemsetAsync(S, 0, L.total, st));
+    HIP_TRY(hipMemcpyAsync(S + L.w_master, w_host, 4 * (size_t)kMlpParams, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(S + L.w_bf16, wb.data(), 2 * (size_t)kMlpParams, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));   // the host staging vector goes out of scope
+    return RT_OK;
+}
+
+size_t rt_render_cached_workspace_bytes(const rt_scene* scene, const rt_camera* cam, const rt_params* params,
+                                        const rt_cache* cache) {
+    if (!scene || !cam || !params) {
+        set_error("rt_render_cached_workspace_bytes: NULL argument");
+        return 0;
+    }
+    CachePlan cp;
+    std::string why;
+    if (!make_cache_plan(scene->h, *cam, *params, cache, cp, why)) {
+        set_error("rt_render_cached_workspace_bytes: " + why);
+        return 0;
+    }
+    return cp.total;
+}
+
+rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt_params* params, const rt_cache* cache,
+                           float* out_rgb, int32_t* out_hit_ids) {
+    if (!scene || !cam || !params || !out_rgb) {
+        set_error("rt_render_cached: NULL argument");
+        return RT_ERR_INVALID_ARG;
+    }
+    const SceneHost& h = scene->h;
+    if (!h.dev) {
+        set_error("rt_render_cached: scene not uploaded (call rt_scene_upload)");
+        return RT_ERR_NOT_UPLOADED;
+    }
+    const rt_params& p = *params;
+    if (!std::isfinite(p.eps) || p.eps < 0.0f || !(cam->vfov_deg > 0.0f && cam->vfov_deg < 180.0f)) {
+        set_error("rt_render_cached: invalid eps or vfov");
+        return RT_ERR_INVALID_ARG;
+    }
+    CacheArgs C;
+    std::memset(&C, 0, sizeof C);
+    std::string why;
+    if (!make_cache_plan(h, *cam, p, cache, C.cp, why)) {
+        set_error("rt_render_cached: " + why);
+        return RT_ERR_INVALID_ARG;
+    }
+    if (C.cp.c.depth > p.max_depth) {
+        set_error("rt_render_cached: cache depth must not exceed max_depth");
+        return RT_ERR_INVALID_ARG;
+    }
+    if (!p.workspace || p.workspace_bytes < C.cp.total) {
+        set_error("rt_render_cached: workspace missing or smaller than rt_render_cached_workspace_bytes (" +
+                  std::to_string(C.cp.total) + ")");
+        return RT_ERR_CAPACITY;
+    }
+    if ((reinterpret_cast<uintptr_t>(p.workspace) | reinterpret_cast<uintptr_t>(out_rgb) |
+         reinterpret_cast<uintptr_t>(cache->state)) & 255) {
+        set_error("rt_render_cached: device pointers must be 256-byte aligned");
+        return RT_ERR_INVALID_ARG;
+    }
+    FrameArgs& A = C.F;
+    A.sc = h.dev_view();
+    camera_consts(*cam, p, A.cam);
+    A.cam.frame = 0;
+    for (int i = 0; i < 3; ++i) A.shc.bg[i] = p.bg[i];
+    A.shc.eps = p.eps;
+    A.shc.max_depth = p.max_depth;
+    A.shc.spp = p.spp;
+    A.shc.qcap = C.cp.base.qcap;
+    A.shc.scap = C.cp.base.scap;
+    A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
+    A.shc.acc_off = 0;
+    A.shc.out_ids = out_hit_ids;
+    A.pl = C.cp.base;
+    A.ws = static_cast<uint8_t*>(p.workspace);
+    A.stats = static_cast<rt_stats*>(p.stats);
+    A.out_rgb = out_rgb;
+    A.out_ids = out_hit_ids;
+    A.count_work = (p.flags & RT_FLAG_COUNT_WORK) != 0;
+    A.spp = p.spp;
+    A.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
+    A.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
+    C.state = static_cast<uint8_t*>(cache->state);
+    rt_status rs = frame_grids(A);
+    if (rs != RT_OK) return rs;
+    hipStream_t st = static_cast<hipStream_t>(p.stream);
+    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + A.pl.off_ctr + 4 * kCtrFrame), (int)p.frame, 1,
+                              st));
+    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
+    rs = launch_cached(C, st, graph, h.uid);
+    if (rs != RT_OK) return rs;
+    if (p.flags & RT_FLAG_SYNC) {
+        HIP_TRY(hipStreamSynchronize(st));
+        if (A.stats) {
+            uint32_t status = 0;
+            HIP_TRY(hipMemcpy(&status, &A.stats->status, 4, hipMemcpyDeviceToHost));
+            if (status) {
+                set_error("rt_render_cached: queue overflow (status " + std::to_string(status) + ")");
+                return RT_ERR_CAPACITY;
+            }
+        }
+    }
+    return RT_OK;
+}
+
 rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset) {
     std::lock_guard<std::mutex> g(g_time_mu);
     for (const EventPair& e : g_pending) {
@@ -1535,7 +2155,7 @@ rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset) {
         g_event_pool.push_back(e.b);
     }
     g_pending.clear();
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 5; ++k) {
         if (ms) ms[k] = g_time_ms[k];
         if (launches) launches[k] = g_time_n[k];
         if (reset) {

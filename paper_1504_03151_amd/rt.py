@@ -80,6 +80,20 @@ class SceneInfo(C.Structure):
                 ("build_seconds", C.c_double), ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3)]
 
 
+class CacheC(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("depth", C.c_int32), ("full_depth", C.c_int32), ("train_samples", C.c_int32),
+                ("train_steps", C.c_int32), ("lr", C.c_float), ("b1", C.c_float), ("b2", C.c_float),
+                ("eps", C.c_float), ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3),
+                ("state", C.c_void_p)]
+
+
+class CacheLayout(C.Structure):
+    _fields_ = [(k, C.c_size_t) for k in ("w_master", "w_bf16", "m", "v", "grad", "counters", "train_rays",
+                                           "train_feats", "train_targets", "train_pix", "total")] + [("capacity", C.c_int32)]
+
+
+CACHE_INFER, CACHE_TRAIN = 1, 2
+
 # every symbol include/mirt.h declares: name -> (restype, argtypes)
 _P = C.c_void_p
 SIGNATURES = {
@@ -101,6 +115,12 @@ SIGNATURES = {
     "rt_mlp_grad": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P]),
     "rt_mlp_adam": (C.c_int32, [_P, _P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
     "rt_mlp_mfma_probe": (C.c_int32, [_P, _P, _P, _P]),
+    "rt_cache_state_layout": (C.c_int32, [C.c_int32, C.POINTER(CacheLayout)]),
+    "rt_cache_state_bytes": (C.c_size_t, [C.c_int32]),
+    "rt_cache_init": (C.c_int32, [_P, C.c_int32, _P, _P]),
+    "rt_render_cached_workspace_bytes": (C.c_size_t, [_P, C.POINTER(CameraC), C.POINTER(ParamsC),
+                                                      C.POINTER(CacheC)]),
+    "rt_render_cached": (C.c_int32, [_P, C.POINTER(CameraC), C.POINTER(ParamsC), C.POINTER(CacheC), _P, _P]),
     "rt_last_error": (C.c_char_p, []),
     "rt_version": (C.c_char_p, []),
 }
@@ -385,10 +405,10 @@ def occluded(scene: Scene, rays, stream=None):
 
 def kernel_times(reset: bool = True) -> dict:
     """Totals recorded by frames rendered with FLAG_TIME_KERNELS: {kernel: (ms, launches)}."""
-    ms = (C.c_double * 3)()
-    n = (C.c_int64 * 3)()
+    ms = (C.c_double * 5)()
+    n = (C.c_int64 * 5)()
     _check(lib().rt_kernel_times(ms, n, int(reset)), "rt_kernel_times")
-    return {k: (ms[i], n[i]) for i, k in enumerate(("extend", "shade", "shadow"))}
+    return {k: (ms[i], n[i]) for i, k in enumerate(("extend", "shade", "shadow", "cache_infer", "cache_train"))}
 
 
 def make_rays(o, d, tmax=None) -> np.ndarray:
@@ -447,3 +467,100 @@ def mfma_probe(a_bits, b_bits, stream=None):
     _check(lib().rt_mlp_mfma_probe(a_bits.data_ptr(), b_bits.data_ptr(), d.data_ptr(), _stream_ptr(stream)),
            "rt_mlp_mfma_probe")
     return d
+
+
+
+class RadianceCache:
+    """Device state of the learned form: weights, Adam moments, last frame's training batch."""
+
+    def __init__(self, weights, capacity: int = 65536, device="cuda"):
+        import torch
+        L = CacheLayout()
+        _check(lib().rt_cache_state_layout(int(capacity), C.byref(L)), "rt_cache_state_layout")
+        self.layout = {k: int(getattr(L, k)) for k, _ in CacheLayout._fields_}
+        self.capacity = int(capacity)
+        self._buf = torch.empty(self.layout["total"] + 256, dtype=torch.uint8, device=device)
+        self.base = (self._buf.data_ptr() + 255) // 256 * 256
+        self._off = self.base - self._buf.data_ptr()
+        w = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float32).reshape(-1) for x in weights])
+                                 if isinstance(weights, (list, tuple)) else np.asarray(weights, np.float32))
+        assert w.size == mlp_num_params(), w.size
+        _check(lib().rt_cache_init(self.base, self.capacity, w.ctypes.data, _stream_ptr()), "rt_cache_init")
+
+    def _view(self, key, nbytes, dtype):
+        import torch
+        o = self._off + self.layout[key]
+        return self._buf[o:o + nbytes].view(dtype)
+
+    def master_weights(self):
+        import torch
+        return self._view("w_master", 4 * mlp_num_params(), torch.float32).clone()
+
+    def bf16_weights(self):
+        import torch
+        return self._view("w_bf16", 2 * mlp_num_params(), torch.int16).clone()
+
+    def counters(self) -> dict:
+        import torch
+        c = self._view("counters", 256, torch.int32).cpu().numpy()
+        return {"steps": int(c[0]), "n_train": int(c[1]), "loss_sums": c[2:18].view(np.float32).copy()}
+
+    def training_batch(self):
+        """(rays [n,6], features [n,64] f32, targets [n,3], pixel [n]) of the last trained frame (device tensors)."""
+        import torch
+        n = self.counters()["n_train"]
+        rays = self._view("train_rays", 24 * self.capacity, torch.float32).reshape(-1, 6)[:n]
+        feats = self._view("train_feats", 128 * self.capacity, torch.int16).reshape(-1, 64)[:n]
+        tg = self._view("train_targets", 12 * self.capacity, torch.float32).reshape(-1, 3)[:n]
+        pix = self._view("train_pix", 4 * self.capacity, torch.int32)[:n]
+        return rays.clone(), bf16_to_f32(feats.contiguous()), tg.clone(), pix.clone()
+
+
+class CachedRenderer(Renderer):
+    """Frames of the learned form: recursion below `depth` answered (and trained) by the network."""
+
+    def __init__(self, scene: Scene, camera, params, cache: RadianceCache, mode=CACHE_TRAIN, depth=2, full_depth=8,
+                 train_samples=None, train_steps=4, lr=1e-3, bounds=None, **kw):
+        self.cache = cache
+        self.cc = CacheC()
+        self.cc.mode, self.cc.depth, self.cc.full_depth = int(mode), int(depth), int(full_depth)
+        self.cc.train_samples = int(train_samples or cache.capacity)
+        self.cc.train_steps = int(train_steps)
+        self.cc.lr, self.cc.b1, self.cc.b2, self.cc.eps = float(lr), 0.9, 0.999, 1e-8
+        if bounds is not None:
+            self.cc.bounds_lo[:] = [float(x) for x in bounds[0]]
+            self.cc.bounds_hi[:] = [float(x) for x in bounds[1]]
+        self.cc.state = cache.base
+        super().__init__(scene, camera, params, **kw)
+
+    def _alloc(self, with_ids):
+        import torch
+        p = params_c(self.params, self.base_flags, self.samples_per_pass, self.queue_factor, self.queue_chunk)
+        n = lib().rt_render_cached_workspace_bytes(self.scene.handle, C.byref(self.cam_c), C.byref(p),
+                                                   C.byref(self.cc))
+        if n == 0:
+            raise RTError(-1, "rt_render_cached_workspace_bytes", lib().rt_last_error().decode())
+        self.ws_bytes = int(n)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        H, W = self.camera.height, self.camera.width
+        shape = (H, W, self.params.spp, 3) if self.base_flags & FLAG_PER_SAMPLE else (H, W, 3)
+        self.rgb = torch.empty(shape, dtype=torch.float32, device=self.device)
+        self.ids = torch.empty((H, W, self.params.spp), dtype=torch.int32, device=self.device) if with_ids else None
+        self.stats = torch.zeros(C.sizeof(Stats) + 64, dtype=torch.uint8, device=self.device)
+
+    def set_mode(self, mode):
+        self.cc.mode = int(mode)
+
+    def render(self, flags=0, stream=None, reset_stats=True):
+        if reset_stats:
+            self.stats.zero_()
+        if not self.graph:
+            flags |= FLAG_NO_GRAPH
+        p = params_c(self.params, flags | self.base_flags, self.samples_per_pass, self.queue_factor,
+                     self.queue_chunk)
+        p.workspace, p.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
+        p.stats = self.stats.data_ptr()
+        p.stream = _stream_ptr(stream)
+        _check(lib().rt_render_cached(self.scene.handle, C.byref(self.cam_c), C.byref(p), C.byref(self.cc),
+                                      self.rgb.data_ptr(), _ptr(self.ids)), "rt_render_cached")
+        return self.rgb, self.ids

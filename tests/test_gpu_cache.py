@@ -1,0 +1,120 @@
+"""Learned form (radiance cache below depth 2) against the oracle.
+
+* Inference: with fixed weights, the GPU frame equals the oracle's cut-off
+  render plus w * max(network(features), 0) of each of its depth-2 hits (the
+  network evaluated by oracle/mlp.py), on robust pixels.
+* Targets: each training sample's target equals the oracle's radiance of the
+  oracle's own depth-2 ray of the same pixel (matched by direction).
+* Training frames lower the loss; graph replays reproduce eager frames.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle import mlp as M
+from paper_1504_03151_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1504_03151_amd import rt as _rt
+    _rt.lib()
+    return _rt
+
+
+def _scene():
+    w = S.random_tiny(11, size=40, depth=4)     # spheres, triangles, plane, mirrors and glass
+    w.camera.height = 37
+    return w
+
+
+def test_cache_inference_matches_oracle(rt):
+    w = _scene()
+    sc = rt.Scene(w.scene).upload()
+    bounds = (np.array(sc.info["bounds_lo"]) - 1.0, np.array(sc.info["bounds_hi"]) + 1.0)
+    ws = M.init_weights(7)
+    ws[5] = np.abs(ws[5])                               # positive outputs: the cache terms are visible
+    cache = rt.RadianceCache(ws, capacity=4096)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_INFER, depth=2, bounds=bounds)
+    rgb, ids = r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert r.read_stats()["status"] == 0
+    ref = oracle.render_cache(w.scene, w.camera, w.params, 2)
+    rec = ref["records"]
+    assert len(rec) > 50
+    feats = M.encode(rec[:, 1:4], rec[:, 4:7], rec[:, 7:10], bounds[0].astype(np.float32),
+                     bounds[1].astype(np.float32))
+    y, _ = M.forward(ws, feats)
+    term = rec[:, 10:13] * np.maximum(y, 0.0)
+    img = ref["rgb"].copy()
+    cache_mag = np.zeros_like(img)
+    np.add.at(img, rec[:, 0].astype(int), term)
+    np.add.at(cache_mag, rec[:, 0].astype(int), np.abs(term))
+    rob = ref["margin"] > 1e-4
+    assert rob.mean() > 0.93
+    g = rgb.reshape(-1, 3).double().cpu().numpy()
+    err = np.abs(g - img)
+    tol = 1e-3 + 3e-2 * cache_mag
+    assert (err[rob] <= tol[rob]).all(), (err - tol)[rob].max()
+    assert (cache_mag[rob] > 1e-3).sum() > 30                      # the cache really contributes
+    # the oracle's ids are the ones of the plain frame (primary rays are unaffected)
+    full = oracle.render(w.scene, w.camera, w.params)
+    assert (ids.reshape(-1).cpu().numpy()[rob] == full["ids"][rob, 0]).all()
+
+
+def test_training_targets_match_oracle_radiance(rt):
+    w = _scene()
+    sc = rt.Scene(w.scene).upload()
+    cache = rt.RadianceCache(M.init_weights(3), capacity=2048)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2, full_depth=6,
+                          train_samples=2048, train_steps=2)
+    r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    c = cache.counters()
+    assert c["steps"] == 2 and c["n_train"] > 50
+    rays, feats, targets, pix = [t.cpu().numpy() for t in cache.training_batch()]
+    p6 = S.Params(spp=1, max_depth=6, jitter=0, seed=w.params.seed, bg=w.params.bg, eps=w.params.eps)
+    checked = 0
+    for j in range(0, len(rays), max(1, len(rays) // 120)):
+        tree, _ = oracle.ray_tree(w.scene, w.camera, w.params, int(pix[j]))
+        cand = tree[((tree[:, 0] == 1) | (tree[:, 0] == 2)) & (tree[:, 1] == 2)]
+        if not len(cand) or (tree[:, 11] <= 1e-4).any():
+            continue
+        k = int(np.argmax(cand[:, 5:8] @ rays[j, 3:6]))
+        if cand[k, 5:8] @ rays[j, 3:6] < 1 - 1e-6:
+            continue
+        L, m = oracle.radiance(w.scene, p6, cand[k, 2:5], cand[k, 5:8], 2, so=cand[k, 2:5].max() * 4e-7, sd=4e-7)
+        if m[0] <= 1e-4:
+            continue
+        np.testing.assert_allclose(targets[j], L[0], atol=1e-3, rtol=0)
+        checked += 1
+    assert checked >= 20, checked
+
+
+def test_training_frames_lower_the_loss_and_graph_replays_match(rt):
+    w = _scene()
+    sc = rt.Scene(w.scene).upload()
+    cache = rt.RadianceCache(M.init_weights(5), capacity=2048)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2, full_depth=6,
+                          train_samples=2048, train_steps=4, lr=3e-3)
+    losses = []
+    for f in range(40):
+        w.params.frame = f
+        r.render()
+        torch.cuda.synchronize()
+        c = cache.counters()
+        losses.append(float(c["loss_sums"][:4].sum()) / (3 * c["n_train"]))
+    assert np.mean(losses[-5:]) < 0.5 * np.mean(losses[:3]), losses
+    # inference frames: graph replay == eager frame, same weights
+    r.set_mode(rt.CACHE_INFER)
+    a = [t.clone() for t in r.render(rt.FLAG_SYNC)]
+    r.graph = False
+    b = r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert torch.equal(a[1], b[1]) and torch.allclose(a[0], b[0], atol=1e-5)
