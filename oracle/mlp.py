@@ -62,24 +62,6 @@ def encode(x, nf, v, lo, hi):
     return f
 
 
-def init_weights(seed: int):
-    """He-uniform FP32 master weights: [W_1 .. W_5] (64x64), W_6 (3x64).
-
-    The fan-in of W_1 counts only the 42 real inputs."""
-    rng = np.random.default_rng(seed)
-    ws = []
-    for l in range(N_HIDDEN):
-        fan = N_IN if l == 0 else WIDTH
-        b = np.sqrt(6.0 / fan)
-        w = rng.uniform(-b, b, size=(WIDTH, WIDTH))
-        if l == 0:
-            w[:, N_IN:] = 0.0
-        ws.append(w.astype(np.float32))
-    b = np.sqrt(6.0 / WIDTH)
-    ws.append(rng.uniform(-b, b, size=(N_OUT, WIDTH)).astype(np.float32))
-    return ws
-
-
 def _r(x, rounding):
     return bf16_round(x) if rounding else np.asarray(x, np.float64)
 

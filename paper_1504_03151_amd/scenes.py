@@ -371,4 +371,29 @@ def pixel_subset(cam: Camera, n: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(cam.n_pixels, size=n, replace=False)).astype(np.int64)
 
 
-WORKLOADS = {"c0": config0, "c1": config1, "c2": config2}
+def mlp_init_weights(seed: int):
+    """He-uniform FP32 initial weights of the radiance-cache network from a seeded RNG:
+    [W1 .. W5] (64 x 64, row-major out x in), W6 (3 x 64).  The fan-in of W1 counts the
+    42 real input features; its columns for the zero padding are zero."""
+    rng = np.random.default_rng(seed)
+    ws = []
+    for l in range(5):
+        fan = 42 if l == 0 else 64
+        b = math.sqrt(6.0 / fan)
+        w = rng.uniform(-b, b, size=(64, 64))
+        if l == 0:
+            w[:, 42:] = 0.0
+        ws.append(w.astype(np.float32))
+    b = math.sqrt(6.0 / 64)
+    ws.append(rng.uniform(-b, b, size=(3, 64)).astype(np.float32))
+    return ws
+
+
+def config4(seed: int = 2, **kw) -> Workload:
+    """The learned form's workload: the c2 scene, camera and samples (plain reference at depth 8)."""
+    w = config2(seed, **kw)
+    w.name = w.name.replace("c2_", "c4_cache_")
+    return w
+
+
+WORKLOADS = {"c0": config0, "c1": config1, "c2": config2, "c4": config4}

@@ -38,7 +38,7 @@ def test_cache_inference_matches_oracle(rt):
     w = _scene()
     sc = rt.Scene(w.scene).upload()
     bounds = (np.array(sc.info["bounds_lo"]) - 1.0, np.array(sc.info["bounds_hi"]) + 1.0)
-    ws = M.init_weights(7)
+    ws = S.mlp_init_weights(7)
     ws[5] = np.abs(ws[5])                               # positive outputs: the cache terms are visible
     cache = rt.RadianceCache(ws, capacity=4096)
     r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_INFER, depth=2, bounds=bounds)
@@ -71,7 +71,7 @@ def test_cache_inference_matches_oracle(rt):
 def test_training_targets_match_oracle_radiance(rt):
     w = _scene()
     sc = rt.Scene(w.scene).upload()
-    cache = rt.RadianceCache(M.init_weights(3), capacity=2048)
+    cache = rt.RadianceCache(S.mlp_init_weights(3), capacity=2048)
     r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2, full_depth=6,
                           train_samples=2048, train_steps=2)
     r.render(rt.FLAG_SYNC)
@@ -100,7 +100,7 @@ def test_training_targets_match_oracle_radiance(rt):
 def test_training_frames_lower_the_loss_and_graph_replays_match(rt):
     w = _scene()
     sc = rt.Scene(w.scene).upload()
-    cache = rt.RadianceCache(M.init_weights(5), capacity=2048)
+    cache = rt.RadianceCache(S.mlp_init_weights(5), capacity=2048)
     r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2, full_depth=6,
                           train_samples=2048, train_steps=4, lr=3e-3)
     losses = []

@@ -10,6 +10,7 @@ import pytest
 torch = pytest.importorskip("torch")
 
 from oracle import mlp as M
+from paper_1504_03151_amd import scenes as S
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +54,7 @@ def test_mfma_operand_layout(rt):
 
 def _problem(seed, n):
     rng = np.random.default_rng(seed)
-    ws = M.init_weights(seed)
+    ws = S.mlp_init_weights(seed)
     x = rng.uniform(-1, 1, size=(n, 3)) * 20
     nf = rng.normal(size=(n, 3))
     nf /= np.linalg.norm(nf, axis=1, keepdims=True)

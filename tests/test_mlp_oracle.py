@@ -7,11 +7,12 @@ special cases (zero weights, identity weights), never from the oracle itself.
 import numpy as np
 
 from oracle import mlp
+from paper_1504_03151_amd import scenes as S
 
 
 def _rand_problem(seed, n=24):
     rng = np.random.default_rng(seed)
-    ws = mlp.init_weights(seed)
+    ws = S.mlp_init_weights(seed)
     feats = rng.normal(size=(n, mlp.WIDTH))
     feats[:, mlp.N_IN:] = 0.0
     target = rng.uniform(0, 2, size=(n, 3))
@@ -97,7 +98,7 @@ def test_encoding_closed_form():
 
 def test_training_reduces_the_loss():
     rng = np.random.default_rng(5)
-    ws = [w.astype(np.float64) for w in mlp.init_weights(5)]
+    ws = [w.astype(np.float64) for w in S.mlp_init_weights(5)]
     feats = rng.uniform(-1, 1, size=(256, 64))
     feats[:, 42:] = 0.0
     target = np.abs(np.sin(3 * feats[:, :3])) + 0.2
