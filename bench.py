@@ -85,7 +85,16 @@ def bench_batch(args):
     log(f"built {len(scs)} BVHs in {time.perf_counter() - t0:.1f} s")
     for sc in scs:
         sc.upload()
-    br = rt.BatchRenderer(scs, [w.camera for w in ws], [w.params for w in ws], queue_chunk=args.queue_chunk)
+    cams, ps = [w.camera for w in ws], [w.params for w in ws]
+    chunk, tile, tuned = args.queue_chunk, 0, None
+    if not args.no_autotune:
+        from paper_1504_03151_amd import autotune
+        t0 = time.perf_counter()
+        tuned = autotune.tune(scs, cams, ps, batch=True, log=log)
+        chunk, tile = tuned["config"]["chunk"], tuned["config"]["tile"]
+        log(f"autotune {time.perf_counter() - t0:.1f} s: {tuned['config']} {tuned['ms']:.3f} ms "
+            f"(defaults {tuned['default_ms']:.3f} ms)")
+    br = rt.BatchRenderer(scs, cams, ps, queue_chunk=chunk, tile=tile)
     log(f"batch workspace {br.ws_bytes / 2 ** 30:.2f} GiB")
     br.render(rt.FLAG_SYNC)
     st = br.read_stats()
@@ -100,7 +109,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     batched_ms = (time.perf_counter() - t0) * 1e3 / args.steps
     # sequential baseline: one single-scene frame after another on the same stream (graphs cached)
-    rs = [rt.Renderer(sc, w.camera, w.params, queue_chunk=args.queue_chunk) for sc, w in zip(scs, ws)]
+    rs = [rt.Renderer(sc, w.camera, w.params, queue_chunk=chunk, tile=tile) for sc, w in zip(scs, ws)]
     for r in rs:
         r.render()
     torch.cuda.synchronize()
@@ -117,9 +126,118 @@ def bench_batch(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(batched_ms, 3),
         "sequential_ms": round(seq_ms, 3), "speedup_vs_sequential": round(seq_ms / batched_ms, 3),
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "autotune": None if tuned is None else {"config": tuned["config"], "ms": tuned["ms"],
+                                                 "default_ms": tuned["default_ms"], "trials": len(tuned["trials"])},
         "config": {"workload": f"c3_batch_{len(ws)}_scenes", "rays": rays, "shadow_rays": shadow,
                    "triangles": sum(len(w.scene.tris) for w in ws),
                    "pixels": sum(w.camera.n_pixels for w in ws)}}), flush=True)
+
+
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+# algorithmic FLOP of the radiance-cache network (42 real inputs, 4 hidden 64x64 products, 3 outputs)
+MLP_FWD_FLOP = 2 * (42 * 64 + 4 * 64 * 64 + 64 * 3)                    # 38,528 per query
+MLP_TRAIN_FLOP = MLP_FWD_FLOP + MLP_FWD_FLOP + 2 * (4 * 64 * 64 + 64 * 3)  # forward, dW, input grads: 110,208
+
+
+def bench_cache(w, sc, plain, args):
+    """Learned form vs the plain depth-8 frame on the same scene, camera, samples and frame numbers.
+
+    32 frames of online training (65,536 samples, 4 Adam steps each) warm the network up; the next 16 frames
+    are timed (training included) beside plain depth-8 frames of the same frame numbers, which are the judge
+    of the relative MSE.  Depth-2 truncation (the network replaced by zero) shows what the network gains.
+    """
+    import numpy as np
+    import torch
+    from paper_1504_03151_amd import rt, scenes
+    cache = rt.RadianceCache(scenes.mlp_init_weights(2), capacity=65536)
+    zero = rt.RadianceCache([np.zeros_like(x) for x in scenes.mlp_init_weights(0)], capacity=1024)
+    cr = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2,
+                           full_depth=w.params.max_depth, train_samples=65536, train_steps=4, lr=1e-3,
+                           queue_chunk=plain.queue_chunk, tile=plain.tile, with_ids=False)
+    log(f"cache workspace {cr.ws_bytes / 2 ** 30:.2f} GiB")
+    f0 = 1000
+    for f in range(args.cache_warmup):
+        w.params.frame = f0 + f
+        cr.render()
+    torch.cuda.synchronize()
+    c = cache.counters()
+    log(f"cache warm-up: {args.cache_warmup} frames, {c['steps']} Adam steps, last loss "
+        f"{float(c['loss_sums'][:4].sum()) / (3 * max(1, c['n_train'])):.4f}")
+
+    def rel_mse(x, ref, mask=None):
+        e = (x.double() - ref.double()) ** 2 / (ref.double() ** 2 + 0.01)
+        if mask is not None:
+            e = e[mask]
+        return float(e.mean()) if e.numel() else 0.0
+
+    def timed(renderer):
+        rt.kernel_times(reset=True)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        out = renderer.render(rt.FLAG_TIME_KERNELS)
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b), rt.kernel_times(reset=True), renderer.read_stats(), out[0]
+
+    rows = []
+    kt_c = {}
+    kt_p = {}
+    for f in range(args.cache_frames):
+        w.params.frame = f0 + args.cache_warmup + f
+        ms_c, kc, st_c, img_c = timed(cr)
+        assert st_c["status"] == 0, st_c
+        img_c = img_c.clone()
+        ms_p, kp, st_p, img_p = timed(plain)
+        assert st_p["status"] == 0, st_p
+        cr.cc.state, cr.cc.mode = zero.base, rt.CACHE_INFER
+        img_t = cr.render(rt.FLAG_SYNC | rt.FLAG_NO_GRAPH)[0]
+        cr.cc.state, cr.cc.mode = cache.base, rt.CACHE_TRAIN
+        torch.cuda.synchronize()
+        aff = ((img_p - img_t).abs() > 1e-6).any(dim=-1)
+        rows.append({"ms_cache": ms_c, "ms_plain": ms_p, "rel_mse": rel_mse(img_c, img_p),
+                     "rel_mse_affected": rel_mse(img_c, img_p, aff), "trunc_rel_mse": rel_mse(img_t, img_p),
+                     "trunc_rel_mse_affected": rel_mse(img_t, img_p, aff), "affected": float(aff.double().mean()),
+                     "queries": st_c["cache_queries"], "rays": sum(st_c["rays"]) + sum(st_c["shadow"]),
+                     "target_rays": st_c["target_rays"] + st_c["target_shadow"],
+                     "plain_rays": sum(st_p["rays"]) + sum(st_p["shadow"])})
+        for k, v in kc.items():
+            kt_c[k] = (kt_c.get(k, (0.0, 0))[0] + v[0], kt_c.get(k, (0.0, 0))[1] + v[1])
+        for k, v in kp.items():
+            kt_p[k] = (kt_p.get(k, (0.0, 0))[0] + v[0], kt_p.get(k, (0.0, 0))[1] + v[1])
+    n = len(rows)
+    med = lambda key: float(np.median([r[key] for r in rows]))
+    mean = lambda key: float(np.mean([r[key] for r in rows]))
+    ms_c, ms_p = med("ms_cache"), med("ms_plain")
+    q = mean("queries")
+    inf_ms = kt_c["cache_infer"][0] / n
+    tr_ms = kt_c["cache_train"][0] / n
+    inf_tflops = q * MLP_FWD_FLOP / (inf_ms / 1e3) / 1e12 if inf_ms > 0 else None
+    tr_tflops = 65536 * MLP_TRAIN_FLOP / (tr_ms / 1e3) / 1e12 if tr_ms > 0 else None
+    out = {
+        "ms_per_frame": round(ms_c, 3), "plain_ms_per_frame": round(ms_p, 3),
+        "speedup_vs_plain": round(ms_p / ms_c, 3),
+        "rel_mse": mean("rel_mse"), "rel_mse_affected": mean("rel_mse_affected"),
+        "truncation_rel_mse": mean("trunc_rel_mse"), "truncation_rel_mse_affected": mean("trunc_rel_mse_affected"),
+        "affected_pixel_frac": round(mean("affected"), 4),
+        "meets_target": bool(mean("rel_mse") <= 1e-2 and ms_c < ms_p),
+        "mrays_per_s": round((mean("rays") + mean("target_rays")) / (ms_c / 1e3) / 1e6, 1),
+        "rays_per_frame": int(mean("rays")), "target_rays_per_frame": int(mean("target_rays")),
+        "plain_rays_per_frame": int(mean("plain_rays")), "queries_per_frame": int(q),
+        "warmup_frames": args.cache_warmup, "frames": n, "train_samples": 65536, "train_steps": 4, "lr": 1e-3,
+        "kernel_ms_per_frame": {k: round(v[0] / n, 3) for k, v in kt_c.items()},
+        "plain_kernel_ms_per_frame": {k: round(v[0] / n, 3) for k, v in kt_p.items()},
+        "mlp_roofline": {"bound": "mfma", "kernel": "k_mlp_forward<1> (inference)",
+                         "achieved": round(inf_tflops, 2) if inf_tflops else None,
+                         "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(inf_tflops / MFMA_BF16_PEAK_TFLOPS, 4) if inf_tflops else None,
+                         "flop_per_query": MLP_FWD_FLOP, "traffic": None},
+        "mlp_train": {"achieved": round(tr_tflops, 2) if tr_tflops else None, "unit": "TFLOP/s",
+                      "flop_per_sample": MLP_TRAIN_FLOP, "ms_per_frame": round(tr_ms, 3)},
+    }
+    log(f"cache {ms_c:.2f} ms vs plain {ms_p:.2f} ms ({ms_p / ms_c:.2f}x); rel-MSE {out['rel_mse']:.2e} "
+        f"(affected {out['rel_mse_affected']:.2e}); truncation {out['truncation_rel_mse']:.2e} "
+        f"(affected {out['truncation_rel_mse_affected']:.2e}); infer {inf_tflops} TFLOP/s, train {tr_tflops} TFLOP/s")
+    return out
 
 
 def main():
@@ -134,6 +252,10 @@ def main():
     ap.add_argument("--samples-per-pass", type=int, default=0, help="0 = chosen by the library")
     ap.add_argument("--queue-chunk", type=int, default=0, help="0 = library default")
     ap.add_argument("--n-scenes", type=int, default=256, help="scenes of the c3 batch")
+    ap.add_argument("--no-cache", action="store_true", help="skip the learned-form comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="c3: keep the default tile, chunk and node layout")
+    ap.add_argument("--cache-warmup", type=int, default=32, help="online-training frames before measuring")
+    ap.add_argument("--cache-frames", type=int, default=16, help="measured learned-form frames")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (reference for HBM byte counters) and exit")
     args = ap.parse_args()
@@ -165,7 +287,15 @@ def main():
     sc = rt.Scene(w.scene)
     log(f"BVH build {time.perf_counter() - t0:.2f} s: {sc.info}")
     sc.upload()
-    r = rt.Renderer(sc, w.camera, w.params, samples_per_pass=args.samples_per_pass, queue_chunk=args.queue_chunk)
+    chunk, tile, tuned = args.queue_chunk, 0, None
+    if not args.no_autotune:
+        from paper_1504_03151_amd import autotune
+        t0 = time.perf_counter()
+        tuned = autotune.tune([sc], [w.camera], [w.params], batch=False, log=log)
+        chunk, tile = tuned["config"]["chunk"], tuned["config"]["tile"]
+        log(f"autotune {time.perf_counter() - t0:.1f} s: {tuned['config']} {tuned['ms']:.3f} ms "
+            f"(defaults {tuned['default_ms']:.3f} ms)")
+    r = rt.Renderer(sc, w.camera, w.params, samples_per_pass=args.samples_per_pass, queue_chunk=chunk, tile=tile)
     log(f"workspace {r.ws_bytes / 2 ** 30:.2f} GiB")
 
     # untimed counting frame: rays per depth and BVH work of every traversal launch
@@ -211,6 +341,11 @@ def main():
                 "avg_launch_ms": round(avg_launch_s * 1e3, 4), "bytes_per_launch": int(bytes_per_launch),
                 "kernel_ms_per_frame": {k: round(v[0] / args.steps, 3) for k, v in kt.items()}}
 
+    cache = None
+    if not args.no_cache and w.name.startswith("c2"):
+        log("learned form (radiance cache below depth 2) vs plain depth 8")
+        cache = bench_cache(w, sc, r, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -226,6 +361,9 @@ def main():
                    "spheres": len(w.scene.spheres), "lights": len(w.scene.lights),
                    "rays_per_frame": rays, "shadow_rays_per_frame": shadow, "parallelism": "single-gpu"},
         "roofline": roof,
+        "autotune": None if tuned is None else {"config": tuned["config"], "ms": tuned["ms"],
+                                                 "default_ms": tuned["default_ms"], "trials": len(tuned["trials"])},
+        "radiance_cache": cache,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

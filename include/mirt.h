@@ -82,12 +82,18 @@ typedef struct {
     int32_t n_lights;
 } rt_scene_desc;
 
+enum { RT_LAYOUT_DFS = 0, RT_LAYOUT_BFS = 1, RT_LAYOUT_TREELET = 2 };
+
 /* BVH build options; zero fields take the defaults in brackets. */
 typedef struct {
     int32_t leaf_max;     /* [4]  split while a node holds more primitives (<= 15) */
     int32_t sah_bins;     /* [32] centroid bins per axis of the binned SAH build */
     int32_t max_depth;    /* [60] deeper trees fail with RT_ERR_BVH_DEPTH (<= 61: LDS stack budget) */
-    int32_t node_layout;  /* [0]  0 = depth-first order (left child at index + 1) */
+    int32_t node_layout;  /* [0]  order of the 64-byte nodes in memory (root first in every layout):
+                             RT_LAYOUT_DFS depth-first pre-order (left child at index + 1),
+                             RT_LAYOUT_BFS breadth-first (level by level),
+                             RT_LAYOUT_TREELET blocks of up to 7 nodes (three levels of a subtree,
+                             breadth-first inside) stored contiguously, blocks in depth-first order */
 } rt_build_opts;
 
 /* Pinhole camera: vfov_deg is the vertical field of view; pixel row 0 is the
@@ -109,6 +115,8 @@ enum {
     RT_FLAG_PER_SAMPLE = 16   /* keep every sample: out_rgb is [H][W][spp][3], not averaged */
 };
 
+enum { RT_TILE_8X8 = 0, RT_TILE_16X4 = 1, RT_TILE_32X2 = 2, RT_TILE_4X16 = 3 };
+
 /* Per-frame rendering parameters. */
 typedef struct {
     int32_t spp;              /* samples per pixel (>= 1); a square count is stratified */
@@ -122,6 +130,8 @@ typedef struct {
     int32_t flags;            /* RT_FLAG_* */
     float queue_factor;       /* ray-queue capacity per pass, in primary rays (0 = 2.0) */
     int32_t queue_chunk;      /* queue entries a traversal wave takes per fetch (0 = 128; multiple of 64) */
+    int32_t tile;             /* pixels of one wave's primary rays: RT_TILE_8X8 (0), RT_TILE_16X4,
+                                 RT_TILE_32X2, RT_TILE_4X16 */
     void* workspace;          /* device, rt_render_workspace_bytes() bytes */
     size_t workspace_bytes;
     void* stats;              /* device rt_stats or NULL; accumulated, caller zeroes it */
@@ -139,6 +149,9 @@ typedef struct {
     uint64_t tri_tests;       /* ... ray/triangle tests of closest-hit queries */
     uint64_t sphere_tests;    /* ... ray/sphere tests of closest-hit queries */
     uint64_t shadow_node_visits, shadow_tri_tests, shadow_sphere_tests;
+    uint64_t cache_queries;   /* learned form: network queries (hits at the cache depth) */
+    uint64_t target_rays;     /* learned form: closest-hit queries traced for training targets */
+    uint64_t target_shadow;   /* ... and their shadow queries (not counted in rays / shadow) */
 } rt_stats;
 
 typedef struct rt_scene rt_scene;   /* opaque, host memory only */
@@ -152,6 +165,7 @@ typedef struct {
     double sah_cost;
     double build_seconds;
     float bounds_lo[3], bounds_hi[3];   /* scene bounds (spheres and triangles) */
+    int32_t node_layout;    /* RT_LAYOUT_* of the nodes */
 } rt_scene_info;
 
 /* Validate the description, build a binned-SAH binary BVH over spheres and
@@ -162,6 +176,11 @@ typedef struct {
 rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, rt_scene** out);
 void rt_destroy_scene(rt_scene* scene);
 rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* out);
+/* Reorder the nodes of a built scene into another RT_LAYOUT_* (same tree, same
+ * traversal order, so every query returns the same hit).  Drops the scene's
+ * device copy: call rt_scene_upload again before rendering.  Errors:
+ * RT_ERR_INVALID_ARG (NULL scene, unknown layout). */
+rt_status rt_scene_set_layout(rt_scene* scene, int32_t node_layout);
 
 /* Bytes of the device blob (nodes | primitives | normals | planes | materials | lights). */
 size_t rt_scene_device_bytes(const rt_scene* scene);

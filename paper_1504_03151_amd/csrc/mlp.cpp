@@ -17,6 +17,7 @@
 // sigma = swap of bits 2 and 3.  The weights of layers 2..6 are staged into
 // LDS with their input columns permuted by sigma, so no activation moves.
 #include <hip/hip_runtime.h>
+#include <atomic>
 
 #include <string>
 
@@ -401,10 +402,15 @@ __global__ void k_mlp_adam(float* __restrict__ w, uint16_t* __restrict__ wb, flo
 }
 
 static int grid_for(int64_t tiles, int per_block) {
+    static std::atomic<int> cu_count[64];   // per device, 0 = not queried yet
     int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        cus = cu_count[dev].load(std::memory_order_relaxed);
+        if (cus <= 0) {
+            int n = 0;
+            cus = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0 ? n : 256;
+            cu_count[dev].store(cus, std::memory_order_relaxed);
+        }
     }
     const int64_t need = (tiles + per_block - 1) / per_block;
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * 4));

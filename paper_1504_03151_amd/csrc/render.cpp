@@ -70,9 +70,25 @@ struct CamConst {
     double eye[3], f[3], r[3], u[3];
     double th, aspect;
     int W, H, spp, jitter, m;   // m = sqrt(spp) when spp is a perfect square > 1, else 0
+    int tw_log2;                // a wave's pixel tile is 2^tw_log2 wide and 64 / 2^tw_log2 high
     uint32_t frame;
     uint64_t seed;
 };
+
+// pixel tile of one wave's primary rays: log2 of its width (height = 64 / width)
+static int tile_log2w(int tile) {
+    static const int lw[4] = {3, 4, 5, 2};   // RT_TILE_8X8, 16X4, 32X2, 4X16
+    return lw[tile & 3];
+}
+static bool tile_ok(int tile) { return tile >= RT_TILE_8X8 && tile <= RT_TILE_4X16; }
+static int64_t tiles_x_of(int width, int tile) {
+    const int w = 1 << tile_log2w(tile);
+    return (width + w - 1) / w;
+}
+static int64_t tiles_y_of(int height, int tile) {
+    const int h = 64 >> tile_log2w(tile);
+    return (height + h - 1) / h;
+}
 
 struct ShadeConst {
     float bg[3];
@@ -220,15 +236,16 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
     if (i < n) p[i] = v;
 }
 
-// Ray slots of a pass map 1:1 to threads: a wave covers one 8x8 pixel tile of
-// one sample, so primary rays of a wave are coherent and no atomic is needed.
+// Ray slots of a pass map 1:1 to threads: a wave covers one 64-pixel tile
+// (8x8, 16x4, 32x2 or 4x16) of one sample, so primary rays of a wave are
+// coherent and no atomic is needed.
 // Lanes past the image edge (ragged tiles) write a dead ray (pixel kDeadRay)
 // that the later stages skip.  The camera ray is formed in FP64 and rounded
 // once to FP32.
 constexpr uint32_t kDeadRay = 0xFFFFFFFFu;
 
 // Primary ray for slot `slot` = local thread index `g` of a pass over one
-// scene (8x8 tiles, samples s0 .. s0 + ns - 1).  Returns false for a dead
+// scene (64-pixel tiles, samples s0 .. s0 + ns - 1).  Returns false for a dead
 // padding slot.
 __device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int s0, int ns, int tiles_x, uint32_t g,
                                         int per_sample, uint32_t acc_off, uint32_t meta_hi, RayQ q, uint32_t slot) {
@@ -237,8 +254,9 @@ __device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int
     const uint32_t tile = tile_sample / (uint32_t)ns;
     const int s = s0 + (int)(tile_sample - tile * (uint32_t)ns);
     const uint32_t ty = tile / (uint32_t)tiles_x;
-    const int px = (int)(tile - ty * (uint32_t)tiles_x) * 8 + (int)(lane & 7u);
-    const int py = (int)ty * 8 + (int)(lane >> 3);
+    const int lw = cam.tw_log2;
+    const int px = ((int)(tile - ty * (uint32_t)tiles_x) << lw) + (int)(lane & ((1u << lw) - 1u));
+    const int py = ((int)ty << (6 - lw)) + (int)(lane >> lw);
     if (px >= cam.W || py >= cam.H) {
         q.pix[slot] = kDeadRay;
         return false;
@@ -853,15 +871,28 @@ __global__ void k_resolve(const float* acc, float* out, int64_t n3, float inv_sp
 }
 
 // fold a pass's queue counters into the caller's statistics
-__global__ void k_stats(const uint32_t* ctr, rt_stats* st, int max_depth) {
+// part 0: a frame's pass; 1: a learned-form frame (also its network queries);
+// 2: the rays traced for training targets (kept apart from the image's rays)
+__global__ void k_stats(const uint32_t* ctr, rt_stats* st, int max_depth, int part) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (!st) return;
     st->status |= ctr[kCtrStatus];
+    if (part == 2) {
+        uint64_t r = 0, s = 0;
+        for (int k = 0; k <= max_depth && k < RT_STATS_MAX_DEPTH; ++k) {
+            r += ctr[kCtrRays + k];
+            s += ctr[kCtrShadow + k];
+        }
+        st->target_rays += r;
+        st->target_shadow += s;
+        return;
+    }
     st->passes += 1;
     for (int k = 0; k <= max_depth && k < RT_STATS_MAX_DEPTH; ++k) {
         st->rays[k] += (uint64_t)ctr[kCtrRays + k] - (k == 0 ? (uint64_t)ctr[kCtrDead] : 0ull);
         st->shadow[k] += (uint64_t)ctr[kCtrShadow + k];
     }
+    if (part == 1) st->cache_queries += ctr[kCtrRec];
 }
 
 // rays [n][8] -> queue; and hit buffer -> (t, original id)
@@ -980,6 +1011,10 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
         why = "max_depth must be in [0, 14]";
         return false;
     }
+    if (!tile_ok(p.tile)) {
+        why = "tile must be RT_TILE_8X8, RT_TILE_16X4, RT_TILE_32X2 or RT_TILE_4X16";
+        return false;
+    }
     pl.npix = (int64_t)cam.width * cam.height;
     if (pl.npix > ((int64_t)1 << 31)) {
         why = "too many pixels";
@@ -990,8 +1025,8 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
                                            : (int)std::max<int64_t>(1, std::min<int64_t>(p.spp, target / pl.npix));
     pl.spp_pass = spp_pass;
     pl.passes = (p.spp + spp_pass - 1) / spp_pass;
-    // ray slots of a full pass: every 8x8 tile is padded to 64 slots
-    pl.n_primary = (int64_t)((cam.width + 7) / 8) * ((cam.height + 7) / 8) * 64 * spp_pass;
+    // ray slots of a full pass: every pixel tile is padded to 64 slots
+    pl.n_primary = tiles_x_of(cam.width, p.tile) * tiles_y_of(cam.height, p.tile) * 64 * spp_pass;
     const double qf = p.queue_factor > 0.0f ? std::max(1.0f, p.queue_factor) : 2.0;
     const double qcap = std::ceil(pl.n_primary * qf);
     const double scap = qcap * std::max(1, s.n_lights);
@@ -1080,6 +1115,7 @@ static void camera_consts(const rt_camera& cam, const rt_params& p, CamConst& c)
     c.m = (p.spp > 1 && m * m == p.spp) ? m : 0;
     c.frame = p.frame;
     c.seed = p.seed;
+    c.tw_log2 = tile_log2w(p.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -1146,6 +1182,7 @@ struct FrameArgs {
     size_t lds;
     bool time_kernels;
     uint32_t chunk;             // queue entries per fetch of a persistent traversal wave
+    int tile;                   // RT_TILE_* of the primary rays
 };
 
 static rt_status frame_grids(FrameArgs& A) {
@@ -1180,7 +1217,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
 
     const int64_t n3 = 3 * pl.nacc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
-    const int tiles_x = (A.cam.W + 7) / 8, tiles_y = (A.cam.H + 7) / 8;
+    const int tiles_x = (int)tiles_x_of(A.cam.W, A.tile), tiles_y = (int)tiles_y_of(A.cam.H, A.tile);
     for (int pass = 0; pass < pl.passes; ++pass) {
         const int s0 = pass * pl.spp_pass;
         const int ns = std::min(pl.spp_pass, A.spp - s0);
@@ -1219,7 +1256,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
                                    ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow, swork);
             }
         }
-        hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth);
+        hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth, 0);
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
                        A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp);
@@ -1331,12 +1368,12 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
         }
         if (cam.width <= 0 || cam.height <= 0 || p.spp < 1 || p.spp > 65535 || p.max_depth < 0 ||
             p.max_depth > RT_STATS_MAX_DEPTH - 2 || !(cam.vfov_deg > 0.0f && cam.vfov_deg < 180.0f) ||
-            !std::isfinite(p.eps) || p.eps < 0.0f) {
+            !std::isfinite(p.eps) || p.eps < 0.0f || !tile_ok(p.tile)) {
             why = "invalid camera or parameters of scene " + std::to_string(i);
             return false;
         }
         const SceneHost& h = sc->h;
-        const int tiles_x = (cam.width + 7) / 8, tiles_y = (cam.height + 7) / 8;
+        const int64_t tiles_x = tiles_x_of(cam.width, p.tile), tiles_y = tiles_y_of(cam.height, p.tile);
         const uint64_t nr = (uint64_t)tiles_x * tiles_y * 64 * p.spp;
         const uint64_t npix = (uint64_t)cam.width * cam.height;
         const uint64_t na = per_sample ? npix * p.spp : npix;
@@ -1363,7 +1400,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
             B.ray_off = (uint32_t)rays;
             B.n_rays = (uint32_t)nr;
             B.n_acc = (uint32_t)na;
-            B.tiles_x = tiles_x;
+            B.tiles_x = (int)tiles_x;
             B.inv_spp = per_sample ? 1.0f : 1.0f / (float)p.spp;
             B.out_rgb = out_rgb[i];
         }
@@ -1505,7 +1542,7 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
                                    swork);
         }
     }
-    hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, B.stats, pl.dmax);
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, B.stats, pl.dmax, 0);
     hipLaunchKernelGGL(k_resolve_batch, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, tab, pl.n, acc, n3);
     HIP_TRY(hipGetLastError());
     return RT_OK;
@@ -1735,7 +1772,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ctr + kCtrRec, 1);
-    const int tiles_x = (A.cam.W + 7) / 8, tiles_y = (A.cam.H + 7) / 8;
+    const int tiles_x = (int)tiles_x_of(A.cam.W, A.tile), tiles_y = (int)tiles_y_of(A.cam.H, A.tile);
     const uint32_t nthreads = (uint32_t)((int64_t)tiles_x * tiles_y * A.spp * 64);
     hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, 0, A.spp, tiles_x, nthreads,
                        q[0], ctr, pl.qcap, A.shc.per_sample);
@@ -1755,10 +1792,9 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         rt_status rs = mlp_infer_launch(w_bf16, rec.feats, rec.cap, ctr + kCtrRec, rec.pix, rec.w, acc, st);
         if (rs != RT_OK) return rs;
     }
-    hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, cd);
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, cd, 1);
 
     if (cc.mode == RT_CACHE_TRAIN) {
-        KernelTimer kt(A.time_kernels, st, 4);
         uint32_t* tctr = reinterpret_cast<uint32_t*>(A.ws + cp.off_tctr);
         RayQ tq[2] = {ray_queue(A.ws + cp.off_tq[0], cp.tcap), ray_queue(A.ws + cp.off_tq[1], cp.tcap)};
         HitQ th = hit_queue(A.ws + cp.off_thit, cp.tcap);
@@ -1782,13 +1818,14 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         tc.qcap = cp.tcap;
         tc.scap = cp.tscap;
         for (int k = cd; k <= cc.full_depth; ++k) bounce(tq[k & 1], tq[(k + 1) & 1], th, ts, tctr, tc, targets, k);
-        hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, tctr, A.stats, cc.full_depth);
+        hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, tctr, A.stats, cc.full_depth, 2);
         const int64_t bs = (T + cc.train_steps - 1) / cc.train_steps;
         float* wm = reinterpret_cast<float*>(S + L.w_master);
         uint16_t* wb = reinterpret_cast<uint16_t*>(S + L.w_bf16);
         float* m = reinterpret_cast<float*>(S + L.m);
         float* v = reinterpret_cast<float*>(S + L.v);
         float* g = reinterpret_cast<float*>(S + L.grad);
+        KernelTimer kt(A.time_kernels, st, 4);   // the network's training only (targets are timed as bounces)
         for (int step = 0; step < cc.train_steps; ++step) {
             rt_status rs = mlp_grad_launch(wb, t_feats + (size_t)step * bs * 64, targets + (size_t)step * bs * 3, bs, bs,
                                            counters + 1, step * bs, g, reinterpret_cast<float*>(counters + 2 + step),
@@ -1936,6 +1973,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.spp = p.spp;
     A.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
     A.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
+    A.tile = p.tile;
     rt_status rs = frame_grids(A);
     if (rs != RT_OK) return rs;
     hipStream_t st = static_cast<hipStream_t>(p.stream);
@@ -2120,6 +2158,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     A.spp = p.spp;
     A.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
     A.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
+    A.tile = p.tile;
     C.state = static_cast<uint8_t*>(cache->state);
     rt_status rs = frame_grids(A);
     if (rs != RT_OK) return rs;

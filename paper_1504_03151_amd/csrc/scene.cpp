@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <stdexcept>
 #include <string>
 #include <thread>
 #include <vector>
@@ -198,6 +199,68 @@ struct Builder {
     }
 };
 
+// Node order in memory.  Every layout keeps the root at index 0 and only
+// renumbers inner-node references, so traversal visits the same nodes in the
+// same order and returns the same hits whatever the layout.
+constexpr size_t kTreeletNodes = 7;   // three levels of a binary subtree
+
+std::vector<int32_t> layout_order(const std::vector<Node>& nodes, int layout) {
+    std::vector<int32_t> order;
+    order.reserve(nodes.size());
+    if (nodes.empty()) return order;
+    if (layout == RT_LAYOUT_BFS) {
+        order.push_back(0);
+        for (size_t h = 0; h < order.size(); ++h) {
+            const int4 d = nodes[order[h]].d;
+            if (d.x >= 0) order.push_back(d.x);
+            if (d.y >= 0) order.push_back(d.y);
+        }
+    } else if (layout == RT_LAYOUT_TREELET) {
+        std::vector<int32_t> roots{0}, blk, below;
+        while (!roots.empty()) {
+            const int32_t r = roots.back();
+            roots.pop_back();
+            blk.assign(1, r);
+            below.clear();
+            for (size_t h = 0; h < blk.size(); ++h) {
+                const int4 d = nodes[blk[h]].d;
+                for (int32_t c : {d.x, d.y}) {
+                    if (c < 0) continue;
+                    if (blk.size() < kTreeletNodes) blk.push_back(c);
+                    else below.push_back(c);
+                }
+            }
+            order.insert(order.end(), blk.begin(), blk.end());
+            roots.insert(roots.end(), below.rbegin(), below.rend());   // left-most block next
+        }
+    } else {   // depth-first pre-order, left subtree first
+        std::vector<int32_t> st{0};
+        while (!st.empty()) {
+            const int32_t i = st.back();
+            st.pop_back();
+            order.push_back(i);
+            const int4 d = nodes[i].d;
+            if (d.y >= 0) st.push_back(d.y);
+            if (d.x >= 0) st.push_back(d.x);
+        }
+    }
+    return order;
+}
+
+void apply_layout(Node* nodes, int64_t n, int layout) {
+    std::vector<Node> old(nodes, nodes + n);
+    const std::vector<int32_t> order = layout_order(old, layout);
+    if ((int64_t)order.size() != n) throw std::runtime_error("BVH node layout: tree does not reach every node");
+    std::vector<int32_t> pos(n);
+    for (int64_t k = 0; k < n; ++k) pos[order[k]] = (int32_t)k;
+    for (int64_t k = 0; k < n; ++k) {
+        Node nd = old[order[k]];
+        if (nd.d.x >= 0) nd.d.x = pos[nd.d.x];
+        if (nd.d.y >= 0) nd.d.y = pos[nd.d.y];
+        nodes[k] = nd;
+    }
+}
+
 bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -301,9 +364,9 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         const int leaf_max = o.leaf_max > 0 ? std::min(o.leaf_max, kLeafMaxCount) : 4;
         const int bins = o.sah_bins > 1 ? std::min(o.sah_bins, 256) : 32;
         const int max_depth = o.max_depth > 0 ? std::min(o.max_depth, 61) : 60;
-        if (o.node_layout != 0) {
-            set_error("rt_build_scene: only node_layout 0 (depth-first) is implemented");
-            return RT_ERR_UNSUPPORTED;
+        if (o.node_layout < RT_LAYOUT_DFS || o.node_layout > RT_LAYOUT_TREELET) {
+            set_error("rt_build_scene: node_layout must be RT_LAYOUT_DFS, RT_LAYOUT_BFS or RT_LAYOUT_TREELET");
+            return RT_ERR_INVALID_ARG;
         }
 
         const auto t0 = std::chrono::steady_clock::now();
@@ -348,6 +411,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
             set_error("rt_build_scene: BVH deeper than max_depth " + std::to_string(max_depth));
             return RT_ERR_BVH_DEPTH;
         }
+        if (o.node_layout != RT_LAYOUT_DFS) apply_layout(nodes.data(), (int64_t)nodes.size(), o.node_layout);
         const auto t1 = std::chrono::steady_clock::now();
 
         SceneHost h;
@@ -438,6 +502,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
             I.bounds_lo[k] = root.lo[k];
             I.bounds_hi[k] = root.hi[k];
         }
+        I.node_layout = o.node_layout;
         h.uid = g_scene_uid.fetch_add(1);
         rt_scene* s = new rt_scene;
         s->h = std::move(h);
@@ -458,6 +523,25 @@ rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* out) {
     }
     *out = scene->h.info;
     return RT_OK;
+}
+
+rt_status rt_scene_set_layout(rt_scene* scene, int32_t node_layout) {
+    if (!scene || node_layout < RT_LAYOUT_DFS || node_layout > RT_LAYOUT_TREELET) {
+        set_error("rt_scene_set_layout: NULL scene or unknown node layout");
+        return RT_ERR_INVALID_ARG;
+    }
+    try {
+        SceneHost& h = scene->h;
+        apply_layout(reinterpret_cast<Node*>(h.blob.data() + h.off_nodes), h.n_nodes, node_layout);
+        h.info.node_layout = node_layout;
+        h.dev = nullptr;
+        h.dev_bytes = 0;
+        h.uid = g_scene_uid.fetch_add(1);
+        return RT_OK;
+    } catch (const std::exception& e) {
+        set_error(std::string("rt_scene_set_layout: ") + e.what());
+        return RT_ERR_INVALID_ARG;
+    }
 }
 
 size_t rt_scene_device_bytes(const rt_scene* scene) { return scene ? scene->h.blob.size() : 0; }

@@ -62,7 +62,8 @@ class ParamsC(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("jitter", C.c_int32), ("frame", C.c_uint32),
                 ("seed", C.c_uint64), ("bg", C.c_float * 3), ("eps", C.c_float),
                 ("samples_per_pass", C.c_int32), ("flags", C.c_int32), ("queue_factor", C.c_float),
-                ("queue_chunk", C.c_int32), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("queue_chunk", C.c_int32), ("tile", C.c_int32), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t),
                 ("stats", C.c_void_p), ("stream", C.c_void_p)]
 
 
@@ -71,13 +72,15 @@ class Stats(C.Structure):
                 ("rays", C.c_uint64 * STATS_MAX_DEPTH), ("shadow", C.c_uint64 * STATS_MAX_DEPTH),
                 ("node_visits", C.c_uint64), ("tri_tests", C.c_uint64), ("sphere_tests", C.c_uint64),
                 ("shadow_node_visits", C.c_uint64), ("shadow_tri_tests", C.c_uint64),
-                ("shadow_sphere_tests", C.c_uint64)]
+                ("shadow_sphere_tests", C.c_uint64), ("cache_queries", C.c_uint64), ("target_rays", C.c_uint64),
+                ("target_shadow", C.c_uint64)]
 
 
 class SceneInfo(C.Structure):
     _fields_ = [("n_nodes", C.c_int64), ("depth", C.c_int32), ("stack_size", C.c_int32),
                 ("n_leaves", C.c_int64), ("n_bvh_prims", C.c_int64), ("sah_cost", C.c_double),
-                ("build_seconds", C.c_double), ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3)]
+                ("build_seconds", C.c_double), ("bounds_lo", C.c_float * 3), ("bounds_hi", C.c_float * 3),
+                ("node_layout", C.c_int32)]
 
 
 class CacheC(C.Structure):
@@ -93,6 +96,9 @@ class CacheLayout(C.Structure):
 
 
 CACHE_INFER, CACHE_TRAIN = 1, 2
+LAYOUT_DFS, LAYOUT_BFS, LAYOUT_TREELET = 0, 1, 2
+TILE_8X8, TILE_16X4, TILE_32X2, TILE_4X16 = 0, 1, 2, 3
+TILE_SHAPES = {TILE_8X8: (8, 8), TILE_16X4: (16, 4), TILE_32X2: (32, 2), TILE_4X16: (4, 16)}
 
 # every symbol include/mirt.h declares: name -> (restype, argtypes)
 _P = C.c_void_p
@@ -100,6 +106,7 @@ SIGNATURES = {
     "rt_build_scene": (C.c_int32, [C.POINTER(SceneDesc), C.POINTER(BuildOpts), C.POINTER(C.c_void_p)]),
     "rt_destroy_scene": (None, [_P]),
     "rt_scene_get_info": (C.c_int32, [_P, C.POINTER(SceneInfo)]),
+    "rt_scene_set_layout": (C.c_int32, [_P, C.c_int32]),
     "rt_scene_device_bytes": (C.c_size_t, [_P]),
     "rt_scene_upload": (C.c_int32, [_P, _P, C.c_size_t, _P]),
     "rt_render_workspace_bytes": (C.c_size_t, [_P, C.POINTER(CameraC), C.POINTER(ParamsC)]),
@@ -194,10 +201,20 @@ class Scene:
         _check(L.rt_build_scene(C.byref(d), C.byref(opts), C.byref(h)), "rt_build_scene")
         self.handle = h
         self.blob = None
+        self._read_info()
+
+    def _read_info(self):
         info = SceneInfo()
-        _check(L.rt_scene_get_info(self.handle, C.byref(info)), "rt_scene_get_info")
+        _check(lib().rt_scene_get_info(self.handle, C.byref(info)), "rt_scene_get_info")
         self.info = {k: (list(getattr(info, k)) if k.startswith("bounds") else getattr(info, k))
                      for k, _ in SceneInfo._fields_}
+
+    def set_layout(self, node_layout: int):
+        """Reorder the BVH nodes (LAYOUT_*); the device copy is dropped, upload() again before rendering."""
+        _check(lib().rt_scene_set_layout(self.handle, int(node_layout)), "rt_scene_set_layout")
+        self.blob = None
+        self._read_info()
+        return self
 
     def __del__(self):
         try:
@@ -241,7 +258,7 @@ def camera_c(cam) -> CameraC:
     return c
 
 
-def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0, queue_chunk=0) -> ParamsC:
+def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0, queue_chunk=0, tile=0) -> ParamsC:
     q = ParamsC()
     q.spp, q.max_depth, q.jitter, q.frame = int(p.spp), int(p.max_depth), int(p.jitter), int(p.frame)
     q.seed = int(p.seed) & (2 ** 64 - 1)
@@ -251,6 +268,7 @@ def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0, queue_chunk=0) ->
     q.flags = int(flags)
     q.queue_factor = float(queue_factor)
     q.queue_chunk = int(queue_chunk)
+    q.tile = int(tile)
     return q
 
 
@@ -261,14 +279,15 @@ def stats_dict(buf) -> dict:
     return {"status": s.status, "passes": s.passes, "rays": list(s.rays), "shadow": list(s.shadow),
             "node_visits": s.node_visits, "tri_tests": s.tri_tests, "sphere_tests": s.sphere_tests,
             "shadow_node_visits": s.shadow_node_visits, "shadow_tri_tests": s.shadow_tri_tests,
-            "shadow_sphere_tests": s.shadow_sphere_tests}
+            "shadow_sphere_tests": s.shadow_sphere_tests, "cache_queries": s.cache_queries,
+            "target_rays": s.target_rays, "target_shadow": s.target_shadow}
 
 
 class Renderer:
     """Owns the device workspace, outputs and stats for repeated frames of one scene/camera."""
 
     def __init__(self, scene: Scene, camera, params, device="cuda", with_ids=True, samples_per_pass=0,
-                 queue_factor=0.0, graph=True, per_sample=False, queue_chunk=0):
+                 queue_factor=0.0, graph=True, per_sample=False, queue_chunk=0, tile=0):
         import torch
         if scene.blob is None:
             scene.upload(device)
@@ -276,13 +295,13 @@ class Renderer:
         self.device = device
         self.samples_per_pass, self.queue_factor, self.graph = samples_per_pass, queue_factor, graph
         self.base_flags = FLAG_PER_SAMPLE if per_sample else 0
-        self.queue_chunk = queue_chunk
+        self.queue_chunk, self.tile = queue_chunk, tile
         self.cam_c = camera_c(camera)
         self._alloc(with_ids)
 
     def _alloc(self, with_ids):
         import torch
-        p = params_c(self.params, self.base_flags, self.samples_per_pass, self.queue_factor)
+        p = params_c(self.params, self.base_flags, self.samples_per_pass, self.queue_factor, tile=self.tile)
         n = lib().rt_render_workspace_bytes(self.scene.handle, C.byref(self.cam_c), C.byref(p))
         if n == 0:
             raise RTError(-1, "rt_render_workspace_bytes", lib().rt_last_error().decode())
@@ -300,7 +319,7 @@ class Renderer:
         if not self.graph:
             flags |= FLAG_NO_GRAPH
         p = params_c(self.params, flags | self.base_flags, self.samples_per_pass, self.queue_factor,
-                     self.queue_chunk)
+                     self.queue_chunk, self.tile)
         p.workspace, p.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
         p.stats = self.stats.data_ptr()
         p.stream = _stream_ptr(stream)
@@ -316,7 +335,7 @@ class BatchRenderer:
     """Many scenes in one batched wavefront (rt_render_batch): one queue, one graph."""
 
     def __init__(self, scenes: Sequence[Scene], cameras, params, device="cuda", with_ids=True, queue_factor=0.0,
-                 queue_chunk=0, graph=True, per_sample=False):
+                 queue_chunk=0, graph=True, per_sample=False, tile=0):
         import torch
         n = len(scenes)
         assert n == len(cameras) == len(params) and n > 0
@@ -329,7 +348,9 @@ class BatchRenderer:
         self.queue_factor, self.queue_chunk = queue_factor, queue_chunk
         self._h = (C.c_void_p * n)(*[s.handle.value for s in scenes])
         self._cams = (CameraC * n)(*[camera_c(c) for c in cameras])
-        self._params = (ParamsC * n)(*[params_c(p, self.base_flags, 0, queue_factor, queue_chunk) for p in params])
+        tiles = list(tile) if isinstance(tile, (list, tuple)) else [tile] * n
+        self._params = (ParamsC * n)(*[params_c(p, self.base_flags, 0, queue_factor, queue_chunk, t)
+                                       for p, t in zip(params, tiles)])
         nb = lib().rt_render_batch_workspace_bytes(self._h, self._cams, self._params, n)
         if nb == 0:
             raise RTError(-1, "rt_render_batch_workspace_bytes", lib().rt_last_error().decode())
@@ -535,7 +556,7 @@ class CachedRenderer(Renderer):
 
     def _alloc(self, with_ids):
         import torch
-        p = params_c(self.params, self.base_flags, self.samples_per_pass, self.queue_factor, self.queue_chunk)
+        p = params_c(self.params, self.base_flags, self.samples_per_pass, self.queue_factor, self.queue_chunk, self.tile)
         n = lib().rt_render_cached_workspace_bytes(self.scene.handle, C.byref(self.cam_c), C.byref(p),
                                                    C.byref(self.cc))
         if n == 0:
@@ -557,7 +578,7 @@ class CachedRenderer(Renderer):
         if not self.graph:
             flags |= FLAG_NO_GRAPH
         p = params_c(self.params, flags | self.base_flags, self.samples_per_pass, self.queue_factor,
-                     self.queue_chunk)
+                     self.queue_chunk, self.tile)
         p.workspace, p.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
         p.stats = self.stats.data_ptr()
         p.stream = _stream_ptr(stream)

@@ -133,3 +133,50 @@ def test_bvh_info_and_work_counts_are_sane():
     t, ids, work = s.host_trace(rt.make_rays(o, d), with_work=True)
     # a BVH visits far fewer primitives than brute force
     assert work[:, 1].mean() < 0.01 * len(w.scene.tris)
+
+
+@pytest.mark.parametrize("layout", [rt.LAYOUT_BFS, rt.LAYOUT_TREELET])
+def test_node_layouts_keep_every_hit_and_every_traversal_step(layout):
+    """A node layout only renumbers nodes: the same rays must see the same hits (bit-equal t and id) and fetch
+    the same number of nodes and primitives as in depth-first order, for closest and any hit."""
+    w = S.config1(width=64, height=36, grid=96)
+    base = rt.Scene(w.scene)
+    other = rt.Scene(w.scene, node_layout=layout)
+    assert other.info["node_layout"] == layout and base.info["node_layout"] == rt.LAYOUT_DFS
+    assert other.info["n_nodes"] == base.info["n_nodes"] and other.info["depth"] == base.info["depth"]
+    rng = np.random.default_rng(7)
+    o = rng.uniform(-100, 100, (4000, 3)) * [1, 0, 1] + [0, 40, 0]
+    d = rng.normal(size=(4000, 3)) - [0, 1.5, 0]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    for any_hit in (False, True):
+        R = rt.make_rays(o, d, 150.0 if any_hit else None)
+        t0, i0, w0 = base.host_trace(R, any_hit=any_hit, with_work=True)
+        t1, i1, w1 = other.host_trace(R, any_hit=any_hit, with_work=True)
+        assert (i0 >= 0).mean() > 0.3
+        np.testing.assert_array_equal(i0, i1)
+        np.testing.assert_array_equal(t0, t1)
+        np.testing.assert_array_equal(w0, w1)
+    # re-layout of a built scene, and back: identical again; the device copy is dropped
+    other.set_layout(rt.LAYOUT_DFS)
+    assert other.info["node_layout"] == rt.LAYOUT_DFS and other.blob is None
+    R = rt.make_rays(o, d)
+    np.testing.assert_array_equal(base.host_trace(R)[1], other.host_trace(R)[1])
+    with pytest.raises(rt.RTError, match="INVALID_ARG"):
+        other.set_layout(3)
+    with pytest.raises(rt.RTError, match="INVALID_ARG"):
+        rt.Scene(w.scene, node_layout=-1)
+
+
+def test_tile_shapes_are_validated_and_size_the_workspace():
+    import ctypes as C
+    w = S.config0()
+    s = rt.Scene(w.scene)
+    cam = rt.camera_c(w.camera)
+    sizes = []
+    for tile in (rt.TILE_8X8, rt.TILE_16X4, rt.TILE_32X2, rt.TILE_4X16):
+        p = rt.params_c(w.params, tile=tile)
+        sizes.append(rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)))
+    assert all(n > 0 for n in sizes)
+    p = rt.params_c(w.params, tile=4)
+    assert rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)) == 0
+    assert b"tile" in rt.lib().rt_last_error()

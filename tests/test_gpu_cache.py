@@ -118,3 +118,30 @@ def test_training_frames_lower_the_loss_and_graph_replays_match(rt):
     b = r.render(rt.FLAG_SYNC)
     torch.cuda.synchronize()
     assert torch.equal(a[1], b[1]) and torch.allclose(a[0], b[0], atol=1e-5)
+
+
+def test_trained_network_beats_depth2_truncation(rt):
+    """What the network gains: after online training, the learned-form image is closer (relative MSE) to the
+    oracle's full-depth image than the same frame cut off at depth 2 without the network (parity unpinned:
+    training is order- and rounding-dependent, so only this gain is asserted)."""
+    w = _scene()
+    sc = rt.Scene(w.scene).upload()
+    cache = rt.RadianceCache(S.mlp_init_weights(9), capacity=2048)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2,
+                          full_depth=w.params.max_depth, train_samples=2048, train_steps=4, lr=3e-3)
+    for f in range(80):
+        w.params.frame = f
+        r.render()
+    r.set_mode(rt.CACHE_INFER)
+    rgb, _ = r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    img = rgb.reshape(-1, 3).double().cpu().numpy()
+    full = oracle.render(w.scene, w.camera, w.params)["rgb"]
+    trunc = oracle.render_cache(w.scene, w.camera, w.params, 2)["rgb"]
+    aff = (np.abs(full - trunc) > 1e-6).any(axis=1)
+    assert aff.sum() > 50, aff.sum()
+    e_net = M.rel_mse(img[aff], full[aff])
+    e_cut = M.rel_mse(trunc[aff], full[aff])
+    print(f"affected pixels {aff.sum()}: rel-MSE network {e_net:.3e}, truncation {e_cut:.3e}")
+    assert e_net < 0.5 * e_cut, (e_net, e_cut)
+    assert M.rel_mse(img, full) < M.rel_mse(trunc, full)
