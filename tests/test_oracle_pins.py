@@ -365,3 +365,53 @@ def test_config0_is_mostly_robust():
     out = oracle.render(w.scene, w.camera, w.params)
     assert (out["margin"] > 1e-4).mean() >= 0.99
     assert 0.3 < (out["ids"][:, 0] >= 0).mean() < 0.8
+
+
+# ---------------------------------------------------------------- learned form: the cut-off at a depth
+
+def test_cut_off_render_plus_exact_depth2_radiance_is_the_full_render():
+    """Whitted radiance is linear in what the depth-2 rays return: the full image equals the image cut off at
+    depth 2 plus, for every depth-2 hit, its path weight times the radiance traced from there.  Pins the
+    cut-off's depth, its weights and its background handling (a miss at depth 2 still returns bg) against
+    the plain recursion and the per-ray radiance entry."""
+    w = S.random_tiny(11, size=40, depth=4)
+    w.camera.height = 37
+    full = oracle.render(w.scene, w.camera, w.params)
+    cut = oracle.render_cache(w.scene, w.camera, w.params, 2)
+    rec = cut["records"]
+    assert len(rec) > 50
+    x, v, wt = rec[:, 1:4], rec[:, 7:10], rec[:, 10:13]
+    d = -v
+    L, m = oracle.radiance(w.scene, w.params, x - 1e-2 * d, d, 2)      # restart just before each depth-2 hit
+    idx = rec[:, 0].astype(int)
+    recon = cut["rgb"].copy()
+    np.add.at(recon, idx, wt * L)
+    ok = (full["margin"] > 1e-4) & (cut["margin"] > 1e-4)
+    bad = np.zeros(len(ok), bool)
+    bad[idx[m <= 1e-4]] = True
+    ok &= ~bad
+    assert ok.mean() > 0.9
+    _close(recon[ok], full["rgb"][ok], atol=1e-9)
+    # the cut-off really removes something on the pixels with depth-2 hits, and nothing elsewhere
+    touched = np.zeros(len(ok), bool)
+    touched[idx] = True
+    assert (np.abs(full["rgb"] - cut["rgb"]).max(axis=1)[ok & touched] > 1e-6).mean() > 0.5
+    _close(cut["rgb"][ok & ~touched & (full["counts"][:, 2, 0] == 0)],
+           full["rgb"][ok & ~touched & (full["counts"][:, 2, 0] == 0)], atol=1e-12)
+
+
+def test_cut_off_below_the_maximum_depth_changes_nothing():
+    w = S.random_tiny(5, size=24, depth=3)
+    full = oracle.render(w.scene, w.camera, w.params)
+    cut = oracle.render_cache(w.scene, w.camera, w.params, 4)
+    assert len(cut["records"]) == 0
+    _close(cut["rgb"], full["rgb"], atol=0)
+
+
+def test_per_ray_radiance_of_camera_rays_is_the_pixel():
+    w = S.config0()
+    pix = S.pixel_subset(w.camera, 300, 4)
+    out = oracle.render(w.scene, w.camera, w.params, pix)
+    o, d = oracle.camera_rays(w.camera, w.params, pix)
+    L, m = oracle.radiance(w.scene, w.params, o, d, 0)
+    _close(L, out["rgb"], atol=0)
