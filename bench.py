@@ -66,6 +66,11 @@ def cpu_baseline(w, budget_s: float, seed: int = 5):
                       f"{elapsed:.1f} s, FP64 brute force over every primitive, no BVH)"}
 
 
+def fixed_config(args) -> bool:
+    """Tile, queue chunk and node layout all given on the command line: nothing to tune."""
+    return args.tile is not None and args.layout is not None and args.queue_chunk > 0
+
+
 def build_scenes(ws, rt, threads=16):
     import concurrent.futures as cf
     with cf.ThreadPoolExecutor(threads) as ex:
@@ -86,8 +91,11 @@ def bench_batch(args):
     for sc in scs:
         sc.upload()
     cams, ps = [w.camera for w in ws], [w.params for w in ws]
-    chunk, tile, tuned = args.queue_chunk, 0, None
-    if not args.no_autotune:
+    chunk, tile, tuned = args.queue_chunk, args.tile or 0, None
+    if args.layout:
+        for sc in scs:
+            sc.set_layout(args.layout).upload()
+    if not (args.no_autotune or fixed_config(args)):
         from paper_1504_03151_amd import autotune
         t0 = time.perf_counter()
         tuned = autotune.tune(scs, cams, ps, batch=True, log=log)
@@ -253,7 +261,12 @@ def main():
     ap.add_argument("--queue-chunk", type=int, default=0, help="0 = library default")
     ap.add_argument("--n-scenes", type=int, default=256, help="scenes of the c3 batch")
     ap.add_argument("--no-cache", action="store_true", help="skip the learned-form comparison")
-    ap.add_argument("--no-autotune", action="store_true", help="c3: keep the default tile, chunk and node layout")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the given (or default) tile, queue chunk and node layout instead of tuning them")
+    ap.add_argument("--tile", type=int, default=None, help="primary-ray tile (0 8x8, 1 16x4, 2 32x2, 3 4x16); "
+                                                           "with --layout and --queue-chunk: no tuning")
+    ap.add_argument("--layout", type=int, default=None, help="BVH node layout (0 depth-first, 1 breadth-first, "
+                                                             "2 treelets)")
     ap.add_argument("--cache-warmup", type=int, default=32, help="online-training frames before measuring")
     ap.add_argument("--cache-frames", type=int, default=16, help="measured learned-form frames")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -287,8 +300,10 @@ def main():
     sc = rt.Scene(w.scene)
     log(f"BVH build {time.perf_counter() - t0:.2f} s: {sc.info}")
     sc.upload()
-    chunk, tile, tuned = args.queue_chunk, 0, None
-    if not args.no_autotune:
+    chunk, tile, tuned = args.queue_chunk, args.tile or 0, None
+    if args.layout:
+        sc.set_layout(args.layout).upload()
+    if not (args.no_autotune or fixed_config(args)):
         from paper_1504_03151_amd import autotune
         t0 = time.perf_counter()
         tuned = autotune.tune([sc], [w.camera], [w.params], batch=False, log=log)
@@ -359,7 +374,8 @@ def main():
         "config": {"workload": w.name, "width": w.camera.width, "height": w.camera.height, "spp": w.params.spp,
                    "max_depth": w.params.max_depth, "triangles": len(w.scene.tris),
                    "spheres": len(w.scene.spheres), "lights": len(w.scene.lights),
-                   "rays_per_frame": rays, "shadow_rays_per_frame": shadow, "parallelism": "single-gpu"},
+                   "rays_per_frame": rays, "shadow_rays_per_frame": shadow, "parallelism": "single-gpu",
+                   "tile": rt.TILE_SHAPES[tile], "queue_chunk": chunk or 128, "node_layout": sc.info["node_layout"]},
         "roofline": roof,
         "autotune": None if tuned is None else {"config": tuned["config"], "ms": tuned["ms"],
                                                  "default_ms": tuned["default_ms"], "trials": len(tuned["trials"])},
