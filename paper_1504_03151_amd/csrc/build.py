@@ -46,13 +46,13 @@ def _stale(obj: str, src: str) -> bool:
     return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
 
 
-def build(jobs: int = 0, verbose: bool = False, force: bool = True) -> str:
-    os.makedirs(OBJDIR, exist_ok=True)
+def build(jobs: int = 0, verbose: bool = False, force: bool = True, out: str = OUT, objdir: str = OBJDIR) -> str:
+    os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
     objs, cmds = [], []
     for s in SOURCES:
         src = os.path.join(HERE, s)
-        obj = os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o")
+        obj = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
         objs.append(obj)
         if force or _stale(obj, src):
             cmds.append([cc] + COMMON + ["-c", src, "-o", obj])
@@ -68,11 +68,11 @@ def build(jobs: int = 0, verbose: bool = False, force: bool = True) -> str:
 
     with cf.ThreadPoolExecutor(max_workers=jobs or min(8, os.cpu_count() or 1)) as ex:
         list(ex.map(run, cmds))
-    tmp = OUT + ".tmp"
+    tmp = out + ".tmp"
     link = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + ["-lamdhip64"]
     run(link)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
@@ -80,5 +80,7 @@ if __name__ == "__main__":
     ap.add_argument("--jobs", type=int, default=0)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--incremental", action="store_true")
+    ap.add_argument("--out", default=OUT, help="library path (default: in-tree libmirt.so)")
+    ap.add_argument("--objdir", default=OBJDIR)
     a = ap.parse_args()
-    print(build(a.jobs, a.verbose, force=not a.incremental))
+    print(build(a.jobs, a.verbose, force=not a.incremental, out=os.path.abspath(a.out), objdir=a.objdir))

@@ -154,6 +154,7 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t n_lane, uint32_t* tail
 struct LdsStack {
     int32_t* p;   // this lane's column
     int sp;
+    static __device__ bool wave_all(bool v) { return __all(v); }
     __device__ void reset() {
         p[0] = kStackDone;
         sp = 1;
@@ -185,6 +186,7 @@ struct SplitStack {
     int32_t* g;      // overflow column of this thread (stride = threads of the grid)
     uint32_t gstride;
     int sp;
+    static __device__ bool wave_all(bool v) { return __all(v); }   // every active lane of the wave
     __device__ void reset() {
         p[0] = kStackDone;
         sp = 1;

@@ -260,9 +260,14 @@ HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& 
             if (ANY) return h;
         }
     }
+    // While-while traversal with postponed leaves: a lane that reaches a leaf
+    // keeps it and goes on descending until every active lane of the wave
+    // holds a leaf (Stack::wave_all), then the wave tests leaves together, so
+    // fewer lanes idle in the primitive loop.  Leaf order changes the work,
+    // never the result (closest hit with the id tie-break, or any hit).
     stk.reset();
-    int32_t node = 0;
-    for (;;) {
+    int32_t node = 0, leaf = 0;   // leaf 0 = none (the root is always an inner node)
+    while (node != kStackDone) {
         while (node >= 0) {
             const Node* n = s.nodes + node;
             const float4 a = n->a, b = n->b, c = n->c;
@@ -287,28 +292,39 @@ HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& 
             } else {
                 node = stk.pop();
             }
+            if (node < 0 && node != kStackDone && leaf == 0) {
+                leaf = node;
+                node = stk.pop();
+            }
+            if (Stack::wave_all(leaf != 0)) break;
         }
-        if (node == kStackDone) break;
-        const int32_t first = leaf_first(node), cnt = leaf_count(node);
-        for (int i = first; i < first + cnt; ++i) {
-            const float4 p0 = s.prims[3 * i];
-            const int id = as_int_f(p0.w);
-            float t;
-            if (id < s.n_spheres) {
-                if (COUNT) work.spheres++;
-                t = sphere_t(r, p0, s.prims[3 * i + 1]);
+        while (leaf != 0) {
+            const int32_t first = leaf_first(leaf), cnt = leaf_count(leaf);
+            for (int i = first; i < first + cnt; ++i) {
+                const float4 p0 = s.prims[3 * i];
+                const int id = as_int_f(p0.w);
+                float t;
+                if (id < s.n_spheres) {
+                    if (COUNT) work.spheres++;
+                    t = sphere_t(r, p0, s.prims[3 * i + 1]);
+                } else {
+                    if (COUNT) work.tris++;
+                    t = tri_t(r, p0, s.prims[3 * i + 1], s.prims[3 * i + 2]);
+                }
+                if (t > 0.0f && (t < h.t || (t == h.t && h.prim >= 0 && id < h.id))) {
+                    h.t = t;
+                    h.prim = i;
+                    h.id = id;
+                    if (ANY) return h;
+                }
+            }
+            if (node < 0 && node != kStackDone) {
+                leaf = node;
+                node = stk.pop();
             } else {
-                if (COUNT) work.tris++;
-                t = tri_t(r, p0, s.prims[3 * i + 1], s.prims[3 * i + 2]);
-            }
-            if (t > 0.0f && (t < h.t || (t == h.t && h.prim >= 0 && id < h.id))) {
-                h.t = t;
-                h.prim = i;
-                h.id = id;
-                if (ANY) return h;
+                leaf = 0;
             }
         }
-        node = stk.pop();
     }
     return h;
 }

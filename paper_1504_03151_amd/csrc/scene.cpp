@@ -576,6 +576,7 @@ namespace {
 struct HostStack {
     int32_t v[kMaxStack];
     int sp = 0;
+    static bool wave_all(bool v) { return v; }   // one ray at a time
     void reset() {
         v[0] = kStackDone;
         sp = 1;

@@ -124,7 +124,7 @@ def test_trained_network_beats_depth2_truncation(rt):
     """What the network gains: after online training, the learned-form image is closer (relative MSE) to the
     oracle's full-depth image than the same frame cut off at depth 2 without the network (parity unpinned:
     training is order- and rounding-dependent, so only this gain is asserted)."""
-    w = _scene()
+    w = S.random_tiny(7, size=64, depth=4)          # 176 pixels change when the recursion is cut at depth 2
     sc = rt.Scene(w.scene).upload()
     cache = rt.RadianceCache(S.mlp_init_weights(9), capacity=2048)
     r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2,
@@ -139,7 +139,7 @@ def test_trained_network_beats_depth2_truncation(rt):
     full = oracle.render(w.scene, w.camera, w.params)["rgb"]
     trunc = oracle.render_cache(w.scene, w.camera, w.params, 2)["rgb"]
     aff = (np.abs(full - trunc) > 1e-6).any(axis=1)
-    assert aff.sum() > 50, aff.sum()
+    assert aff.sum() > 150, aff.sum()
     e_net = M.rel_mse(img[aff], full[aff])
     e_cut = M.rel_mse(trunc[aff], full[aff])
     print(f"affected pixels {aff.sum()}: rel-MSE network {e_net:.3e}, truncation {e_cut:.3e}")
