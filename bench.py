@@ -66,6 +66,34 @@ def cpu_baseline(w, budget_s: float, seed: int = 5):
                       f"{elapsed:.1f} s, FP64 brute force over every primitive, no BVH)"}
 
 
+KERNEL_SOURCES = ["paper_1504_03151_amd/csrc/rt_common.h", "paper_1504_03151_amd/csrc/render.cpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(kernel, workload, tile, layout, chunk):
+    """HBM bytes per launch measured by rocprofv3 (FETCH_SIZE, WRITE_SIZE) for this kernel, workload and setting,
+    from the committed profile summaries; None when none matches or the kernel sources changed since."""
+    import glob
+    want = {"kernel": kernel, "workload": workload, "tile": tile, "layout": layout, "queue_chunk": chunk,
+            "source_sha256_16": kernel_source_hash()}
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(f) as fh:
+            for line in fh:
+                if line.startswith("traffic-record:"):
+                    rec = json.loads(line.split(":", 1)[1])
+                    if all(rec.get(k) == v for k, v in want.items()):
+                        return int(rec["bytes_per_launch"])
+    return None
+
+
 def fixed_config(args) -> bool:
     """Tile, queue chunk and node layout all given on the command line: nothing to tune."""
     return args.tile is not None and args.layout is not None and args.queue_chunk > 0
@@ -351,8 +379,9 @@ def main():
         avg_launch_s = kt[dom][0] / 1e3 / kt[dom][1]
         bytes_per_launch = per[dom] / launches_per_frame
         achieved = bytes_per_launch / avg_launch_s / 1e9
+        traffic = traffic_record(f"k_{dom}", w.name, tile, sc.info["node_layout"], chunk or 128)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": f"k_{dom}",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": f"k_{dom}",
                 "avg_launch_ms": round(avg_launch_s * 1e3, 4), "bytes_per_launch": int(bytes_per_launch),
                 "kernel_ms_per_frame": {k: round(v[0] / args.steps, 3) for k, v in kt.items()}}
 
