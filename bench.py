@@ -8,7 +8,7 @@ wavefront pass, bounce and shadow query).  Inputs (scene blob) are resident in
 HBM before the timed region.
 
 Prints ONE JSON line.  roofline: the dominant traversal kernel's algorithmic
-bytes (64 B per BVH node fetched + 48 B per triangle record + 32 B per sphere,
+bytes (64 B per binary BVH node fetched, 128 B per four-wide node, + 48 B per triangle record + 32 B per sphere,
 counted by an untimed counting frame) divided by its average launch time from
 HIP events recorded on the launch stream during the timed frames.
 cpu_baseline: the FP64 brute-force oracle on a bounded pixel sample of the
@@ -370,9 +370,10 @@ def main():
 
     roof = None
     if not args.graph:
+        nb = 128 if sc.info["node_layout"] == rt.LAYOUT_BVH4 else 64      # bytes per node fetch
         per = {
-            "extend": 64 * cst["node_visits"] + 48 * cst["tri_tests"] + 32 * cst["sphere_tests"],
-            "shadow": 64 * cst["shadow_node_visits"] + 48 * cst["shadow_tri_tests"] + 32 * cst["shadow_sphere_tests"],
+            "extend": nb * cst["node_visits"] + 48 * cst["tri_tests"] + 32 * cst["sphere_tests"],
+            "shadow": nb * cst["shadow_node_visits"] + 48 * cst["shadow_tri_tests"] + 32 * cst["shadow_sphere_tests"],
         }
         dom = max(("extend", "shadow"), key=lambda k: kt[k][0])
         launches_per_frame = kt[dom][1] / args.steps

@@ -82,7 +82,7 @@ typedef struct {
     int32_t n_lights;
 } rt_scene_desc;
 
-enum { RT_LAYOUT_DFS = 0, RT_LAYOUT_BFS = 1, RT_LAYOUT_TREELET = 2 };
+enum { RT_LAYOUT_DFS = 0, RT_LAYOUT_BFS = 1, RT_LAYOUT_TREELET = 2, RT_LAYOUT_BVH4 = 3 };
 
 /* BVH build options; zero fields take the defaults in brackets. */
 typedef struct {
@@ -93,7 +93,9 @@ typedef struct {
                              RT_LAYOUT_DFS depth-first pre-order (left child at index + 1),
                              RT_LAYOUT_BFS breadth-first (level by level),
                              RT_LAYOUT_TREELET blocks of up to 7 nodes (three levels of a subtree,
-                             breadth-first inside) stored contiguously, blocks in depth-first order */
+                             breadth-first inside) stored contiguously, blocks in depth-first order,
+                             RT_LAYOUT_BVH4 the binary tree collapsed into 128-byte four-wide nodes
+                             (depth-first); RT_ERR_BVH_DEPTH if its traversal stack would exceed 96 */
 } rt_build_opts;
 
 /* Pinhole camera: vfov_deg is the vertical field of view; pixel row 0 is the
@@ -176,10 +178,11 @@ typedef struct {
 rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, rt_scene** out);
 void rt_destroy_scene(rt_scene* scene);
 rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* out);
-/* Reorder the nodes of a built scene into another RT_LAYOUT_* (same tree, same
- * traversal order, so every query returns the same hit).  Drops the scene's
- * device copy: call rt_scene_upload again before rendering.  Errors:
- * RT_ERR_INVALID_ARG (NULL scene, unknown layout). */
+/* Re-lay the nodes of a built scene in another RT_LAYOUT_* (the same binary
+ * tree, or its four-wide collapse; every query returns the same hit).  Drops
+ * the scene's device copy and may change rt_scene_device_bytes and the
+ * workspace size: call rt_scene_upload again before rendering.  Errors:
+ * RT_ERR_INVALID_ARG (NULL scene, unknown layout), RT_ERR_BVH_DEPTH. */
 rt_status rt_scene_set_layout(rt_scene* scene, int32_t node_layout);
 
 /* Bytes of the device blob (nodes | primitives | normals | planes | materials | lights). */

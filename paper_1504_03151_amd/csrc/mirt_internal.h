@@ -23,6 +23,8 @@ struct SceneHost {
     int n_spheres = 0, n_tris = 0, n_planes = 0, n_lights = 0, n_materials = 0;
     int64_t n_nodes = 0;
     int depth = 0, stack_size = 0;
+    int layout = 0;               // RT_LAYOUT_* of the node section
+    std::vector<Node> bvh2;       // the binary tree as built (depth-first), source of every layout
     float scale = 1.0f;           // max(1, max |coordinate|) of the scene
     rt_scene_info info{};
     void* dev = nullptr;
@@ -32,6 +34,8 @@ struct SceneHost {
     DevScene view(const uint8_t* base) const {
         DevScene s;
         s.nodes = reinterpret_cast<const Node*>(base + off_nodes);
+        s.nodes4 = reinterpret_cast<const Node4*>(base + off_nodes);
+        s.wide = layout == RT_LAYOUT_BVH4 ? 1 : 0;
         s.prims = reinterpret_cast<const float4*>(base + off_prims);
         s.normals = reinterpret_cast<const float4*>(base + off_normals);
         s.planes = reinterpret_cast<const float4*>(base + off_planes);

@@ -2016,6 +2016,13 @@ static rt_status trace_rays(const rt_scene* scene, const float* rays, int64_t n,
     }
     const DevScene sc = scene->h.dev_view();
     const size_t lds = (size_t)sc.stack_size * 64 * 4 * 4;
+    DevInfo di;
+    rt_status rd = device_info(di);
+    if (rd != RT_OK) return rd;
+    if (lds > (size_t)di.max_lds) {
+        set_error("rt_intersect/rt_occluded: the scene's traversal stack does not fit in LDS");
+        return RT_ERR_UNSUPPORTED;
+    }
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint32_t* cursor = static_cast<uint32_t*>(workspace);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, cursor, 1);

@@ -33,6 +33,17 @@ struct alignas(16) Node {
 };
 static_assert(sizeof(Node) == 64, "node must be 64 bytes");
 
+// Four-wide node (RT_LAYOUT_BVH4): 128 bytes, one L2 line, holding the boxes of
+// up to four children in SoA form (component i of each float4 is child i).
+// An unused slot has an all-+inf box, which no slab test accepts, and an empty
+// leaf reference.  Built on the host by collapsing the binary tree.
+struct alignas(128) Node4 {
+    float4 lox, hix, loy, hiy, loz, hiz;
+    int4 child;
+    int4 pad;
+};
+static_assert(sizeof(Node4) == 128, "four-wide node must be 128 bytes");
+
 constexpr int kLeafBits = 4;
 constexpr int kLeafMaxCount = 15;
 constexpr int32_t kStackDone = INT32_MIN;
@@ -61,6 +72,8 @@ struct alignas(16) DevLight {
 // Device view of one scene (pointers into the uploaded blob).
 struct DevScene {
     const Node* nodes;
+    const Node4* nodes4;      // the same section, when wide
+    int wide;                 // 1: four-wide nodes (RT_LAYOUT_BVH4)
     const float4* prims;      // [n_bvh * 3]
     const float4* normals;    // [n_bvh]  unit geometric normal of triangles (FP64 on host, rounded)
     const float4* planes;     // [n_planes] (n, h): n.x = h
@@ -150,6 +163,17 @@ HD TRay make_tray(V3 o, V3 d) {
 
 // Slab test of both children of a node.  Boxes are padded outward by the
 // builder, so the FP32 test never rejects a box the ray truly crosses.
+// Slab test of one child of a four-wide node, same arithmetic as box2.
+HD bool box1(const TRay& r, float lx, float hx, float ly, float hy, float lz, float hz, float tbest, float& tn) {
+    const float x0 = fmaf(lx, r.inv.x, -r.oinv.x), x1 = fmaf(hx, r.inv.x, -r.oinv.x);
+    const float y0 = fmaf(ly, r.inv.y, -r.oinv.y), y1 = fmaf(hy, r.inv.y, -r.oinv.y);
+    const float z0 = fmaf(lz, r.inv.z, -r.oinv.z), z1 = fmaf(hz, r.inv.z, -r.oinv.z);
+    const float tmin = max3f(fminf(x0, x1), fminf(y0, y1), fmaxf(fminf(z0, z1), 0.0f));
+    const float tmax = min3f(fmaxf(x0, x1), fmaxf(y0, y1), fminf(fmaxf(z0, z1), tbest));
+    tn = tmin;
+    return tmin <= tmax;
+}
+
 HD void box2(const TRay& r, float4 a, float4 b, float4 c, float tbest, bool& hitL, bool& hitR, float& tl,
              float& tr) {
     const float lx0 = fmaf(a.x, r.inv.x, -r.oinv.x), lx1 = fmaf(a.y, r.inv.x, -r.oinv.x);
@@ -241,25 +265,33 @@ struct Work {
     uint32_t nodes, tris, spheres;
 };
 
-// Closest hit (ANY = false) or any hit (ANY = true) in (0, tmax).  Ties in t
-// go to the smaller original id.  Stack is a small push/pop policy object
-// (LDS-resident on the GPU, an array on the host).
-template <bool ANY, bool COUNT, class Stack>
-HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& work) {
-    Hit h;
-    h.t = tmax;
-    h.prim = -1;
-    h.id = -1;
-    for (int k = 0; k < s.n_planes; ++k) {
-        const float t = plane_t(r, s.planes[k]);
-        const int id = s.n_bvh + k;
+// Tests the primitives of one leaf; true when an any-hit query is answered.
+template <bool ANY, bool COUNT>
+HD bool leaf_hits(const DevScene& s, const TRay& r, int32_t leaf, Hit& h, Work& work) {
+    const int32_t first = leaf_first(leaf), cnt = leaf_count(leaf);
+    for (int i = first; i < first + cnt; ++i) {
+        const float4 p0 = s.prims[3 * i];
+        const int id = as_int_f(p0.w);
+        float t;
+        if (id < s.n_spheres) {
+            if (COUNT) work.spheres++;
+            t = sphere_t(r, p0, s.prims[3 * i + 1]);
+        } else {
+            if (COUNT) work.tris++;
+            t = tri_t(r, p0, s.prims[3 * i + 1], s.prims[3 * i + 2]);
+        }
         if (t > 0.0f && (t < h.t || (t == h.t && h.prim >= 0 && id < h.id))) {
             h.t = t;
-            h.prim = s.n_bvh + k;
+            h.prim = i;
             h.id = id;
-            if (ANY) return h;
+            if (ANY) return true;
         }
     }
+    return false;
+}
+
+template <bool ANY, bool COUNT, class Stack>
+HD bool trace_bvh2(const DevScene& s, const TRay& r, Hit& h, Stack& stk, Work& work) {
     // While-while traversal with postponed leaves: a lane that reaches a leaf
     // keeps it and goes on descending until every active lane of the wave
     // holds a leaf (Stack::wave_all), then the wave tests leaves together, so
@@ -299,25 +331,7 @@ HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& 
             if (Stack::wave_all(leaf != 0)) break;
         }
         while (leaf != 0) {
-            const int32_t first = leaf_first(leaf), cnt = leaf_count(leaf);
-            for (int i = first; i < first + cnt; ++i) {
-                const float4 p0 = s.prims[3 * i];
-                const int id = as_int_f(p0.w);
-                float t;
-                if (id < s.n_spheres) {
-                    if (COUNT) work.spheres++;
-                    t = sphere_t(r, p0, s.prims[3 * i + 1]);
-                } else {
-                    if (COUNT) work.tris++;
-                    t = tri_t(r, p0, s.prims[3 * i + 1], s.prims[3 * i + 2]);
-                }
-                if (t > 0.0f && (t < h.t || (t == h.t && h.prim >= 0 && id < h.id))) {
-                    h.t = t;
-                    h.prim = i;
-                    h.id = id;
-                    if (ANY) return h;
-                }
-            }
+            if (leaf_hits<ANY, COUNT>(s, r, leaf, h, work)) return true;
             if (node < 0 && node != kStackDone) {
                 leaf = node;
                 node = stk.pop();
@@ -326,6 +340,97 @@ HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& 
             }
         }
     }
+    return false;
+}
+
+HD void cswap(float& ka, int32_t& ca, float& kb, int32_t& cb) {
+    if (kb < ka) {
+        const float k = ka;
+        ka = kb;
+        kb = k;
+        const int32_t c = ca;
+        ca = cb;
+        cb = c;
+    }
+}
+
+// Four-wide traversal: the hit children of a node are ordered by entry
+// distance (five-comparator network, misses sorted last), the far ones pushed,
+// the nearest taken next; leaves are postponed as in the binary traversal.
+template <bool ANY, bool COUNT, class Stack>
+HD bool trace_bvh4(const DevScene& s, const TRay& r, Hit& h, Stack& stk, Work& work) {
+    stk.reset();
+    int32_t node = 0, leaf = 0;
+    while (node != kStackDone) {
+        while (node >= 0) {
+            const Node4* n = s.nodes4 + node;
+            const float4 lx = n->lox, hx = n->hix, ly = n->loy, hy = n->hiy, lz = n->loz, hz = n->hiz;
+            const int4 ch = n->child;
+            if (COUNT) work.nodes++;
+            float k0, k1, k2, k3;
+            const bool b0 = box1(r, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, h.t, k0);
+            const bool b1 = box1(r, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, h.t, k1);
+            const bool b2 = box1(r, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, h.t, k2);
+            const bool b3 = box1(r, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, h.t, k3);
+            const int cnt = (int)b0 + (int)b1 + (int)b2 + (int)b3;
+            if (cnt == 0) {
+                node = stk.pop();
+            } else {
+                int32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
+                k0 = b0 ? k0 : INFINITY;
+                k1 = b1 ? k1 : INFINITY;
+                k2 = b2 ? k2 : INFINITY;
+                k3 = b3 ? k3 : INFINITY;
+                cswap(k0, c0, k1, c1);
+                cswap(k2, c2, k3, c3);
+                cswap(k0, c0, k2, c2);
+                cswap(k1, c1, k3, c3);
+                cswap(k1, c1, k2, c2);
+                if (cnt > 3) stk.push(c3);
+                if (cnt > 2) stk.push(c2);
+                if (cnt > 1) stk.push(c1);
+                node = c0;
+            }
+            if (node < 0 && node != kStackDone && leaf == 0) {
+                leaf = node;
+                node = stk.pop();
+            }
+            if (Stack::wave_all(leaf != 0)) break;
+        }
+        while (leaf != 0) {
+            if (leaf_hits<ANY, COUNT>(s, r, leaf, h, work)) return true;
+            if (node < 0 && node != kStackDone) {
+                leaf = node;
+                node = stk.pop();
+            } else {
+                leaf = 0;
+            }
+        }
+    }
+    return false;
+}
+
+// Closest hit (ANY = false) or any hit (ANY = true) in (0, tmax).  Ties in t
+// go to the smaller original id.  Stack is a small push/pop policy object
+// (LDS-resident on the GPU, an array on the host).
+template <bool ANY, bool COUNT, class Stack>
+HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& work) {
+    Hit h;
+    h.t = tmax;
+    h.prim = -1;
+    h.id = -1;
+    for (int k = 0; k < s.n_planes; ++k) {
+        const float t = plane_t(r, s.planes[k]);
+        const int id = s.n_bvh + k;
+        if (t > 0.0f && (t < h.t || (t == h.t && h.prim >= 0 && id < h.id))) {
+            h.t = t;
+            h.prim = s.n_bvh + k;
+            h.id = id;
+            if (ANY) return h;
+        }
+    }
+    if (s.wide) trace_bvh4<ANY, COUNT>(s, r, h, stk, work);
+    else trace_bvh2<ANY, COUNT>(s, r, h, stk, work);
     return h;
 }
 

@@ -261,6 +261,99 @@ void apply_layout(Node* nodes, int64_t n, int layout) {
     }
 }
 
+// Four-wide collapse of the binary tree: a four-wide node takes the two
+// children of a binary node and keeps opening the inner child with the largest
+// box surface until it holds four children or only leaves are left.  Child
+// boxes are copied unchanged (already padded); an empty box becomes the
+// all-+inf box no slab test accepts.
+struct Child4 {
+    float lo[3], hi[3];
+    int32_t ref;
+};
+
+void binary_children(const Node& n, Child4& l, Child4& r) {
+    l = Child4{{n.a.x, n.a.z, n.c.x}, {n.a.y, n.a.w, n.c.y}, n.d.x};
+    r = Child4{{n.b.x, n.b.z, n.c.z}, {n.b.y, n.b.w, n.c.w}, n.d.y};
+}
+
+double child_area(const Child4& c) {
+    const double e0 = (double)c.hi[0] - c.lo[0], e1 = (double)c.hi[1] - c.lo[1], e2 = (double)c.hi[2] - c.lo[2];
+    if (!(e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0)) return -1.0;
+    return e0 * e1 + e1 * e2 + e2 * e0;
+}
+
+int32_t collapse4(const std::vector<Node>& n2, int32_t idx, int depth, std::vector<Node4>& out, int& max_depth) {
+    Child4 e[4];
+    int k = 2;
+    binary_children(n2[idx], e[0], e[1]);
+    while (k < 4) {
+        int best = -1;
+        double ba = -2.0;
+        for (int i = 0; i < k; ++i)
+            if (e[i].ref >= 0 && child_area(e[i]) > ba) {
+                best = i;
+                ba = child_area(e[i]);
+            }
+        if (best < 0) break;
+        Child4 l, r;
+        binary_children(n2[e[best].ref], l, r);
+        e[best] = l;
+        e[k++] = r;
+    }
+    const int32_t me = (int32_t)out.size();
+    out.emplace_back();
+    max_depth = std::max(max_depth, depth);
+    int32_t refs[4];
+    for (int i = 0; i < k; ++i) refs[i] = e[i].ref >= 0 ? collapse4(n2, e[i].ref, depth + 1, out, max_depth) : e[i].ref;
+    float b[6][4];
+    int32_t c[4];
+    for (int i = 0; i < 4; ++i) {
+        const bool used = i < k && child_area(e[i]) >= 0.0;
+        for (int a = 0; a < 3; ++a) {
+            b[2 * a][i] = used ? e[i].lo[a] : INFINITY;
+            b[2 * a + 1][i] = used ? e[i].hi[a] : INFINITY;
+        }
+        c[i] = i < k ? refs[i] : leaf_ref(0, 0);
+    }
+    Node4& o = out[me];
+    o.lox = make_float4(b[0][0], b[0][1], b[0][2], b[0][3]);
+    o.hix = make_float4(b[1][0], b[1][1], b[1][2], b[1][3]);
+    o.loy = make_float4(b[2][0], b[2][1], b[2][2], b[2][3]);
+    o.hiy = make_float4(b[3][0], b[3][1], b[3][2], b[3][3]);
+    o.loz = make_float4(b[4][0], b[4][1], b[4][2], b[4][3]);
+    o.hiz = make_float4(b[5][0], b[5][1], b[5][2], b[5][3]);
+    o.child = make_int4(c[0], c[1], c[2], c[3]);
+    o.pad = make_int4(0, 0, 0, 0);
+    return me;
+}
+
+// Node section of a layout (bytes), with the node count and the traversal
+// stack entries a ray needs in it.  Returns false if that stack would not fit.
+bool layout_nodes(const std::vector<Node>& dfs, int layout, int depth2, std::vector<uint8_t>& bytes, int64_t& n_nodes,
+                  int& stack_size) {
+    if (layout == RT_LAYOUT_BVH4) {
+        std::vector<Node4> n4;
+        n4.reserve(dfs.size() / 2 + 1);
+        int d4 = 0;
+        collapse4(dfs, 0, 0, n4, d4);
+        // at most three siblings pushed per level on the way down, plus the
+        // end marker and the pushes of the deepest node
+        stack_size = 3 * d4 + 5;
+        if (stack_size > kMaxStack) return false;
+        bytes.resize(n4.size() * sizeof(Node4));
+        std::memcpy(bytes.data(), n4.data(), bytes.size());
+        n_nodes = (int64_t)n4.size();
+        return true;
+    }
+    std::vector<Node> v = dfs;
+    if (layout != RT_LAYOUT_DFS) apply_layout(v.data(), (int64_t)v.size(), layout);
+    stack_size = depth2 + 3;
+    bytes.resize(v.size() * sizeof(Node));
+    std::memcpy(bytes.data(), v.data(), bytes.size());
+    n_nodes = (int64_t)v.size();
+    return true;
+}
+
 bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -364,8 +457,8 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         const int leaf_max = o.leaf_max > 0 ? std::min(o.leaf_max, kLeafMaxCount) : 4;
         const int bins = o.sah_bins > 1 ? std::min(o.sah_bins, 256) : 32;
         const int max_depth = o.max_depth > 0 ? std::min(o.max_depth, 61) : 60;
-        if (o.node_layout < RT_LAYOUT_DFS || o.node_layout > RT_LAYOUT_TREELET) {
-            set_error("rt_build_scene: node_layout must be RT_LAYOUT_DFS, RT_LAYOUT_BFS or RT_LAYOUT_TREELET");
+        if (o.node_layout < RT_LAYOUT_DFS || o.node_layout > RT_LAYOUT_BVH4) {
+            set_error("rt_build_scene: node_layout must be one of RT_LAYOUT_DFS, _BFS, _TREELET, _BVH4");
             return RT_ERR_INVALID_ARG;
         }
 
@@ -411,7 +504,13 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
             set_error("rt_build_scene: BVH deeper than max_depth " + std::to_string(max_depth));
             return RT_ERR_BVH_DEPTH;
         }
-        if (o.node_layout != RT_LAYOUT_DFS) apply_layout(nodes.data(), (int64_t)nodes.size(), o.node_layout);
+        std::vector<uint8_t> node_bytes;
+        int64_t n_nodes = 0;
+        int stack_size = 0;
+        if (!layout_nodes(nodes, o.node_layout, B.depth_reached, node_bytes, n_nodes, stack_size)) {
+            set_error("rt_build_scene: four-wide traversal stack would exceed " + std::to_string(kMaxStack) + " entries");
+            return RT_ERR_BVH_DEPTH;
+        }
         const auto t1 = std::chrono::steady_clock::now();
 
         SceneHost h;
@@ -420,14 +519,15 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         h.n_planes = (int)np;
         h.n_lights = nl;
         h.n_materials = nm;
-        h.n_nodes = (int64_t)nodes.size();
+        h.n_nodes = n_nodes;
         h.depth = B.depth_reached;
-        h.stack_size = B.depth_reached + 3;
+        h.stack_size = stack_size;
+        h.layout = o.node_layout;
         h.scale = scale;
         const int64_t nb = ns + nt;
         size_t off = 0;
         h.off_nodes = off;
-        off = align256(off + sizeof(Node) * nodes.size());
+        off = align256(off + node_bytes.size());
         h.off_prims = off;
         off = align256(off + 48 * (size_t)std::max<int64_t>(nb, 1));
         h.off_normals = off;
@@ -442,7 +542,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         off = align256(off + sizeof(DevLight) * (size_t)std::max(nl, 1));
         h.blob.assign(off, 0);
         uint8_t* base = h.blob.data();
-        std::memcpy(base + h.off_nodes, nodes.data(), sizeof(Node) * nodes.size());
+        std::memcpy(base + h.off_nodes, node_bytes.data(), node_bytes.size());
         float4* prims = reinterpret_cast<float4*>(base + h.off_prims);
         float4* normals = reinterpret_cast<float4*>(base + h.off_normals);
         for (int64_t i = 0; i < nb; ++i) {
@@ -504,6 +604,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         }
         I.node_layout = o.node_layout;
         h.uid = g_scene_uid.fetch_add(1);
+        h.bvh2 = std::move(nodes);
         rt_scene* s = new rt_scene;
         s->h = std::move(h);
         *out = s;
@@ -526,14 +627,36 @@ rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* out) {
 }
 
 rt_status rt_scene_set_layout(rt_scene* scene, int32_t node_layout) {
-    if (!scene || node_layout < RT_LAYOUT_DFS || node_layout > RT_LAYOUT_TREELET) {
+    if (!scene || node_layout < RT_LAYOUT_DFS || node_layout > RT_LAYOUT_BVH4) {
         set_error("rt_scene_set_layout: NULL scene or unknown node layout");
         return RT_ERR_INVALID_ARG;
     }
     try {
         SceneHost& h = scene->h;
-        apply_layout(reinterpret_cast<Node*>(h.blob.data() + h.off_nodes), h.n_nodes, node_layout);
+        std::vector<uint8_t> node_bytes;
+        int64_t n_nodes = 0;
+        int stack_size = 0;
+        if (!layout_nodes(h.bvh2, node_layout, h.depth, node_bytes, n_nodes, stack_size)) {
+            set_error("rt_scene_set_layout: four-wide traversal stack would exceed " + std::to_string(kMaxStack) +
+                      " entries");
+            return RT_ERR_BVH_DEPTH;
+        }
+        // new blob: the node section, then every later section moved by the same amount
+        const size_t tail = h.blob.size() - h.off_prims;
+        const size_t new_prims = align256(node_bytes.size());
+        std::vector<uint8_t> blob(new_prims + tail, 0);
+        std::memcpy(blob.data(), node_bytes.data(), node_bytes.size());
+        std::memcpy(blob.data() + new_prims, h.blob.data() + h.off_prims, tail);
+        const size_t old_prims = h.off_prims;
+        for (size_t* o : {&h.off_prims, &h.off_normals, &h.off_planes, &h.off_plane_mat, &h.off_mats, &h.off_lights})
+            *o = *o - old_prims + new_prims;
+        h.blob.swap(blob);
+        h.n_nodes = n_nodes;
+        h.stack_size = stack_size;
+        h.layout = node_layout;
         h.info.node_layout = node_layout;
+        h.info.n_nodes = n_nodes;
+        h.info.stack_size = stack_size;
         h.dev = nullptr;
         h.dev_bytes = 0;
         h.uid = g_scene_uid.fetch_add(1);

@@ -96,10 +96,11 @@ def test_workspace_and_render_argument_errors():
     assert rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)) == 0
 
 
-def test_host_traversal_matches_brute_force_on_tiny_scenes():
+@pytest.mark.parametrize("layout", [rt.LAYOUT_DFS, rt.LAYOUT_BVH4])
+def test_host_traversal_matches_brute_force_on_tiny_scenes(layout):
     for seed in range(6):
         w = S.random_tiny(seed, n_spheres=6, n_tris=80)
-        s = rt.Scene(w.scene)
+        s = rt.Scene(w.scene, node_layout=layout)
         rng = np.random.default_rng(100 + seed)
         o = rng.uniform(-6, 6, (3000, 3))
         d = rng.normal(size=(3000, 3))
@@ -135,15 +136,21 @@ def test_bvh_info_and_work_counts_are_sane():
     assert work[:, 1].mean() < 0.01 * len(w.scene.tris)
 
 
-@pytest.mark.parametrize("layout", [rt.LAYOUT_BFS, rt.LAYOUT_TREELET])
+@pytest.mark.parametrize("layout", [rt.LAYOUT_BFS, rt.LAYOUT_TREELET, rt.LAYOUT_BVH4])
 def test_node_layouts_keep_every_hit_and_every_traversal_step(layout):
     """A node layout only renumbers nodes: the same rays must see the same hits (bit-equal t and id) and fetch
-    the same number of nodes and primitives as in depth-first order, for closest and any hit."""
+    the same number of nodes and primitives as in depth-first order, for closest and any hit.  The four-wide
+    collapse of the same tree must give the same closest hits (bit-equal) and the same any-hit answers, with
+    fewer node fetches."""
     w = S.config1(width=64, height=36, grid=96)
     base = rt.Scene(w.scene)
     other = rt.Scene(w.scene, node_layout=layout)
     assert other.info["node_layout"] == layout and base.info["node_layout"] == rt.LAYOUT_DFS
-    assert other.info["n_nodes"] == base.info["n_nodes"] and other.info["depth"] == base.info["depth"]
+    wide = layout == rt.LAYOUT_BVH4
+    if wide:
+        assert other.info["n_nodes"] < 0.6 * base.info["n_nodes"]
+    else:
+        assert other.info["n_nodes"] == base.info["n_nodes"] and other.info["depth"] == base.info["depth"]
     rng = np.random.default_rng(7)
     o = rng.uniform(-100, 100, (4000, 3)) * [1, 0, 1] + [0, 40, 0]
     d = rng.normal(size=(4000, 3)) - [0, 1.5, 0]
@@ -153,16 +160,22 @@ def test_node_layouts_keep_every_hit_and_every_traversal_step(layout):
         t0, i0, w0 = base.host_trace(R, any_hit=any_hit, with_work=True)
         t1, i1, w1 = other.host_trace(R, any_hit=any_hit, with_work=True)
         assert (i0 >= 0).mean() > 0.3
+        if any_hit and wide:                  # any hit: the same answer, possibly another blocker
+            np.testing.assert_array_equal(i0 >= 0, i1 >= 0)
+            continue
         np.testing.assert_array_equal(i0, i1)
         np.testing.assert_array_equal(t0, t1)
-        np.testing.assert_array_equal(w0, w1)
+        if wide:
+            assert w1[:, 0].sum() < 0.75 * w0[:, 0].sum()
+        else:
+            np.testing.assert_array_equal(w0, w1)
     # re-layout of a built scene, and back: identical again; the device copy is dropped
     other.set_layout(rt.LAYOUT_DFS)
     assert other.info["node_layout"] == rt.LAYOUT_DFS and other.blob is None
     R = rt.make_rays(o, d)
     np.testing.assert_array_equal(base.host_trace(R)[1], other.host_trace(R)[1])
     with pytest.raises(rt.RTError, match="INVALID_ARG"):
-        other.set_layout(3)
+        other.set_layout(4)
     with pytest.raises(rt.RTError, match="INVALID_ARG"):
         rt.Scene(w.scene, node_layout=-1)
 

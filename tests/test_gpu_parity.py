@@ -161,10 +161,11 @@ def test_intersect_and_occluded_on_oracle_rays(rt, cfg):
             np.testing.assert_allclose(t[hit], tr[hit], rtol=2e-5)
 
 
-def test_random_rays_bvh_equals_brute_force(rt):
+@pytest.mark.parametrize("layout", [0, 3])         # binary depth-first, four-wide
+def test_random_rays_bvh_equals_brute_force(rt, layout):
     for seed in range(3):
         w = S.random_tiny(20 + seed, n_spheres=8, n_tris=200)
-        sc = rt.Scene(w.scene).upload()
+        sc = rt.Scene(w.scene, node_layout=layout).upload()
         rng = np.random.default_rng(seed)
         o = rng.uniform(-6, 6, (20000, 3))
         d = rng.normal(size=(20000, 3))
@@ -178,6 +179,15 @@ def test_random_rays_bvh_equals_brute_force(rt):
         # and the host traversal of the same BVH agrees with the device
         th, ih = sc.host_trace(R)
         assert (ih[rob] == ir[rob]).all()
+        # any hit on segments: the device answer is the oracle's on robust rays
+        tm = rng.uniform(0.5, 9, 20000).astype(np.float32)
+        R2 = rt.make_rays(o, d, tm)
+        occ = rt.occluded(sc, torch.from_numpy(R2).cuda()).cpu().numpy().astype(bool)
+        oc, m2 = oracle.occluded(w.scene, R2[:, :3].astype(np.float64), R2[:, 3:6].astype(np.float64),
+                                 R2[:, 7].astype(np.float64))
+        rob2 = m2 > ROBUST
+        assert rob2.mean() > 0.97
+        assert (occ[rob2] == oc[rob2]).all()
 
 
 # ------------------------------------------------------------------ full-size configurations, sampled pixels
