@@ -8,9 +8,10 @@ wavefront pass, bounce and shadow query).  Inputs (scene blob) are resident in
 HBM before the timed region.
 
 Prints ONE JSON line.  roofline: the dominant traversal kernel's algorithmic
-bytes (64 B per binary BVH node fetched, 128 B per four-wide node, + 48 B per triangle record + 32 B per sphere,
-counted by an untimed counting frame) divided by its average launch time from
-HIP events recorded on the launch stream during the timed frames.
+bytes (64 B per binary or quantized four-wide node fetched, 128 B per float
+four-wide node, + 48 B per triangle record + 32 B per sphere, counted by an
+untimed counting frame) divided by its average launch time from HIP events
+recorded on the launch stream during the timed frames.
 cpu_baseline: the FP64 brute-force oracle on a bounded pixel sample of the
 same frame, on the host cores.
 """
@@ -370,7 +371,7 @@ def main():
 
     roof = None
     if not args.graph:
-        nb = 128 if sc.info["node_layout"] == rt.LAYOUT_BVH4 else 64      # bytes per node fetch
+        nb = rt.NODE_BYTES[sc.info["node_layout"]]      # bytes per node fetch
         per = {
             "extend": nb * cst["node_visits"] + 48 * cst["tri_tests"] + 32 * cst["sphere_tests"],
             "shadow": nb * cst["shadow_node_visits"] + 48 * cst["shadow_tri_tests"] + 32 * cst["shadow_sphere_tests"],

@@ -82,7 +82,7 @@ typedef struct {
     int32_t n_lights;
 } rt_scene_desc;
 
-enum { RT_LAYOUT_DFS = 0, RT_LAYOUT_BFS = 1, RT_LAYOUT_TREELET = 2, RT_LAYOUT_BVH4 = 3 };
+enum { RT_LAYOUT_DFS = 0, RT_LAYOUT_BFS = 1, RT_LAYOUT_TREELET = 2, RT_LAYOUT_BVH4 = 3, RT_LAYOUT_BVH4Q = 4 };
 
 /* BVH build options; zero fields take the defaults in brackets. */
 typedef struct {
@@ -95,7 +95,9 @@ typedef struct {
                              RT_LAYOUT_TREELET blocks of up to 7 nodes (three levels of a subtree,
                              breadth-first inside) stored contiguously, blocks in depth-first order,
                              RT_LAYOUT_BVH4 the binary tree collapsed into 128-byte four-wide nodes
-                             (depth-first); RT_ERR_BVH_DEPTH if its traversal stack would exceed 96 */
+                             (depth-first), RT_LAYOUT_BVH4Q the same tree in 64-byte nodes whose child
+                             boxes are 8-bit offsets, rounded outward, from the node's corner;
+                             RT_ERR_BVH_DEPTH if a four-wide traversal stack would exceed 96 */
 } rt_build_opts;
 
 /* Pinhole camera: vfov_deg is the vertical field of view; pixel row 0 is the

@@ -5,8 +5,9 @@ to waves, never what is computed: the tile shape decides which 64 pixels share
 a wave (and so how coherent the secondary rays of a wave are), the queue chunk
 how many queue entries a persistent traversal wave takes per atomic fetch, and
 the node layout (binary tree depth-first, breadth-first or in three-level
-treelets, or its four-wide collapse) which nodes share cache lines and how many
-dependent node fetches a ray makes.  The tuner times real frames of the caller's workload
+treelets, or its four-wide collapse with float or 8-bit quantized child boxes)
+which nodes share cache lines and how many bytes and dependent node fetches a
+ray needs.  The tuner times real frames of the caller's workload
 through the C-ABI, keeps the fastest setting, and checks that every candidate
 returns the same primary-hit ids as the default setting (a candidate that
 does not is rejected).
@@ -27,7 +28,7 @@ from typing import Callable, Optional, Sequence
 from . import rt
 
 SPACE = {
-    "layout": [rt.LAYOUT_DFS, rt.LAYOUT_BFS, rt.LAYOUT_TREELET, rt.LAYOUT_BVH4],
+    "layout": [rt.LAYOUT_DFS, rt.LAYOUT_BFS, rt.LAYOUT_TREELET, rt.LAYOUT_BVH4, rt.LAYOUT_BVH4Q],
     "chunk": [64, 128, 256, 512, 1024],
     "tile": [rt.TILE_8X8, rt.TILE_16X4, rt.TILE_32X2, rt.TILE_4X16],
 }

@@ -35,7 +35,8 @@ struct SceneHost {
         DevScene s;
         s.nodes = reinterpret_cast<const Node*>(base + off_nodes);
         s.nodes4 = reinterpret_cast<const Node4*>(base + off_nodes);
-        s.wide = layout == RT_LAYOUT_BVH4 ? 1 : 0;
+        s.nodes4q = reinterpret_cast<const Node4q*>(base + off_nodes);
+        s.wide = layout == RT_LAYOUT_BVH4 ? 1 : (layout == RT_LAYOUT_BVH4Q ? 2 : 0);
         s.prims = reinterpret_cast<const float4*>(base + off_prims);
         s.normals = reinterpret_cast<const float4*>(base + off_normals);
         s.planes = reinterpret_cast<const float4*>(base + off_planes);

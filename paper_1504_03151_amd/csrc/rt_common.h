@@ -44,6 +44,23 @@ struct alignas(128) Node4 {
 };
 static_assert(sizeof(Node4) == 128, "four-wide node must be 128 bytes");
 
+// Quantized four-wide node (RT_LAYOUT_BVH4Q): 64 bytes.  Child box planes are
+// 8-bit offsets from the node's origin p in units of a power of two per axis:
+// plane = fma(q, 2^e_axis, p_axis), which is exact in the product and rounds
+// once; the host chooses each q so that the decoded box contains the child's
+// (padded) box, so traversal stays exact and only visits a little more.
+//   origin = (p.x, p.y, p.z, bits: biased e_x | e_y << 8 | e_z << 16 | valid-child mask << 24)
+//   qa = (lo.x, hi.x, lo.y, hi.y) with byte i = child i
+//   qb = (lo.z, hi.z, child 0, child 1)
+//   qc = (child 2, child 3, 0, 0)
+struct alignas(64) Node4q {
+    float4 origin;
+    uint4 qa;
+    uint4 qb;
+    int4 qc;
+};
+static_assert(sizeof(Node4q) == 64, "quantized four-wide node must be 64 bytes");
+
 constexpr int kLeafBits = 4;
 constexpr int kLeafMaxCount = 15;
 constexpr int32_t kStackDone = INT32_MIN;
@@ -72,8 +89,9 @@ struct alignas(16) DevLight {
 // Device view of one scene (pointers into the uploaded blob).
 struct DevScene {
     const Node* nodes;
-    const Node4* nodes4;      // the same section, when wide
-    int wide;                 // 1: four-wide nodes (RT_LAYOUT_BVH4)
+    const Node4* nodes4;      // the same section, when wide == 1
+    const Node4q* nodes4q;    // the same section, when wide == 2
+    int wide;                 // 0 binary nodes; 1 four-wide (RT_LAYOUT_BVH4); 2 quantized four-wide (RT_LAYOUT_BVH4Q)
     const float4* prims;      // [n_bvh * 3]
     const float4* normals;    // [n_bvh]  unit geometric normal of triangles (FP64 on host, rounded)
     const float4* planes;     // [n_planes] (n, h): n.x = h
@@ -357,21 +375,55 @@ HD void cswap(float& ka, int32_t& ca, float& kb, int32_t& cb) {
 // Four-wide traversal: the hit children of a node are ordered by entry
 // distance (five-comparator network, misses sorted last), the far ones pushed,
 // the nearest taken next; leaves are postponed as in the binary traversal.
-template <bool ANY, bool COUNT, class Stack>
+// Byte i of a quantized plane word, decoded: fma(q, scale, origin).
+HD float qplane(uint32_t w, int i, float scale, float origin) {
+    return fmaf((float)((w >> (8 * i)) & 0xFFu), scale, origin);
+}
+
+// Children of a quantized four-wide node: decoded boxes, then the float slab test.
+HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, bool& b2, bool& b3, float& k0,
+               float& k1, float& k2, float& k3, int4& ch) {
+    const float4 o = n->origin;
+    const uint4 qa = n->qa, qb = n->qb;
+    const int4 qc = n->qc;
+    const uint32_t eb = (uint32_t)as_int_f(o.w);
+    const float sx = as_float_i((int)((eb & 0xFFu) << 23));
+    const float sy = as_float_i((int)(((eb >> 8) & 0xFFu) << 23));
+    const float sz = as_float_i((int)(((eb >> 16) & 0xFFu) << 23));
+    const uint32_t valid = eb >> 24;
+    b0 = ((valid & 1u) != 0u) & box1(r, qplane(qa.x, 0, sx, o.x), qplane(qa.y, 0, sx, o.x), qplane(qa.z, 0, sy, o.y),
+                              qplane(qa.w, 0, sy, o.y), qplane(qb.x, 0, sz, o.z), qplane(qb.y, 0, sz, o.z), tbest, k0);
+    b1 = ((valid & 2u) != 0u) & box1(r, qplane(qa.x, 1, sx, o.x), qplane(qa.y, 1, sx, o.x), qplane(qa.z, 1, sy, o.y),
+                              qplane(qa.w, 1, sy, o.y), qplane(qb.x, 1, sz, o.z), qplane(qb.y, 1, sz, o.z), tbest, k1);
+    b2 = ((valid & 4u) != 0u) & box1(r, qplane(qa.x, 2, sx, o.x), qplane(qa.y, 2, sx, o.x), qplane(qa.z, 2, sy, o.y),
+                              qplane(qa.w, 2, sy, o.y), qplane(qb.x, 2, sz, o.z), qplane(qb.y, 2, sz, o.z), tbest, k2);
+    b3 = ((valid & 8u) != 0u) & box1(r, qplane(qa.x, 3, sx, o.x), qplane(qa.y, 3, sx, o.x), qplane(qa.z, 3, sy, o.y),
+                              qplane(qa.w, 3, sy, o.y), qplane(qb.x, 3, sz, o.z), qplane(qb.y, 3, sz, o.z), tbest, k3);
+    ch = make_int4((int)qb.z, (int)qb.w, qc.x, qc.y);
+}
+
+HD void kids_f(const Node4* n, const TRay& r, float tbest, bool& b0, bool& b1, bool& b2, bool& b3, float& k0,
+               float& k1, float& k2, float& k3, int4& ch) {
+    const float4 lx = n->lox, hx = n->hix, ly = n->loy, hy = n->hiy, lz = n->loz, hz = n->hiz;
+    ch = n->child;
+    b0 = box1(r, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, tbest, k0);
+    b1 = box1(r, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, tbest, k1);
+    b2 = box1(r, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, tbest, k2);
+    b3 = box1(r, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, tbest, k3);
+}
+
+template <bool ANY, bool COUNT, bool QUANT, class Stack>
 HD bool trace_bvh4(const DevScene& s, const TRay& r, Hit& h, Stack& stk, Work& work) {
     stk.reset();
     int32_t node = 0, leaf = 0;
     while (node != kStackDone) {
         while (node >= 0) {
-            const Node4* n = s.nodes4 + node;
-            const float4 lx = n->lox, hx = n->hix, ly = n->loy, hy = n->hiy, lz = n->loz, hz = n->hiz;
-            const int4 ch = n->child;
             if (COUNT) work.nodes++;
+            bool b0, b1, b2, b3;
             float k0, k1, k2, k3;
-            const bool b0 = box1(r, lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, h.t, k0);
-            const bool b1 = box1(r, lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, h.t, k1);
-            const bool b2 = box1(r, lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, h.t, k2);
-            const bool b3 = box1(r, lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, h.t, k3);
+            int4 ch;
+            if (QUANT) kids_q(s.nodes4q + node, r, h.t, b0, b1, b2, b3, k0, k1, k2, k3, ch);
+            else kids_f(s.nodes4 + node, r, h.t, b0, b1, b2, b3, k0, k1, k2, k3, ch);
             const int cnt = (int)b0 + (int)b1 + (int)b2 + (int)b3;
             if (cnt == 0) {
                 node = stk.pop();
@@ -429,7 +481,8 @@ HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& 
             if (ANY) return h;
         }
     }
-    if (s.wide) trace_bvh4<ANY, COUNT>(s, r, h, stk, work);
+    if (s.wide == 2) trace_bvh4<ANY, COUNT, true>(s, r, h, stk, work);
+    else if (s.wide == 1) trace_bvh4<ANY, COUNT, false>(s, r, h, stk, work);
     else trace_bvh2<ANY, COUNT>(s, r, h, stk, work);
     return h;
 }

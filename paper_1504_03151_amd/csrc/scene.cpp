@@ -327,11 +327,81 @@ int32_t collapse4(const std::vector<Node>& n2, int32_t idx, int depth, std::vect
     return me;
 }
 
+// 8-bit quantization of a four-wide node's child boxes (RT_LAYOUT_BVH4Q).
+// Per axis: origin p = the lowest child plane, scale 2^e the smallest power of
+// two with 255 * 2^e >= the node's extent; a lower plane takes the largest q
+// whose decoded fma(q, 2^e, p) is <= the true plane, an upper plane the
+// smallest q whose decoded value is >= it (checked with the same fma the
+// traversal uses), so every decoded box contains its child's padded box.
+float f4c(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+
+bool quantize4(const Node4& n, Node4q& q) {
+    float lo[4][3], hi[4][3];
+    bool valid[4];
+    const float4* L[3] = {&n.lox, &n.loy, &n.loz};
+    const float4* H[3] = {&n.hix, &n.hiy, &n.hiz};
+    for (int i = 0; i < 4; ++i) {
+        for (int a = 0; a < 3; ++a) {
+            lo[i][a] = f4c(*L[a], i);
+            hi[i][a] = f4c(*H[a], i);
+        }
+        valid[i] = std::isfinite(lo[i][0]) && std::isfinite(hi[i][0]);
+    }
+    float p[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t ebytes = 0, qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int i = 0; i < 4; ++i)
+            if (valid[i]) {
+                mn = std::min(mn, lo[i][a]);
+                mx = std::max(mx, hi[i][a]);
+            }
+        if (!(mn <= mx)) {
+            mn = 0.0f;
+            mx = 0.0f;
+        }
+        p[a] = mn;
+        const double ext = (double)mx - mn;
+        int e = -126;
+        if (ext > 0.0) e = std::max(-126, (int)std::ceil(std::log2(ext / 255.0)));
+        for (;; ++e) {
+            if (e > 127) return false;
+            const float sc = std::ldexp(1.0f, e);
+            bool ok = true;
+            uint32_t wl = 0, wh = 0;
+            for (int i = 0; i < 4 && ok; ++i) {
+                if (!valid[i]) continue;
+                double ql = std::max(0.0, std::floor(((double)lo[i][a] - mn) / sc));
+                while (ql > 0.0 && std::fmaf((float)ql, sc, mn) > lo[i][a]) ql -= 1.0;
+                double qh = std::max(0.0, std::ceil(((double)hi[i][a] - mn) / sc));
+                while (qh <= 255.0 && std::fmaf((float)qh, sc, mn) < hi[i][a]) qh += 1.0;
+                if (qh > 255.0 || ql > 255.0) ok = false;
+                wl |= (uint32_t)ql << (8 * i);
+                wh |= (uint32_t)qh << (8 * i);
+            }
+            if (ok) {
+                ebytes |= (uint32_t)(e + 127) << (8 * a);
+                qlo[a] = wl;
+                qhi[a] = wh;
+                break;
+            }
+        }
+    }
+    uint32_t mask = 0;
+    for (int i = 0; i < 4; ++i) mask |= valid[i] ? (1u << i) : 0u;
+    ebytes |= mask << 24;
+    q.origin = make_float4(p[0], p[1], p[2], as_float_i((int)ebytes));
+    q.qa = make_uint4(qlo[0], qhi[0], qlo[1], qhi[1]);
+    q.qb = make_uint4(qlo[2], qhi[2], (uint32_t)n.child.x, (uint32_t)n.child.y);
+    q.qc = make_int4(n.child.z, n.child.w, 0, 0);
+    return true;
+}
+
 // Node section of a layout (bytes), with the node count and the traversal
 // stack entries a ray needs in it.  Returns false if that stack would not fit.
 bool layout_nodes(const std::vector<Node>& dfs, int layout, int depth2, std::vector<uint8_t>& bytes, int64_t& n_nodes,
                   int& stack_size) {
-    if (layout == RT_LAYOUT_BVH4) {
+    if (layout == RT_LAYOUT_BVH4 || layout == RT_LAYOUT_BVH4Q) {
         std::vector<Node4> n4;
         n4.reserve(dfs.size() / 2 + 1);
         int d4 = 0;
@@ -340,9 +410,17 @@ bool layout_nodes(const std::vector<Node>& dfs, int layout, int depth2, std::vec
         // end marker and the pushes of the deepest node
         stack_size = 3 * d4 + 5;
         if (stack_size > kMaxStack) return false;
-        bytes.resize(n4.size() * sizeof(Node4));
-        std::memcpy(bytes.data(), n4.data(), bytes.size());
         n_nodes = (int64_t)n4.size();
+        if (layout == RT_LAYOUT_BVH4) {
+            bytes.resize(n4.size() * sizeof(Node4));
+            std::memcpy(bytes.data(), n4.data(), bytes.size());
+            return true;
+        }
+        std::vector<Node4q> nq(n4.size());
+        for (size_t i = 0; i < n4.size(); ++i)
+            if (!quantize4(n4[i], nq[i])) return false;
+        bytes.resize(nq.size() * sizeof(Node4q));
+        std::memcpy(bytes.data(), nq.data(), bytes.size());
         return true;
     }
     std::vector<Node> v = dfs;
@@ -457,8 +535,8 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         const int leaf_max = o.leaf_max > 0 ? std::min(o.leaf_max, kLeafMaxCount) : 4;
         const int bins = o.sah_bins > 1 ? std::min(o.sah_bins, 256) : 32;
         const int max_depth = o.max_depth > 0 ? std::min(o.max_depth, 61) : 60;
-        if (o.node_layout < RT_LAYOUT_DFS || o.node_layout > RT_LAYOUT_BVH4) {
-            set_error("rt_build_scene: node_layout must be one of RT_LAYOUT_DFS, _BFS, _TREELET, _BVH4");
+        if (o.node_layout < RT_LAYOUT_DFS || o.node_layout > RT_LAYOUT_BVH4Q) {
+            set_error("rt_build_scene: node_layout must be one of RT_LAYOUT_DFS, _BFS, _TREELET, _BVH4, _BVH4Q");
             return RT_ERR_INVALID_ARG;
         }
 
@@ -627,7 +705,7 @@ rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* out) {
 }
 
 rt_status rt_scene_set_layout(rt_scene* scene, int32_t node_layout) {
-    if (!scene || node_layout < RT_LAYOUT_DFS || node_layout > RT_LAYOUT_BVH4) {
+    if (!scene || node_layout < RT_LAYOUT_DFS || node_layout > RT_LAYOUT_BVH4Q) {
         set_error("rt_scene_set_layout: NULL scene or unknown node layout");
         return RT_ERR_INVALID_ARG;
     }

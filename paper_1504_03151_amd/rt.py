@@ -96,7 +96,8 @@ class CacheLayout(C.Structure):
 
 
 CACHE_INFER, CACHE_TRAIN = 1, 2
-LAYOUT_DFS, LAYOUT_BFS, LAYOUT_TREELET, LAYOUT_BVH4 = 0, 1, 2, 3
+LAYOUT_DFS, LAYOUT_BFS, LAYOUT_TREELET, LAYOUT_BVH4, LAYOUT_BVH4Q = 0, 1, 2, 3, 4
+NODE_BYTES = {0: 64, 1: 64, 2: 64, 3: 128, 4: 64}   # bytes fetched per node visit, by layout
 TILE_8X8, TILE_16X4, TILE_32X2, TILE_4X16 = 0, 1, 2, 3
 TILE_SHAPES = {TILE_8X8: (8, 8), TILE_16X4: (16, 4), TILE_32X2: (32, 2), TILE_4X16: (4, 16)}
 

@@ -96,7 +96,7 @@ def test_workspace_and_render_argument_errors():
     assert rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)) == 0
 
 
-@pytest.mark.parametrize("layout", [rt.LAYOUT_DFS, rt.LAYOUT_BVH4])
+@pytest.mark.parametrize("layout", [rt.LAYOUT_DFS, rt.LAYOUT_BVH4, rt.LAYOUT_BVH4Q])
 def test_host_traversal_matches_brute_force_on_tiny_scenes(layout):
     for seed in range(6):
         w = S.random_tiny(seed, n_spheres=6, n_tris=80)
@@ -136,7 +136,7 @@ def test_bvh_info_and_work_counts_are_sane():
     assert work[:, 1].mean() < 0.01 * len(w.scene.tris)
 
 
-@pytest.mark.parametrize("layout", [rt.LAYOUT_BFS, rt.LAYOUT_TREELET, rt.LAYOUT_BVH4])
+@pytest.mark.parametrize("layout", [rt.LAYOUT_BFS, rt.LAYOUT_TREELET, rt.LAYOUT_BVH4, rt.LAYOUT_BVH4Q])
 def test_node_layouts_keep_every_hit_and_every_traversal_step(layout):
     """A node layout only renumbers nodes: the same rays must see the same hits (bit-equal t and id) and fetch
     the same number of nodes and primitives as in depth-first order, for closest and any hit.  The four-wide
@@ -146,7 +146,7 @@ def test_node_layouts_keep_every_hit_and_every_traversal_step(layout):
     base = rt.Scene(w.scene)
     other = rt.Scene(w.scene, node_layout=layout)
     assert other.info["node_layout"] == layout and base.info["node_layout"] == rt.LAYOUT_DFS
-    wide = layout == rt.LAYOUT_BVH4
+    wide = layout in (rt.LAYOUT_BVH4, rt.LAYOUT_BVH4Q)
     if wide:
         assert other.info["n_nodes"] < 0.6 * base.info["n_nodes"]
     else:
@@ -175,7 +175,7 @@ def test_node_layouts_keep_every_hit_and_every_traversal_step(layout):
     R = rt.make_rays(o, d)
     np.testing.assert_array_equal(base.host_trace(R)[1], other.host_trace(R)[1])
     with pytest.raises(rt.RTError, match="INVALID_ARG"):
-        other.set_layout(4)
+        other.set_layout(5)
     with pytest.raises(rt.RTError, match="INVALID_ARG"):
         rt.Scene(w.scene, node_layout=-1)
 

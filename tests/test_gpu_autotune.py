@@ -40,7 +40,7 @@ def test_every_tile_and_layout_gives_the_default_frame(rt):
     rgb0, ids0, st0 = rt.render(sc, w.camera, w.params)
     rgb0, ids0 = rgb0.clone(), ids0.clone()
     torch.cuda.synchronize()
-    for layout in (rt.LAYOUT_DFS, rt.LAYOUT_BFS, rt.LAYOUT_TREELET, rt.LAYOUT_BVH4):
+    for layout in (rt.LAYOUT_DFS, rt.LAYOUT_BFS, rt.LAYOUT_TREELET, rt.LAYOUT_BVH4, rt.LAYOUT_BVH4Q):
         s = rt.Scene(w.scene, node_layout=layout).upload()
         for tile in rt.TILE_SHAPES:
             rgb, ids, st = rt.render(s, w.camera, w.params, tile=tile, queue_chunk=64 if tile % 2 else 256)
@@ -82,7 +82,7 @@ def test_autotuner_picks_a_verified_setting_and_caches_it(rt, tmp_path):
     cfg = res["config"]
     assert cfg["layout"] in space["layout"] and cfg["chunk"] in space["chunk"] and cfg["tile"] in space["tile"]
     assert all(t["ids_match"] for t in res["trials"])
-    assert len(res["trials"]) >= 4 + 2 + 3
+    assert len(res["trials"]) >= 5 + 2 + 3
     assert res["ms"] <= res["default_ms"]
     assert all(s.info["node_layout"] == cfg["layout"] and s.blob is not None for s in scs)
     db = json.load(open(path))

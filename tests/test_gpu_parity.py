@@ -161,7 +161,7 @@ def test_intersect_and_occluded_on_oracle_rays(rt, cfg):
             np.testing.assert_allclose(t[hit], tr[hit], rtol=2e-5)
 
 
-@pytest.mark.parametrize("layout", [0, 3])         # binary depth-first, four-wide
+@pytest.mark.parametrize("layout", [0, 3, 4])      # binary depth-first, four-wide, quantized four-wide
 def test_random_rays_bvh_equals_brute_force(rt, layout):
     for seed in range(3):
         w = S.random_tiny(20 + seed, n_spheres=8, n_tris=200)
