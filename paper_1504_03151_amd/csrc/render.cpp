@@ -991,7 +991,8 @@ struct Plan {
     int spp_pass = 1, passes = 1;
     int64_t n_primary = 0;   // rays of a full pass
     uint32_t qcap = 0, scap = 0;
-    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_stack = 0, total = 0;
+    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_stack = 0, stack_bytes = 0,
+           total = 0;
 };
 
 // persistent traversal grids are capped at this many threads; each owns a
@@ -1056,8 +1057,10 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     off = a256(off + 2 * 4 * (size_t)pl.qcap + 2 * 256);
     pl.off_s = off;
     off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
+    // two overflow regions: closest-hit and shadow traversals may run at the same time
     pl.off_stack = off;
-    off = a256(off + 4 * (size_t)kMaxPersistentThreads * std::max(0, s.stack_size - kSplitLds));
+    pl.stack_bytes = a256(4 * (size_t)kMaxPersistentThreads * std::max(0, s.stack_size - kSplitLds));
+    off += 2 * pl.stack_bytes;
     pl.total = off;
     return true;
 }
@@ -1204,6 +1207,36 @@ static rt_status frame_grids(FrameArgs& A) {
     return RT_OK;
 }
 
+// Second stream of a device: the shadow traversal of depth k runs on it while
+// the closest-hit traversal of depth k + 1 runs on the frame's stream (the two
+// read different queues and use different overflow stacks); the shading of
+// depth k + 1 waits for it because it refills the shadow queue.  Events
+// fork[k] (after shading k) and join[k] (after the shadow traversal k) carry
+// the dependencies, also into a captured graph.  Enqueueing is serialized.
+struct AuxStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork[RT_STATS_MAX_DEPTH], join[RT_STATS_MAX_DEPTH];
+};
+static std::mutex g_aux_mu;
+
+static rt_status aux_stream(AuxStream*& out) {
+    static std::map<int, AuxStream> by_dev;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    auto it = by_dev.find(dev);
+    if (it == by_dev.end()) {
+        AuxStream a;
+        HIP_TRY(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+        for (int k = 0; k < RT_STATS_MAX_DEPTH; ++k) {
+            HIP_TRY(hipEventCreateWithFlags(&a.fork[k], hipEventDisableTiming));
+            HIP_TRY(hipEventCreateWithFlags(&a.join[k], hipEventDisableTiming));
+        }
+        it = by_dev.emplace(dev, a).first;
+    }
+    out = &it->second;
+    return RT_OK;
+}
+
 static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     const Plan& pl = A.pl;
     uint32_t* ctr = reinterpret_cast<uint32_t*>(A.ws + pl.off_ctr);
@@ -1217,6 +1250,11 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
     unsigned long long* swork = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->shadow_node_visits) : nullptr;
 
+    int32_t* overflow_s = reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes);
+    std::lock_guard<std::mutex> aux_lock(g_aux_mu);
+    AuxStream* X = nullptr;
+    rt_status ars = aux_stream(X);
+    if (ars != RT_OK) return ars;
     const int64_t n3 = 3 * pl.nacc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
     const int tiles_x = (int)tiles_x_of(A.cam.W, A.tile), tiles_y = (int)tiles_y_of(A.cam.H, A.tile);
@@ -1241,23 +1279,28 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
                                    ctr + kCtrRays + k,
                                    ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             }
+            if (k > 0) HIP_TRY(hipStreamWaitEvent(st, X->join[k - 1], 0));
             {
             KernelTimer kt(A.time_kernels, st, 1);
             hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr, qi, hq,
                                ctr, k, qo, sq, acc);
             }
+            HIP_TRY(hipEventRecord(X->fork[k], st));
+            HIP_TRY(hipStreamWaitEvent(X->s, X->fork[k], 0));
             {
-            KernelTimer kt(A.time_kernels, st, 2);
+            KernelTimer kt(A.time_kernels, X->s, 2);
             if (A.count_work)
-                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sq,
+                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, X->s, A.sc, nullptr, sq,
                                    ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow, swork);
+                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s, swork);
             else
-                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sq,
+                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, X->s, A.sc, nullptr, sq,
                                    ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow, swork);
+                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s, swork);
             }
+            HIP_TRY(hipEventRecord(X->join[k], X->s));
         }
+        HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth], 0));
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth, 0);
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
