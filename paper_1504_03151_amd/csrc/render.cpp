@@ -991,8 +991,8 @@ struct Plan {
     int spp_pass = 1, passes = 1;
     int64_t n_primary = 0;   // rays of a full pass
     uint32_t qcap = 0, scap = 0;
-    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_stack = 0, stack_bytes = 0,
-           total = 0;
+    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_s2 = 0, off_stack = 0,
+           stack_bytes = 0, total = 0;
 };
 
 // persistent traversal grids are capped at this many threads; each owns a
@@ -1001,7 +1001,8 @@ constexpr uint32_t kMaxPersistentThreads = 1u << 20;
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params& p, Plan& pl, std::string& why) {
+static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params& p, Plan& pl, std::string& why,
+                      bool dual_shadow = true) {
     if (cam.width <= 0 || cam.height <= 0) {
         why = "camera width and height must be > 0";
         return false;
@@ -1057,10 +1058,17 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     off = a256(off + 2 * 4 * (size_t)pl.qcap + 2 * 256);
     pl.off_s = off;
     off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
-    // two overflow regions: closest-hit and shadow traversals may run at the same time
+    // plain frames keep two shadow queues (depths alternate) so that shadow
+    // traversals of consecutive depths and the next closest-hit traversal can
+    // run at the same time, each with its own overflow stack region
+    pl.off_s2 = pl.off_s;
+    if (dual_shadow) {
+        pl.off_s2 = off;
+        off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
+    }
     pl.off_stack = off;
     pl.stack_bytes = a256(4 * (size_t)kMaxPersistentThreads * std::max(0, s.stack_size - kSplitLds));
-    off += 2 * pl.stack_bytes;
+    off += 3 * pl.stack_bytes;
     pl.total = off;
     return true;
 }
@@ -1207,14 +1215,15 @@ static rt_status frame_grids(FrameArgs& A) {
     return RT_OK;
 }
 
-// Second stream of a device: the shadow traversal of depth k runs on it while
-// the closest-hit traversal of depth k + 1 runs on the frame's stream (the two
-// read different queues and use different overflow stacks); the shading of
-// depth k + 1 waits for it because it refills the shadow queue.  Events
-// fork[k] (after shading k) and join[k] (after the shadow traversal k) carry
-// the dependencies, also into a captured graph.  Enqueueing is serialized.
+// Two more streams of a device: the shadow traversal of depth k runs on
+// stream k % 2 while the closest-hit traversal and shading of depth k + 1 (and
+// the shadow traversal of depth k + 1) go on; they read different queues and
+// use different overflow stacks.  Shading of depth k waits for the shadow
+// traversal of depth k - 2, whose queue it refills.  Events fork[k] (after
+// shading k) and join[k] (after the shadow traversal k) carry the
+// dependencies, also into a captured graph.  Enqueueing is serialized.
 struct AuxStream {
-    hipStream_t s = nullptr;
+    hipStream_t s[2] = {nullptr, nullptr};   // shadow traversals of even and odd depths
     hipEvent_t fork[RT_STATS_MAX_DEPTH], join[RT_STATS_MAX_DEPTH];
 };
 static std::mutex g_aux_mu;
@@ -1226,7 +1235,8 @@ static rt_status aux_stream(AuxStream*& out) {
     auto it = by_dev.find(dev);
     if (it == by_dev.end()) {
         AuxStream a;
-        HIP_TRY(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&a.s[0], hipStreamNonBlocking));
+        HIP_TRY(hipStreamCreateWithFlags(&a.s[1], hipStreamNonBlocking));
         for (int k = 0; k < RT_STATS_MAX_DEPTH; ++k) {
             HIP_TRY(hipEventCreateWithFlags(&a.fork[k], hipEventDisableTiming));
             HIP_TRY(hipEventCreateWithFlags(&a.join[k], hipEventDisableTiming));
@@ -1243,14 +1253,15 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     float* acc = reinterpret_cast<float*>(A.ws + pl.off_acc);
     RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
     HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
-    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap, false);
+    ShadowQ sqs[2] = {shadow_queue(A.ws + pl.off_s, pl.scap, false), shadow_queue(A.ws + pl.off_s2, pl.scap, false)};
     int32_t* overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack);
     const size_t lds = A.lds;
     const int gx = A.gx, gs = A.gs, shade_blocks = A.shade_blocks;
     unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
     unsigned long long* swork = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->shadow_node_visits) : nullptr;
 
-    int32_t* overflow_s = reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes);
+    int32_t* overflow_s[2] = {reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes),
+                              reinterpret_cast<int32_t*>(A.ws + pl.off_stack + 2 * pl.stack_bytes)};
     std::lock_guard<std::mutex> aux_lock(g_aux_mu);
     AuxStream* X = nullptr;
     rt_status ars = aux_stream(X);
@@ -1279,28 +1290,31 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
                                    ctr + kCtrRays + k,
                                    ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             }
-            if (k > 0) HIP_TRY(hipStreamWaitEvent(st, X->join[k - 1], 0));
+            const int b = k & 1;
+            ShadowQ& sq = sqs[b];
+            if (k > 1) HIP_TRY(hipStreamWaitEvent(st, X->join[k - 2], 0));
             {
             KernelTimer kt(A.time_kernels, st, 1);
             hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr, qi, hq,
                                ctr, k, qo, sq, acc);
             }
             HIP_TRY(hipEventRecord(X->fork[k], st));
-            HIP_TRY(hipStreamWaitEvent(X->s, X->fork[k], 0));
+            HIP_TRY(hipStreamWaitEvent(X->s[b], X->fork[k], 0));
             {
-            KernelTimer kt(A.time_kernels, X->s, 2);
+            KernelTimer kt(A.time_kernels, X->s[b], 2);
             if (A.count_work)
-                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, X->s, A.sc, nullptr, sq,
+                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, X->s[b], A.sc, nullptr, sq,
                                    ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s, swork);
+                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s[b], swork);
             else
-                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, X->s, A.sc, nullptr, sq,
+                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, X->s[b], A.sc, nullptr, sq,
                                    ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s, swork);
+                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s[b], swork);
             }
-            HIP_TRY(hipEventRecord(X->join[k], X->s));
+            HIP_TRY(hipEventRecord(X->join[k], X->s[b]));
         }
         HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth], 0));
+        if (A.shc.max_depth > 0) HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth - 1], 0));
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth, 0);
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
@@ -1717,7 +1731,7 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
         if (!(c.bounds_hi[k] > c.bounds_lo[k])) c.bounds_hi[k] = c.bounds_lo[k] + 1.0f;
     rt_params q = p;
     q.samples_per_pass = p.spp;   // cache frames trace every sample in one pass
-    if (!make_plan(h, cam, q, cp.base, why)) return false;
+    if (!make_plan(h, cam, q, cp.base, why, false)) return false;
     cp.c = c;
     if (!cache_layout(c.train_samples, cp.L)) {
         why = "train_samples must be in [1, 2^24]";
