@@ -48,6 +48,7 @@ struct ShadowQ {
     float *ox, *oy, *oz, *dx, *dy, *dz, *tmax, *cr, *cg, *cb;
     uint32_t* pix;
     uint32_t* sid;   // scene of each entry (batched frames only)
+    uint32_t* key;   // bin of each entry (deferred shadows: light and origin cell), or NULL
 };
 struct HitQ {
     float* t;
@@ -61,6 +62,8 @@ constexpr int kCtrShadow = 32;    // [16] shadow rays queued at depth k
 constexpr int kCtrShadowCur = 48; // [16] shadow fetch cursors
 constexpr int kCtrStatus = 64;    // overflow flags
 constexpr int kCtrDead = 65;      // padding slots of ragged tiles in the primary queue
+constexpr int kCtrShadowAll = 66; // shadow rays of every depth of a pass (deferred shadow traversal)
+constexpr int kCtrShadowAllCur = 67;
 constexpr int kCtrWords = 128;     // words cleared at the start of every pass
 constexpr int kCtrFrame = 128;     // frame number, written by the host before each launch
 constexpr int kCtrRec = 129;       // learned form: cache queries recorded this frame (cleared per frame)
@@ -99,6 +102,11 @@ struct ShadeConst {
     int per_sample;     // accumulation slot = pixel * spp + sample instead of pixel
     uint32_t acc_off;   // first accumulation slot of the scene
     int32_t* out_ids;   // [H][W][spp] or NULL
+    int defer_shadow;   // 1: shadow rays of all depths go to one queue, traced after the last bounce
+    // deferred shadows are binned by (light, origin cell) before they are traced:
+    // cell = floor((x - bin_lo) * bin_inv) per axis on a bin_c^3 grid over the scene
+    float bin_lo[3], bin_inv[3];
+    int bin_c;
 };
 
 // One scene of a batched frame (device table, one entry per scene).
@@ -375,7 +383,7 @@ template <bool COUNT, bool BATCH>
 __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* tab, ShadowQ s,
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
                                                 uint32_t chunk, float* acc, int32_t* overflow,
-                                                unsigned long long* work_out) {
+                                                unsigned long long* work_out, const uint32_t* perm = nullptr) {
     __shared__ int32_t smem[4 * kSplitLds * 64];
     SplitStack stk = split_stack(smem, overflow);
     const uint32_t count = min(*count_p, cap);
@@ -387,8 +395,9 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* t
         if (base >= count) break;
         const uint32_t end = min(base + chunk, count);
         for (uint32_t b = base; b < end; b += 64) {
-            const uint32_t i = b + lane_id();
-            if (i < end) {
+            const uint32_t j = b + lane_id();
+            if (j < end) {
+                const uint32_t i = perm ? perm[j] : j;   // binned order of deferred shadow rays
                 const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? s.sid[i] : 0u);
                 const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
                 const Hit h = traverse<true, COUNT>(S, r, s.tmax[i], stk, w);
@@ -402,6 +411,71 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* t
         }
     }
     flush_work<COUNT>(w, work_out);
+}
+
+// Binning of the deferred shadow queue (a counting sort by key, keys < nb):
+// k_bin_count adds per-bin counts, k_bin_scan turns them into first slots,
+// k_bin_scatter writes every entry's index into its bin's range of perm.
+// Blocks work on chunks of kBinChunk entries with a histogram in LDS, so the
+// global atomics are per (chunk, bin), not per entry.  Order inside a bin is
+// arbitrary.
+constexpr int kBinMax = 4096;
+constexpr uint32_t kBinChunk = 16384;
+
+__global__ __launch_bounds__(256) void k_bin_count(const uint32_t* key, const uint32_t* count_p, uint32_t cap,
+                                                   uint32_t* hist, int nb) {
+    __shared__ uint32_t h[kBinMax];
+    const uint32_t count = min(*count_p, cap);
+    for (uint32_t c0 = blockIdx.x * kBinChunk; c0 < count; c0 += gridDim.x * kBinChunk) {   // block-uniform
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
+        __syncthreads();
+        const uint32_t c1 = min(c0 + kBinChunk, count);
+        for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) atomicAdd(&h[key[i]], 1u);
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            if (h[b]) atomicAdd(hist + b, h[b]);
+        __syncthreads();
+    }
+}
+
+// one block of 1024 threads: exclusive scan of hist[0, nb) into first[0, nb)
+__global__ __launch_bounds__(1024) void k_bin_scan(const uint32_t* hist, uint32_t* first, int nb) {
+    __shared__ uint32_t part[1024];
+    const int per = (nb + 1023) / 1024;
+    const int b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+    uint32_t sum = 0;
+    for (int b = b0; b < b1; ++b) sum += hist[b];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {   // Hillis-Steele inclusive scan
+        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (int b = b0; b < b1; ++b) {
+        first[b] = run;
+        run += hist[b];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t* key, const uint32_t* count_p, uint32_t cap,
+                                                     uint32_t* first, uint32_t* perm, int nb) {
+    __shared__ uint32_t h[kBinMax];
+    const uint32_t count = min(*count_p, cap);
+    for (uint32_t c0 = blockIdx.x * kBinChunk; c0 < count; c0 += gridDim.x * kBinChunk) {   // block-uniform
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
+        __syncthreads();
+        const uint32_t c1 = min(c0 + kBinChunk, count);
+        for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) atomicAdd(&h[key[i]], 1u);
+        __syncthreads();
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            if (h[b]) h[b] = atomicAdd(first + b, h[b]);   // this chunk's range inside the bin
+        __syncthreads();
+        for (uint32_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) perm[atomicAdd(&h[key[i]], 1u)] = i;
+        __syncthreads();
+    }
 }
 
 // x^n for a non-negative integer n by repeated squaring; other exponents use powf.
@@ -421,7 +495,8 @@ __device__ __forceinline__ float pow_spec(float x, float n) {
 
 // Block-wide reservation: each wave passes its total, one atomic per block and
 // queue; returns the wave's base slot.  All threads of the block must call.
-__device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, uint32_t* tail, uint32_t* lds4) {
+__device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, uint32_t* tail, uint32_t* lds4,
+                                                  uint32_t* also = nullptr) {
     const uint32_t wave = threadIdx.x >> 6;
     if (lane_id() == 0) lds4[wave] = wave_total;
     __syncthreads();
@@ -429,6 +504,7 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, uint32_t*
         const uint32_t t0 = lds4[0], t1 = lds4[1], t2 = lds4[2], t3 = lds4[3];
         const uint32_t tot = t0 + t1 + t2 + t3;
         const uint32_t base = tot ? atomicAdd(tail, tot) : 0u;
+        if (tot && also) atomicAdd(also, tot);   // a second count (per-depth statistics)
         lds4[0] = base;
         lds4[1] = base + t0;
         lds4[2] = base + t0 + t1;
@@ -464,9 +540,14 @@ __device__ __forceinline__ LightTerm light_term(const DevLight& L, V3 x, V3 nf, 
     return t;
 }
 
+__device__ __forceinline__ uint32_t bin_axis(float x, float lo, float inv, int c) {
+    const float f = fminf(fmaxf((x - lo) * inv, 0.0f), (float)(c - 1));   // NaN -> 0
+    return (uint32_t)f;
+}
+
 __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, uint32_t cap, uint32_t* ctr, V3 xs,
                                              const DevLight& L, V3 w, const LightTerm& lt, uint32_t pix,
-                                             uint32_t sid) {
+                                             uint32_t sid, const ShadeConst& C, int l) {
     if (slot >= cap) {
         atomicOr(ctr + kCtrStatus, 2u);
         return;
@@ -486,6 +567,13 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
     sq.cb[slot] = w.z * lt.cb;
     sq.pix[slot] = pix;
     if (sq.sid) sq.sid[slot] = sid;
+    if (sq.key) {
+        const int c = C.bin_c;
+        const uint32_t cell = bin_axis(xs.x, C.bin_lo[0], C.bin_inv[0], c) +
+                              (uint32_t)c * (bin_axis(xs.y, C.bin_lo[1], C.bin_inv[1], c) +
+                                             (uint32_t)c * bin_axis(xs.z, C.bin_lo[2], C.bin_inv[2], c));
+        sq.key[slot] = (uint32_t)(l & 31) * (uint32_t)(c * c * c) + cell;
+    }
 }
 
 // Shading of one depth: Phong local terms (ambient now, light terms deferred to
@@ -584,7 +672,10 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
         }
         uint32_t wave_tot;
         const uint32_t lane_off = wave_scan(n_sh, wave_tot);
-        const uint32_t wave_base = block_reserve(wave_tot, ctr + kCtrShadow + depth, lds_res);
+        // deferred: one queue for the shadow rays of every depth, traced once at the end of the pass
+        const uint32_t wave_base =
+            C.defer_shadow ? block_reserve(wave_tot, ctr + kCtrShadowAll, lds_res, ctr + kCtrShadow + depth)
+                           : block_reserve(wave_tot, ctr + kCtrShadow + depth, lds_res);
         if (light_major) {
             // light-major: for each light, the wave's emitting lanes take consecutive slots
             uint32_t run = wave_base;
@@ -595,7 +686,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
                     const uint32_t slot = run + __builtin_amdgcn_mbcnt_hi(
                                                     (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                     const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
-                    write_shadow(sq, slot, scap, ctr, xs, S.lights[l], w, lt, pix, sid);
+                    write_shadow(sq, slot, scap, ctr, xs, S.lights[l], w, lt, pix, sid, C, l);
                 }
                 run += (uint32_t)__popcll(bal);
             }
@@ -604,7 +695,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
             for (int l = 0; l < S.n_lights; ++l) {
                 const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
                 if (!lt.emit) continue;
-                write_shadow(sq, slot++, scap, ctr, xs, S.lights[l], w, lt, pix, sid);
+                write_shadow(sq, slot++, scap, ctr, xs, S.lights[l], w, lt, pix, sid, C, l);
             }
         }
         // ---- secondary rays
@@ -991,8 +1082,8 @@ struct Plan {
     int spp_pass = 1, passes = 1;
     int64_t n_primary = 0;   // rays of a full pass
     uint32_t qcap = 0, scap = 0;
-    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_s2 = 0, off_stack = 0,
-           stack_bytes = 0, total = 0;
+    size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_s2 = 0, off_bins = 0,
+           off_stack = 0, stack_bytes = 0, total = 0;
 };
 
 // persistent traversal grids are capped at this many threads; each owns a
@@ -1062,10 +1153,12 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     // traversals of consecutive depths and the next closest-hit traversal can
     // run at the same time, each with its own overflow stack region
     pl.off_s2 = pl.off_s;
-    if (dual_shadow) {
+    if (dual_shadow) {   // a second shadow queue, or the keys and order of the deferred one
         pl.off_s2 = off;
         off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
     }
+    pl.off_bins = off;   // per-bin counts and first slots of the deferred shadow queue
+    off = a256(off + 2 * 4 * (size_t)kBinMax);
     pl.off_stack = off;
     pl.stack_bytes = a256(4 * (size_t)kMaxPersistentThreads * std::max(0, s.stack_size - kSplitLds));
     off += 3 * pl.stack_bytes;
@@ -1089,7 +1182,7 @@ static ShadowQ shadow_queue(uint8_t* base, uint32_t cap, bool with_sid) {
     for (int k = 0; k < 10; ++k) f[k] = reinterpret_cast<float*>(base + k * stride);
     ShadowQ s{f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], f[9],
               reinterpret_cast<uint32_t*>(base + 10 * stride),
-              with_sid ? reinterpret_cast<uint32_t*>(base + 11 * stride) : nullptr};
+              with_sid ? reinterpret_cast<uint32_t*>(base + 11 * stride) : nullptr, nullptr};
     return s;
 }
 
@@ -1196,6 +1289,7 @@ struct FrameArgs {
     bool time_kernels;
     uint32_t chunk;             // queue entries per fetch of a persistent traversal wave
     int tile;                   // RT_TILE_* of the primary rays
+    bool bin_shadows;           // deferred shadow rays are binned before their traversal
 };
 
 static rt_status frame_grids(FrameArgs& A) {
@@ -1262,6 +1356,13 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
 
     int32_t* overflow_s[2] = {reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes),
                               reinterpret_cast<int32_t*>(A.ws + pl.off_stack + 2 * pl.stack_bytes)};
+    uint32_t* perm = nullptr;
+    uint32_t* bins = reinterpret_cast<uint32_t*>(A.ws + pl.off_bins);
+    const int nb = std::max(1, std::min(A.sc.n_lights, 32)) * A.shc.bin_c * A.shc.bin_c * A.shc.bin_c;
+    if (A.shc.defer_shadow && A.bin_shadows) {
+        sqs[0].key = reinterpret_cast<uint32_t*>(A.ws + pl.off_s2);
+        perm = reinterpret_cast<uint32_t*>(A.ws + pl.off_s2 + a256(4 * (size_t)pl.scap));
+    }
     std::lock_guard<std::mutex> aux_lock(g_aux_mu);
     AuxStream* X = nullptr;
     rt_status ars = aux_stream(X);
@@ -1290,6 +1391,12 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
                                    ctr + kCtrRays + k,
                                    ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             }
+            if (A.shc.defer_shadow) {
+                KernelTimer kt(A.time_kernels, st, 1);
+                hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr, qi, hq,
+                                   ctr, k, qo, sqs[0], acc);
+                continue;
+            }
             const int b = k & 1;
             ShadowQ& sq = sqs[b];
             if (k > 1) HIP_TRY(hipStreamWaitEvent(st, X->join[k - 2], 0));
@@ -1313,8 +1420,28 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
             }
             HIP_TRY(hipEventRecord(X->join[k], X->s[b]));
         }
-        HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth], 0));
-        if (A.shc.max_depth > 0) HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth - 1], 0));
+        if (A.shc.defer_shadow) {
+            if (perm) {   // counting sort of the pass's shadow rays by (light, origin cell)
+                hipLaunchKernelGGL(k_zero_u32, dim3((nb + 255) / 256), dim3(256), 0, st, bins, nb);
+                hipLaunchKernelGGL(k_bin_count, dim3(1024), dim3(256), 0, st, sqs[0].key, ctr + kCtrShadowAll, pl.scap,
+                                   bins, nb);
+                hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bins, bins + kBinMax, nb);
+                hipLaunchKernelGGL(k_bin_scatter, dim3(1024), dim3(256), 0, st, sqs[0].key, ctr + kCtrShadowAll,
+                                   pl.scap, bins + kBinMax, perm, nb);
+            }
+            KernelTimer kt(A.time_kernels, st, 2);
+            if (A.count_work)
+                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sqs[0],
+                                   ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, A.chunk, acc, overflow_s[0],
+                                   swork, perm);
+            else
+                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sqs[0],
+                                   ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, A.chunk, acc, overflow_s[0],
+                                   swork, perm);
+        } else {
+            HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth], 0));
+            if (A.shc.max_depth > 0) HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth - 1], 0));
+        }
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth, 0);
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
@@ -1363,6 +1490,7 @@ static rt_status launch_frame(const FrameArgs& A, hipStream_t st, bool use_graph
     put(key.bytes, A.gs);
     put(key.bytes, A.shade_blocks);
     put(key.bytes, A.chunk);
+    put(key.bytes, A.bin_shadows);
     std::lock_guard<std::mutex> g(g_graph_mu);
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
@@ -2023,6 +2151,17 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
     A.shc.acc_off = 0;
     A.shc.out_ids = out_hit_ids;
+    A.shc.defer_shadow = 1;
+    A.bin_shadows = true;
+    {
+        const int L = std::max(1, std::min(scene->h.n_lights, 32));
+        A.shc.bin_c = L <= 8 ? 8 : 4;   // L * bin_c^3 <= 4096 bins
+        for (int k = 0; k < 3; ++k) {
+            const float lo = scene->h.info.bounds_lo[k], hi = scene->h.info.bounds_hi[k];
+            A.shc.bin_lo[k] = lo;
+            A.shc.bin_inv[k] = hi > lo ? (float)A.shc.bin_c / (hi - lo) : 0.0f;
+        }
+    }
     A.pl = pl;
     A.ws = static_cast<uint8_t*>(p.workspace);
     A.stats = static_cast<rt_stats*>(p.stats);
