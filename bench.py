@@ -348,7 +348,8 @@ def main():
     assert cst["status"] == 0, cst
     rays = sum(cst["rays"])
     shadow = sum(cst["shadow"])
-    log(f"rays/frame {rays} closest-hit + {shadow} shadow; passes {cst['passes']}")
+    log(f"rays/frame {rays} closest-hit + {shadow} shadow; passes {cst['passes']}; per depth closest "
+        f"{cst['rays'][:w.params.max_depth + 1]} shadow {cst['shadow'][:w.params.max_depth + 1]}")
 
     flags = 0 if args.graph else rt.FLAG_TIME_KERNELS
     for _ in range(args.warmup):

@@ -383,10 +383,14 @@ template <bool COUNT, bool BATCH>
 __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* tab, ShadowQ s,
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
                                                 uint32_t chunk, float* acc, int32_t* overflow,
-                                                unsigned long long* work_out, const uint32_t* perm = nullptr) {
+                                                unsigned long long* work_out, const uint32_t* perm = nullptr,
+                                                const uint32_t* begin_p = nullptr) {
     __shared__ int32_t smem[4 * kSplitLds * 64];
     SplitStack stk = split_stack(smem, overflow);
-    const uint32_t count = min(*count_p, cap);
+    // entries [begin, end) of the queue; with perm, perm[0, end - begin) lists them in binned order
+    const uint32_t end_all = min(*count_p, cap);
+    const uint32_t begin = begin_p ? min(*begin_p, end_all) : 0u;
+    const uint32_t count = end_all - begin;
     Work w{0, 0, 0};
     for (;;) {
         uint32_t base = 0;
@@ -397,7 +401,7 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* t
         for (uint32_t b = base; b < end; b += 64) {
             const uint32_t j = b + lane_id();
             if (j < end) {
-                const uint32_t i = perm ? perm[j] : j;   // binned order of deferred shadow rays
+                const uint32_t i = perm ? perm[j] : begin + j;   // binned order of deferred shadow rays
                 const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? s.sid[i] : 0u);
                 const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
                 const Hit h = traverse<true, COUNT>(S, r, s.tmax[i], stk, w);
@@ -422,11 +426,12 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* t
 constexpr int kBinMax = 4096;
 constexpr uint32_t kBinChunk = 16384;
 
-__global__ __launch_bounds__(256) void k_bin_count(const uint32_t* key, const uint32_t* count_p, uint32_t cap,
-                                                   uint32_t* hist, int nb) {
+__global__ __launch_bounds__(256) void k_bin_count(const uint32_t* key, const uint32_t* begin_p,
+                                                   const uint32_t* count_p, uint32_t cap, uint32_t* hist, int nb) {
     __shared__ uint32_t h[kBinMax];
     const uint32_t count = min(*count_p, cap);
-    for (uint32_t c0 = blockIdx.x * kBinChunk; c0 < count; c0 += gridDim.x * kBinChunk) {   // block-uniform
+    const uint32_t begin = begin_p ? min(*begin_p, count) : 0u;
+    for (uint32_t c0 = begin + blockIdx.x * kBinChunk; c0 < count; c0 += gridDim.x * kBinChunk) {   // block-uniform
         for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
         __syncthreads();
         const uint32_t c1 = min(c0 + kBinChunk, count);
@@ -460,11 +465,13 @@ __global__ __launch_bounds__(1024) void k_bin_scan(const uint32_t* hist, uint32_
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t* key, const uint32_t* count_p, uint32_t cap,
-                                                     uint32_t* first, uint32_t* perm, int nb) {
+__global__ __launch_bounds__(256) void k_bin_scatter(const uint32_t* key, const uint32_t* begin_p,
+                                                     const uint32_t* count_p, uint32_t cap, uint32_t* first,
+                                                     uint32_t* perm, int nb) {
     __shared__ uint32_t h[kBinMax];
     const uint32_t count = min(*count_p, cap);
-    for (uint32_t c0 = blockIdx.x * kBinChunk; c0 < count; c0 += gridDim.x * kBinChunk) {   // block-uniform
+    const uint32_t begin = begin_p ? min(*begin_p, count) : 0u;
+    for (uint32_t c0 = begin + blockIdx.x * kBinChunk; c0 < count; c0 += gridDim.x * kBinChunk) {   // block-uniform
         for (int b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0u;
         __syncthreads();
         const uint32_t c1 = min(c0 + kBinChunk, count);
@@ -1093,7 +1100,7 @@ constexpr uint32_t kMaxPersistentThreads = 1u << 20;
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params& p, Plan& pl, std::string& why,
-                      bool dual_shadow = true) {
+                      bool bin_space = true) {
     if (cam.width <= 0 || cam.height <= 0) {
         why = "camera width and height must be > 0";
         return false;
@@ -1149,19 +1156,17 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     off = a256(off + 2 * 4 * (size_t)pl.qcap + 2 * 256);
     pl.off_s = off;
     off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
-    // plain frames keep two shadow queues (depths alternate) so that shadow
-    // traversals of consecutive depths and the next closest-hit traversal can
-    // run at the same time, each with its own overflow stack region
+    // plain frames bin their deferred shadow queue: a key and an order slot per entry
     pl.off_s2 = pl.off_s;
-    if (dual_shadow) {   // a second shadow queue, or the keys and order of the deferred one
+    if (bin_space) {
         pl.off_s2 = off;
-        off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
+        off = a256(off + 2 * a256(4 * (size_t)pl.scap));
     }
     pl.off_bins = off;   // per-bin counts and first slots of the deferred shadow queue
     off = a256(off + 2 * 4 * (size_t)kBinMax);
-    pl.off_stack = off;
+    pl.off_stack = off;   // overflow stacks: closest-hit and shadow traversals
     pl.stack_bytes = a256(4 * (size_t)kMaxPersistentThreads * std::max(0, s.stack_size - kSplitLds));
-    off += 3 * pl.stack_bytes;
+    off += 2 * pl.stack_bytes;
     pl.total = off;
     return true;
 }
@@ -1309,64 +1314,81 @@ static rt_status frame_grids(FrameArgs& A) {
     return RT_OK;
 }
 
-// Two more streams of a device: the shadow traversal of depth k runs on
-// stream k % 2 while the closest-hit traversal and shading of depth k + 1 (and
-// the shadow traversal of depth k + 1) go on; they read different queues and
-// use different overflow stacks.  Shading of depth k waits for the shadow
-// traversal of depth k - 2, whose queue it refills.  Events fork[k] (after
-// shading k) and join[k] (after the shadow traversal k) carry the
-// dependencies, also into a captured graph.  Enqueueing is serialized.
-struct AuxStream {
-    hipStream_t s[2] = {nullptr, nullptr};   // shadow traversals of even and odd depths
-    hipEvent_t fork[RT_STATS_MAX_DEPTH], join[RT_STATS_MAX_DEPTH];
+// Shadow traversal of the deferred queue's entries [*begin_p, *end_p) on
+// stream `st`: optionally binned first (counting sort into perm), then traced
+// by `grid` persistent blocks.
+struct ShadowSegment {
+    const uint32_t* begin_p;   // NULL: from 0
+    const uint32_t* end_p;
+    uint32_t cap;              // queue capacity
+    uint32_t* cursor;
+    uint32_t* perm;            // NULL: queue order
+    uint32_t* bins;            // [2 * kBinMax]: counts, then first slots
+    int32_t* overflow;
+    int grid;
 };
-static std::mutex g_aux_mu;
 
-static rt_status aux_stream(AuxStream*& out) {
-    static std::map<int, AuxStream> by_dev;
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    auto it = by_dev.find(dev);
-    if (it == by_dev.end()) {
-        AuxStream a;
-        HIP_TRY(hipStreamCreateWithFlags(&a.s[0], hipStreamNonBlocking));
-        HIP_TRY(hipStreamCreateWithFlags(&a.s[1], hipStreamNonBlocking));
-        for (int k = 0; k < RT_STATS_MAX_DEPTH; ++k) {
-            HIP_TRY(hipEventCreateWithFlags(&a.fork[k], hipEventDisableTiming));
-            HIP_TRY(hipEventCreateWithFlags(&a.join[k], hipEventDisableTiming));
-        }
-        it = by_dev.emplace(dev, a).first;
+// Shadow rays of every depth go to one deferred queue, binned by light and by
+// a cell of a grid over the scene bounds (at most 4096 bins).
+static void defer_and_bin_shadows(FrameArgs& A, const SceneHost& h) {
+    A.shc.defer_shadow = 1;
+    A.bin_shadows = true;
+    const int L = std::max(1, std::min(h.n_lights, 32));
+    A.shc.bin_c = L <= 8 ? 8 : 4;   // L * bin_c^3 <= kBinMax
+    for (int k = 0; k < 3; ++k) {
+        const float lo = h.info.bounds_lo[k], hi = h.info.bounds_hi[k];
+        A.shc.bin_lo[k] = lo;
+        A.shc.bin_inv[k] = hi > lo ? (float)A.shc.bin_c / (hi - lo) : 0.0f;
     }
-    out = &it->second;
-    return RT_OK;
 }
 
+static void enqueue_shadow_segment(const FrameArgs& A, const ShadowQ& sq, const ShadowSegment& g, int nb, float* acc,
+                                   unsigned long long* swork, hipStream_t st) {
+    if (g.perm) {
+        hipLaunchKernelGGL(k_zero_u32, dim3((nb + 255) / 256), dim3(256), 0, st, g.bins, nb);
+        hipLaunchKernelGGL(k_bin_count, dim3(1024), dim3(256), 0, st, sq.key, g.begin_p, g.end_p, g.cap, g.bins, nb);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, g.bins, g.bins + kBinMax, nb);
+        hipLaunchKernelGGL(k_bin_scatter, dim3(1024), dim3(256), 0, st, sq.key, g.begin_p, g.end_p, g.cap,
+                           g.bins + kBinMax, g.perm, nb);
+    }
+    KernelTimer kt(A.time_kernels, st, 2);
+    if (A.count_work)
+        hipLaunchKernelGGL((k_shadow<true, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq, g.end_p,
+                           g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p);
+    else
+        hipLaunchKernelGGL((k_shadow<false, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq, g.end_p,
+                           g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p);
+}
+
+// One plain frame.  Per pass: ray generation, then for each depth the
+// closest-hit traversal and the shading, which appends the depth's shadow rays
+// to one deferred queue (shadow rays feed only the accumulator, so nothing
+// waits for them); after the last bounce the queue is binned by light and
+// origin cell and traced in one launch, free of the per-depth launch tails.
 static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     const Plan& pl = A.pl;
     uint32_t* ctr = reinterpret_cast<uint32_t*>(A.ws + pl.off_ctr);
     float* acc = reinterpret_cast<float*>(A.ws + pl.off_acc);
     RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
     HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
-    ShadowQ sqs[2] = {shadow_queue(A.ws + pl.off_s, pl.scap, false), shadow_queue(A.ws + pl.off_s2, pl.scap, false)};
+    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap, false);
     int32_t* overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack);
-    const size_t lds = A.lds;
-    const int gx = A.gx, gs = A.gs, shade_blocks = A.shade_blocks;
+    const int gx = A.gx, shade_blocks = A.shade_blocks;
     unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
     unsigned long long* swork = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->shadow_node_visits) : nullptr;
-
-    int32_t* overflow_s[2] = {reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes),
-                              reinterpret_cast<int32_t*>(A.ws + pl.off_stack + 2 * pl.stack_bytes)};
-    uint32_t* perm = nullptr;
+    const size_t stride = a256(4 * (size_t)pl.scap);
     uint32_t* bins = reinterpret_cast<uint32_t*>(A.ws + pl.off_bins);
     const int nb = std::max(1, std::min(A.sc.n_lights, 32)) * A.shc.bin_c * A.shc.bin_c * A.shc.bin_c;
-    if (A.shc.defer_shadow && A.bin_shadows) {
-        sqs[0].key = reinterpret_cast<uint32_t*>(A.ws + pl.off_s2);
-        perm = reinterpret_cast<uint32_t*>(A.ws + pl.off_s2 + a256(4 * (size_t)pl.scap));
-    }
-    std::lock_guard<std::mutex> aux_lock(g_aux_mu);
-    AuxStream* X = nullptr;
-    rt_status ars = aux_stream(X);
-    if (ars != RT_OK) return ars;
+    if (A.bin_shadows) sq.key = reinterpret_cast<uint32_t*>(A.ws + pl.off_s2);
+    ShadowSegment seg;
+    seg.begin_p = nullptr;
+    seg.cap = pl.scap;
+    seg.end_p = ctr + kCtrShadowAll;
+    seg.cursor = ctr + kCtrShadowAllCur;
+    seg.perm = A.bin_shadows ? reinterpret_cast<uint32_t*>(A.ws + pl.off_s2 + stride) : nullptr;
+    seg.bins = bins;
+    seg.overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes);
+    seg.grid = A.gs;
     const int64_t n3 = 3 * pl.nacc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
     const int tiles_x = (int)tiles_x_of(A.cam.W, A.tile), tiles_y = (int)tiles_y_of(A.cam.H, A.tile);
@@ -1381,67 +1403,21 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
             RayQ& qi = q[k & 1];
             RayQ& qo = q[(k + 1) & 1];
             {
-            KernelTimer kt(A.time_kernels, st, 0);
-            if (A.count_work)
-                hipLaunchKernelGGL((k_extend<true, false>), dim3(gx), dim3(256), lds, st, A.sc, nullptr, qi, hq,
-                                   ctr + kCtrRays + k,
-                                   ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
-            else
-                hipLaunchKernelGGL((k_extend<false, false>), dim3(gx), dim3(256), lds, st, A.sc, nullptr, qi, hq,
-                                   ctr + kCtrRays + k,
-                                   ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
+                KernelTimer kt(A.time_kernels, st, 0);
+                if (A.count_work)
+                    hipLaunchKernelGGL((k_extend<true, false>), dim3(gx), dim3(256), A.lds, st, A.sc, nullptr, qi, hq,
+                                       ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
+                else
+                    hipLaunchKernelGGL((k_extend<false, false>), dim3(gx), dim3(256), A.lds, st, A.sc, nullptr, qi,
+                                       hq, ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
             }
-            if (A.shc.defer_shadow) {
+            {
                 KernelTimer kt(A.time_kernels, st, 1);
                 hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr, qi, hq,
-                                   ctr, k, qo, sqs[0], acc);
-                continue;
+                                   ctr, k, qo, sq, acc);
             }
-            const int b = k & 1;
-            ShadowQ& sq = sqs[b];
-            if (k > 1) HIP_TRY(hipStreamWaitEvent(st, X->join[k - 2], 0));
-            {
-            KernelTimer kt(A.time_kernels, st, 1);
-            hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr, qi, hq,
-                               ctr, k, qo, sq, acc);
-            }
-            HIP_TRY(hipEventRecord(X->fork[k], st));
-            HIP_TRY(hipStreamWaitEvent(X->s[b], X->fork[k], 0));
-            {
-            KernelTimer kt(A.time_kernels, X->s[b], 2);
-            if (A.count_work)
-                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, X->s[b], A.sc, nullptr, sq,
-                                   ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s[b], swork);
-            else
-                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, X->s[b], A.sc, nullptr, sq,
-                                   ctr + kCtrShadow + k,
-                                   ctr + kCtrShadowCur + k, pl.scap, A.chunk, acc, overflow_s[b], swork);
-            }
-            HIP_TRY(hipEventRecord(X->join[k], X->s[b]));
         }
-        if (A.shc.defer_shadow) {
-            if (perm) {   // counting sort of the pass's shadow rays by (light, origin cell)
-                hipLaunchKernelGGL(k_zero_u32, dim3((nb + 255) / 256), dim3(256), 0, st, bins, nb);
-                hipLaunchKernelGGL(k_bin_count, dim3(1024), dim3(256), 0, st, sqs[0].key, ctr + kCtrShadowAll, pl.scap,
-                                   bins, nb);
-                hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, bins, bins + kBinMax, nb);
-                hipLaunchKernelGGL(k_bin_scatter, dim3(1024), dim3(256), 0, st, sqs[0].key, ctr + kCtrShadowAll,
-                                   pl.scap, bins + kBinMax, perm, nb);
-            }
-            KernelTimer kt(A.time_kernels, st, 2);
-            if (A.count_work)
-                hipLaunchKernelGGL((k_shadow<true, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sqs[0],
-                                   ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, A.chunk, acc, overflow_s[0],
-                                   swork, perm);
-            else
-                hipLaunchKernelGGL((k_shadow<false, false>), dim3(gs), dim3(256), lds, st, A.sc, nullptr, sqs[0],
-                                   ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, A.chunk, acc, overflow_s[0],
-                                   swork, perm);
-        } else {
-            HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth], 0));
-            if (A.shc.max_depth > 0) HIP_TRY(hipStreamWaitEvent(st, X->join[A.shc.max_depth - 1], 0));
-        }
+        enqueue_shadow_segment(A, sq, seg, nb, acc, swork, st);
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth, 0);
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
@@ -1820,7 +1796,8 @@ struct CachePlan {
     rt_cache c;            // defaults filled in
     rt_cache_layout L;
     uint32_t rec_cap = 0, tcap = 0, tscap = 0;
-    size_t off_rec = 0, off_tq[2] = {0, 0}, off_thit = 0, off_ts = 0, off_tctr = 0, total = 0;
+    size_t off_rec = 0, off_tq[2] = {0, 0}, off_thit = 0, off_ts = 0, off_tbin = 0, off_tbins = 0, off_tctr = 0,
+           total = 0;
 };
 
 static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_params& p, const rt_cache* cache,
@@ -1859,7 +1836,7 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
         if (!(c.bounds_hi[k] > c.bounds_lo[k])) c.bounds_hi[k] = c.bounds_lo[k] + 1.0f;
     rt_params q = p;
     q.samples_per_pass = p.spp;   // cache frames trace every sample in one pass
-    if (!make_plan(h, cam, q, cp.base, why, false)) return false;
+    if (!make_plan(h, cam, q, cp.base, why)) return false;
     cp.c = c;
     if (!cache_layout(c.train_samples, cp.L)) {
         why = "train_samples must be in [1, 2^24]";
@@ -1880,6 +1857,10 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
     off = a256(off + 2 * a256(4 * (size_t)cp.tcap));
     cp.off_ts = off;
     off = a256(off + 11 * a256(4 * (size_t)cp.tscap));
+    cp.off_tbin = off;    // keys and order of the targets' deferred shadow queue
+    off = a256(off + 2 * a256(4 * (size_t)cp.tscap));
+    cp.off_tbins = off;   // its per-bin counts and first slots
+    off = a256(off + 2 * 4 * (size_t)kBinMax);
     cp.off_tctr = off;
     off = a256(off + 4 * kCtrTotal);
     cp.total = off;
@@ -1925,7 +1906,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     unsigned long long* swork = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->shadow_node_visits) : nullptr;
     const int cd = cc.depth;
 
-    // one bounce of the wavefront over queue set (qs, hit, shadow) with counters c_
+    // one bounce of a wavefront: closest hits and shading; the shading appends
+    // its shadow rays to the chain's deferred queue (counters c_)
     auto bounce = [&](RayQ& qi, RayQ& qo, HitQ& h, ShadowQ& sh, uint32_t* c_, const ShadeConst& shc, float* acc_,
                       int k) {
         {
@@ -1942,18 +1924,23 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
             hipLaunchKernelGGL(k_shade<false>, dim3(A.shade_blocks), dim3(256), 0, st, A.sc, shc, nullptr, qi, h, c_, k,
                                qo, sh, acc_);
         }
-        {
-            KernelTimer kt(A.time_kernels, st, 2);
-            if (A.count_work)
-                hipLaunchKernelGGL((k_shadow<true, false>), dim3(A.gs), dim3(256), 0, st, A.sc, nullptr, sh,
-                                   c_ + kCtrShadow + k, c_ + kCtrShadowCur + k, shc.scap, A.chunk, acc_, overflow,
-                                   swork);
-            else
-                hipLaunchKernelGGL((k_shadow<false, false>), dim3(A.gs), dim3(256), 0, st, A.sc, nullptr, sh,
-                                   c_ + kCtrShadow + k, c_ + kCtrShadowCur + k, shc.scap, A.chunk, acc_, overflow,
-                                   swork);
-        }
     };
+    // the deferred shadow queue of a chain, binned and traced once
+    const int nb = std::max(1, std::min(A.sc.n_lights, 32)) * A.shc.bin_c * A.shc.bin_c * A.shc.bin_c;
+    auto shadows = [&](const ShadowQ& sh, uint32_t* c_, uint32_t cap, uint32_t* perm, uint32_t* bins, float* acc_) {
+        ShadowSegment g;
+        g.begin_p = nullptr;
+        g.end_p = c_ + kCtrShadowAll;
+        g.cap = cap;
+        g.cursor = c_ + kCtrShadowAllCur;
+        g.perm = perm;
+        g.bins = bins;
+        g.overflow = overflow;
+        g.grid = A.gs;
+        enqueue_shadow_segment(A, sh, g, nb, acc_, swork, st);
+    };
+    const size_t sstride = a256(4 * (size_t)pl.scap);
+    sq.key = reinterpret_cast<uint32_t*>(A.ws + pl.off_s2);
 
     const int64_t n3 = 3 * pl.nacc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
@@ -1964,6 +1951,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, 0, A.spp, tiles_x, nthreads,
                        q[0], ctr, pl.qcap, A.shc.per_sample);
     for (int k = 0; k < cd; ++k) bounce(q[k & 1], q[(k + 1) & 1], hq, sq, ctr, A.shc, acc, k);
+    shadows(sq, ctr, pl.scap, reinterpret_cast<uint32_t*>(A.ws + pl.off_s2 + sstride),
+            reinterpret_cast<uint32_t*>(A.ws + pl.off_bins), acc);
     // depth cd: closest hits, then cache queries instead of shading
     {
         KernelTimer kt(A.time_kernels, st, 0);
@@ -1986,6 +1975,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         RayQ tq[2] = {ray_queue(A.ws + cp.off_tq[0], cp.tcap), ray_queue(A.ws + cp.off_tq[1], cp.tcap)};
         HitQ th = hit_queue(A.ws + cp.off_thit, cp.tcap);
         ShadowQ ts = shadow_queue(A.ws + cp.off_ts, cp.tscap, false);
+        ts.key = reinterpret_cast<uint32_t*>(A.ws + cp.off_tbin);
         float* targets = reinterpret_cast<float*>(S + L.train_targets);
         uint16_t* t_feats = reinterpret_cast<uint16_t*>(S + L.train_feats);
         float* t_rays = reinterpret_cast<float*>(S + L.train_rays);
@@ -2005,6 +1995,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         tc.qcap = cp.tcap;
         tc.scap = cp.tscap;
         for (int k = cd; k <= cc.full_depth; ++k) bounce(tq[k & 1], tq[(k + 1) & 1], th, ts, tctr, tc, targets, k);
+        shadows(ts, tctr, cp.tscap, reinterpret_cast<uint32_t*>(A.ws + cp.off_tbin + a256(4 * (size_t)cp.tscap)),
+                reinterpret_cast<uint32_t*>(A.ws + cp.off_tbins), targets);
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, tctr, A.stats, cc.full_depth, 2);
         const int64_t bs = (T + cc.train_steps - 1) / cc.train_steps;
         float* wm = reinterpret_cast<float*>(S + L.w_master);
@@ -2151,17 +2143,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
     A.shc.acc_off = 0;
     A.shc.out_ids = out_hit_ids;
-    A.shc.defer_shadow = 1;
-    A.bin_shadows = true;
-    {
-        const int L = std::max(1, std::min(scene->h.n_lights, 32));
-        A.shc.bin_c = L <= 8 ? 8 : 4;   // L * bin_c^3 <= 4096 bins
-        for (int k = 0; k < 3; ++k) {
-            const float lo = scene->h.info.bounds_lo[k], hi = scene->h.info.bounds_hi[k];
-            A.shc.bin_lo[k] = lo;
-            A.shc.bin_inv[k] = hi > lo ? (float)A.shc.bin_c / (hi - lo) : 0.0f;
-        }
-    }
+    defer_and_bin_shadows(A, scene->h);
     A.pl = pl;
     A.ws = static_cast<uint8_t*>(p.workspace);
     A.stats = static_cast<rt_stats*>(p.stats);
@@ -2354,6 +2336,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
     A.shc.acc_off = 0;
     A.shc.out_ids = out_hit_ids;
+    defer_and_bin_shadows(A, scene->h);
     A.pl = C.cp.base;
     A.ws = static_cast<uint8_t*>(p.workspace);
     A.stats = static_cast<rt_stats*>(p.stats);
