@@ -1559,6 +1559,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
             B.shc.per_sample = per_sample ? 1 : 0;
             B.shc.acc_off = (uint32_t)acc;
             B.shc.out_ids = out_ids ? out_ids[i] : nullptr;
+            B.shc.defer_shadow = 1;   // one shadow queue for every scene and depth, traced after the bounces
             camera_consts(cam, p, B.cam);
             B.ray_off = (uint32_t)rays;
             B.n_rays = (uint32_t)nr;
@@ -1693,17 +1694,15 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
             hipLaunchKernelGGL(k_shade<true>, dim3(B.shade_blocks), dim3(256), 0, st, none, c0, tab, qi, hq, ctr, k,
                                qo, sq, acc);
         }
-        {
-            KernelTimer kt(B.time_kernels, st, 2);
-            if (B.count_work)
-                hipLaunchKernelGGL((k_shadow<true, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
-                                   ctr + kCtrShadow + k, ctr + kCtrShadowCur + k, pl.scap, B.chunk, acc, overflow,
-                                   swork);
-            else
-                hipLaunchKernelGGL((k_shadow<false, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
-                                   ctr + kCtrShadow + k, ctr + kCtrShadowCur + k, pl.scap, B.chunk, acc, overflow,
-                                   swork);
-        }
+    }
+    {   // the deferred shadow rays of every scene and depth
+        KernelTimer kt(B.time_kernels, st, 2);
+        if (B.count_work)
+            hipLaunchKernelGGL((k_shadow<true, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
+                               ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, B.chunk, acc, overflow, swork);
+        else
+            hipLaunchKernelGGL((k_shadow<false, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
+                               ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, B.chunk, acc, overflow, swork);
     }
     hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, B.stats, pl.dmax, 0);
     hipLaunchKernelGGL(k_resolve_batch, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, tab, pl.n, acc, n3);
