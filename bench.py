@@ -44,7 +44,7 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w, budget_s: float, seed: int = 5):
+def cpu_baseline(w, budget_s: float, seed: int = 5, scene=None):
     import numpy as np
 
     import oracle
@@ -62,9 +62,26 @@ def cpu_baseline(w, budget_s: float, seed: int = 5):
         done += len(chunk)
         per_px = dt / max(1, len(chunk))
         n = int(min(max(4, (budget_s - elapsed) / max(per_px, 1e-6) * 0.8), 4096))
-    return {"value": rays / elapsed / 1e6, "unit": "Mrays/s", "cores": ncores, "kind": "oracle",
-            "sample": f"{done} seeded pixels x {w.params.spp} spp of the same frame ({rays} rays, "
-                      f"{elapsed:.1f} s, FP64 brute force over every primitive, no BVH)"}
+    out = {"value": rays / elapsed / 1e6, "unit": "Mrays/s", "cores": ncores, "kind": "oracle",
+           "sample": f"{done} seeded pixels x {w.params.spp} spp of the same frame ({rays} rays, "
+                     f"{elapsed:.1f} s, FP64 brute force over every primitive, no BVH)"}
+    if scene is not None:
+        # the fair CPU figure beside it: the library's FP32 host traversal of the same BVH on the camera rays
+        # of the same pixels (closest hit only), all host cores
+        from paper_1504_03151_amd import rt
+        from paper_1504_03151_amd import scenes
+        o, d = oracle.camera_rays(w.camera, w.params, scenes.pixel_subset(w.camera, 1 << 18, seed))
+        R = rt.make_rays(o, d)
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 2.0 or reps == 0:
+            scene.host_trace(R, nthreads=ncores)
+            reps += 1
+        dt = time.perf_counter() - t0
+        out["host_bvh"] = {"value": round(reps * len(R) / dt / 1e6, 3), "unit": "Mrays/s", "cores": ncores,
+                           "sample": f"{len(R)} camera rays of seeded pixels of the same frame, closest hit, FP32 "
+                                     f"BVH traversal on the host (layout {scene.info['node_layout']}), {reps} runs"}
+    return out
 
 
 KERNEL_SOURCES = ["paper_1504_03151_amd/csrc/rt_common.h", "paper_1504_03151_amd/csrc/render.cpp"]
@@ -396,7 +413,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(w, args.cpu_seconds)
+        cpu = cpu_baseline(w, args.cpu_seconds, scene=sc)
 
     out = {
         "metric": "Mrays/s (closest-hit + shadow rays per second), plain depth-8 Whitted frame",

@@ -239,3 +239,26 @@ def test_config2_full_frame_sampled(rt):
     g_avg = rgb.reshape(-1, 3).double().cpu().numpy()[pixels]
     assert full.sum() >= 8
     assert np.abs(g_avg - ref["rgb"]).max(axis=1)[full].max() <= RGB_TOL
+
+
+def test_deferred_shadow_queue_capacity(rt):
+    """Inside a closed box of reflective Phong walls every ray hits and every hit sends one shadow ray, so the
+    deferred shadow queue of a depth-4 frame holds 5 x the primary rays: queue_factor 1 must report the
+    overflow (RT_ERR_CAPACITY under FLAG_SYNC), queue_factor 5 must fit exactly and match the oracle."""
+    planes = [[1, 0, 0, -5], [-1, 0, 0, -5], [0, 1, 0, -5], [0, -1, 0, -5], [0, 0, 1, -5], [0, 0, -1, -5]]
+    scene = S.make_scene(planes=planes, plane_mat=[0] * 6, materials=np.stack([S.material((0.6, 0.5, 0.4), k_r=0.5)]),
+                         lights=[[1.0, 2.0, 0.5, 1.0, 1.0, 1.0]], name="mirror_box")
+    cam = S.Camera((0.0, 0.0, 0.0), (0.0, 0.0, 1.0), (0.0, 1.0, 0.0), 60.0, 32, 32)
+    p = S.Params(spp=1, max_depth=4, jitter=0, seed=1)
+    sc = rt.Scene(scene).upload()
+    with pytest.raises(rt.RTError, match="CAPACITY"):
+        rt.render(sc, cam, p, queue_factor=1.0)
+    rgb, ids, st = rt.render(sc, cam, p, queue_factor=5.0)
+    torch.cuda.synchronize()
+    assert st["status"] == 0
+    assert st["rays"][:5] == [1024] * 5 and st["shadow"][:5] == [1024] * 5
+    ref = oracle.render(scene, cam, p)
+    rob = ref["margin"] > ROBUST
+    assert rob.mean() > 0.9
+    np.testing.assert_allclose(rgb.reshape(-1, 3).cpu().numpy()[rob], ref["rgb"][rob], rtol=0, atol=1e-3)
+    assert (ids.reshape(-1).cpu().numpy()[rob] == ref["ids"][rob, 0]).all()
