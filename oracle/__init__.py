@@ -87,7 +87,9 @@ def lib():
                                           C.c_int64]
             L.or_radiance.restype = C.c_int
             L.or_radiance.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.c_void_p, C.c_int64, C.c_int32,
-                                      C.c_int32, C.c_void_p, C.c_void_p]
+                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+            L.or_light_point.restype = None
+            L.or_light_point.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32, C.c_int32, C.c_void_p]
             L.or_pcg.restype = C.c_uint32
             L.or_pcg.argtypes = [C.c_uint32]
             L.or_jitter.restype = C.c_double
@@ -280,16 +282,26 @@ def render_cache(scene, camera, params, cache_depth: int, pixels=None, nthreads:
     return dict(rgb=rgb, margin=margin, records=rec[:m].copy(), pixels=pixels)
 
 
-def radiance(scene, params, o, d, start_depth: int, so=0.0, sd=0.0, nthreads: int = 0):
-    """Radiance of rays starting at recursion depth start_depth: (L [n,3], margin [n])."""
+def radiance(scene, params, o, d, start_depth: int, so=0.0, sd=0.0, nthreads: int = 0, sample: int = 0):
+    """Radiance of rays starting at recursion depth start_depth: (L [n,3], margin [n]); area lights take their
+    points of pass `sample`."""
     Lb = lib()
     R = _rays9(o, d, None, so, sd)
     n = len(R)
     out = np.zeros((n, 3), np.float64)
     m = np.zeros(n, np.float64)
     sc, p = OScene(scene), _params(params)
-    rc = Lb.or_radiance(C.byref(sc.c), C.byref(p), R.ctypes.data, n, int(start_depth), nthreads, out.ctypes.data,
-                        m.ctypes.data)
+    rc = Lb.or_radiance(C.byref(sc.c), C.byref(p), R.ctypes.data, n, int(start_depth), int(sample), nthreads,
+                        out.ctypes.data, m.ctypes.data)
     if rc != 0:
         raise ValueError(f"or_radiance failed ({rc})")
     return out, m
+
+
+def light_point(light, seed: int, frame: int, sample: int, index: int):
+    """Sample point of one light record (13 floats) for a pass (frame, sample) and light index."""
+    L = np.ascontiguousarray(light, np.float32).reshape(13)
+    out = np.zeros(3, np.float64)
+    lib().or_light_point(L.ctypes.data, int(seed) & (2 ** 64 - 1), int(frame), int(sample), int(index),
+                         out.ctypes.data)
+    return out

@@ -14,7 +14,8 @@
  *     smallest root in (0, tmax) (the paper does not say which root).
  *   - Triangles by an edge-function test in FP64 (inclusive edges, zero-area
  *     never hit); planes by the plane equation.
- *   - Shadow rays to each point light, counted as blocked by the first
+ *   - Shadow rays to each light (a point light, or the pass's sample point of an
+ *     area light), counted as blocked by the first
  *     primitive found on the segment: the inner loop of Algorithm 1 with its
  *     ELSE branch read as "add the light's term only if nothing blocks".
  *   - Recursion over reflected and refracted secondary rays up to a maximum
@@ -72,8 +73,10 @@ typedef struct {
     int32_t n_materials;
     const float* materials;   /* [m][10] albedo rgb, ka, kd, ks, shininess, kr, ior, type */
     int32_t n_lights;
-    const float* lights;      /* [l][6] pos, intensity */
+    const float* lights;      /* [l][13] pos, intensity, shape, u, v (see or_light_point) */
 } or_scene;
+
+#define LW 13   /* floats per light */
 
 typedef struct {
     double eye[3], look_at[3], up[3];
@@ -124,6 +127,36 @@ double or_jitter(uint64_t seed, uint32_t frame, uint32_t pixel, uint32_t s, uint
     h = or_pcg(h ^ pixel);
     h = or_pcg(h ^ (s * 2u + dim));
     return (double)(h >> 8) * (1.0 / 16777216.0);
+}
+
+/* Light sample point.  Following the paper's progressive scheme (Section V:
+ * each pass samples every light source once, and the passes add up), light l
+ * is sampled at one point per (frame, sample) for all pixels:
+ *   shape 0: a point light at pos;
+ *   shape 1: the parallelogram pos + a u + b v;
+ *   shape 2: the ellipse (disk) pos + sqrt(a) (cos(2 pi b) u + sin(2 pi b) v),
+ *            uniform in area;
+ * with a, b the hash values of the camera jitter taken with the pixel slot
+ * 0xFFFFFFFF - l (no pixel index reaches it).  Computed in FP64 and rounded
+ * once to FP32, the precision the scene's light records have. */
+void or_light_point(const float* L, uint64_t seed, uint32_t frame, int32_t s, int32_t l, double* out) {
+    const int shape = (int)L[6];
+    if (shape == 0) {
+        load3f(out, L);
+        return;
+    }
+    const double a = or_jitter(seed, frame, 0xFFFFFFFFu - (uint32_t)l, (uint32_t)s, 0);
+    const double b = or_jitter(seed, frame, 0xFFFFFFFFu - (uint32_t)l, (uint32_t)s, 1);
+    double cu, cv;
+    if (shape == 1) {
+        cu = a;
+        cv = b;
+    } else {
+        const double r = sqrt(a), phi = 2.0 * M_PI * b;
+        cu = r * cos(phi);
+        cv = r * sin(phi);
+    }
+    for (int i = 0; i < 3; ++i) out[i] = (double)(float)((double)L[i] + cu * (double)L[7 + i] + cv * (double)L[10 + i]);
 }
 
 /* Pinhole camera: vertical field of view, row 0 at the top, right = up x forward. */
@@ -525,6 +558,7 @@ typedef struct {
     int64_t* cache_n;  /* shared record counter */
     int64_t cache_cap;
     int64_t list_index;
+    int32_t sample;    /* sample (pass) index: selects the area lights' sample points */
 } pctx;
 
 /* A decision whose worst-case effect on the sample's radiance is at most
@@ -562,7 +596,7 @@ static double local_bound(const or_scene* sc) {
         mat = fmax(mat, M[4] * am + M[5]);
     }
     for (int l = 0; l < sc->n_lights; ++l) {
-        const float* L = sc->lights + 6 * l;
+        const float* L = sc->lights + LW * l;
         lsum += fmax(L[3], fmax(L[4], L[5]));
     }
     return amb + lsum * mat;
@@ -671,9 +705,9 @@ static void trace(pctx* P, const oray* ray, int kind, int k, const double* w, do
     double local[3];
     for (int i = 0; i < 3; ++i) local[i] = ka * alb[i];
     for (int l = 0; l < sc->n_lights; ++l) {
-        const float* L = sc->lights + 6 * l;
+        const float* L = sc->lights + LW * l;
         double lp[3], lv[3];
-        load3f(lp, L);
+        or_light_point(L, p->seed, p->frame, P->sample, l, lp);
         sub3(lv, lp, x);
         normalize3(lv);
         const double ndl = dot3(nf, lv);
@@ -833,6 +867,7 @@ static void render_one(void* vctx, int64_t i) {
         const double m_before = P.margin;
         P.margin = MARGIN_CAP;
         P.ignored = 0.0;
+        P.sample = s;
         trace(&P, &r, 0, 0, one, L, &pid);
         for (int c = 0; c < 3; ++c) acc[c] += L[c];
         if (J->ids) J->ids[i * J->p->spp + s] = pid;
@@ -937,6 +972,7 @@ int64_t or_ray_tree(const or_scene* sc, const or_camera* cam, const or_params* p
     r.so = EA * maxabs3(r.o);
     r.sd = EA;
     int64_t pid;
+    P.sample = sample;
     trace(&P, &r, 0, 0, one, rgb, &pid);
     oscene_free(&S);
     return P.rec_n;
@@ -968,6 +1004,7 @@ typedef struct {
     int start_depth;
     double* L;
     double* margin;
+    int32_t sample;
 } radiance_job;
 
 static void radiance_one(void* vctx, int64_t i) {
@@ -978,6 +1015,7 @@ static void radiance_one(void* vctx, int64_t i) {
     oray r;
     load_ray(J->rays + 9 * i, &r);
     const double one[3] = {1.0, 1.0, 1.0};
+    P.sample = J->sample;
     trace(&P, &r, 0, J->start_depth, one, J->L + 3 * i, NULL);
     J->margin[i] = P.margin;
 }
@@ -986,11 +1024,11 @@ static void radiance_one(void* vctx, int64_t i) {
  * secondary rays spawn while depth < max_depth): the training targets of the
  * learned form.  rays [n][9] as or_closest; L [n][3]; margin [n]. */
 int or_radiance(const or_scene* sc, const or_params* p, const double* rays, int64_t n, int32_t start_depth,
-                int32_t nthreads, double* L, double* margin) {
+                int32_t sample, int32_t nthreads, double* L, double* margin) {
     if (p->max_depth < 0 || p->max_depth > 63 || start_depth < 0 || start_depth > p->max_depth) return -1;
     oscene S;
     if (oscene_init(&S, sc) != 0) return -2;
-    radiance_job J = {&S, p, rays, start_depth, L, margin};
+    radiance_job J = {&S, p, rays, start_depth, L, margin, sample};
     run_parallel(n, nthreads, radiance_one, &J);
     oscene_free(&S);
     return 0;

@@ -11,7 +11,10 @@ same values exactly to FP64.
 
 Material rows are ``[albedo_r, albedo_g, albedo_b, k_a, k_d, k_s, shininess,
 k_r, ior, type]`` with ``type`` 0 = Phong, 1 = mirror, 2 = dielectric.  Lights
-are ``[x, y, z, I_r, I_g, I_b]`` point lights.
+are ``[x, y, z, I_r, I_g, I_b, shape, u_x, u_y, u_z, v_x, v_y, v_z]``: shape 0
+a point light at (x, y, z), 1 the parallelogram spanned by u and v from it, 2
+the ellipse (a disk when u and v are orthogonal and of equal length) centred
+on it; six-column rows are point lights.
 
 The scene recipes stand in for the paper's sphere scene (Section V, 640x480,
 not distributed): a small random-sphere scene, a large heightfield terrain with
@@ -28,6 +31,8 @@ import numpy as np
 
 PHONG, MIRROR, DIELECTRIC = 0, 1, 2
 MAT_COLS = 10
+LIGHT_COLS = 13
+POINT, PARALLELOGRAM, DISK = 0, 1, 2
 
 
 @dataclasses.dataclass
@@ -39,7 +44,7 @@ class Scene:
     planes: np.ndarray       # (np, 4) f32: nx, ny, nz, h  (n . x = h, |n| = 1)
     plane_mat: np.ndarray    # (np,) i32
     materials: np.ndarray    # (nm, 10) f32
-    lights: np.ndarray       # (nl, 6) f32
+    lights: np.ndarray       # (nl, 13) f32: pos, intensity, shape, u, v
     name: str = "scene"
 
     @property
@@ -51,7 +56,7 @@ class Scene:
         assert self.tris.dtype == np.float32 and self.tris.ndim == 3 and self.tris.shape[1:] == (3, 3)
         assert self.planes.dtype == np.float32 and self.planes.ndim == 2 and self.planes.shape[1] == 4
         assert self.materials.dtype == np.float32 and self.materials.shape[1] == MAT_COLS
-        assert self.lights.dtype == np.float32 and self.lights.shape[1] == 6
+        assert self.lights.dtype == np.float32 and self.lights.shape[1] == LIGHT_COLS
         assert len(self.sphere_mat) == len(self.spheres)
         assert len(self.tri_mat) == len(self.tris)
         assert len(self.plane_mat) == len(self.planes)
@@ -107,7 +112,11 @@ def make_scene(spheres=None, sphere_mat=None, tris=None, tri_mat=None, planes=No
     tm = _empty_i32(len(tr)) if tri_mat is None else np.ascontiguousarray(tri_mat, dtype=np.int32).reshape(-1)
     pm = _empty_i32(len(pl)) if plane_mat is None else np.ascontiguousarray(plane_mat, dtype=np.int32).reshape(-1)
     mats = np.ascontiguousarray(materials, dtype=np.float32).reshape(-1, MAT_COLS)
-    li = np.ascontiguousarray(lights, dtype=np.float32).reshape(-1, 6)
+    li = np.asarray(lights if lights is not None else np.zeros((0, 6)), dtype=np.float32)
+    li = li.reshape(len(li), -1) if li.size else np.zeros((0, 6), np.float32)
+    if li.shape[1] == 6:      # point lights
+        li = np.hstack([li, np.zeros((len(li), LIGHT_COLS - 6), np.float32)])
+    li = np.ascontiguousarray(li, dtype=np.float32).reshape(-1, LIGHT_COLS)
     s = Scene(sp, sm, tr, tm, pl, pm, mats, li, name)
     s.validate_shapes()
     return s

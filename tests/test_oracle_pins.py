@@ -258,7 +258,7 @@ def test_direct_light_is_linear_in_intensity():
     w.params.bg = (0.0, 0.0, 0.0)
     pix = S.pixel_subset(w.camera, 300, 1)
     a = oracle.render(w.scene, w.camera, w.params, pix)
-    w.scene.lights[:, 3:] *= 2.0
+    w.scene.lights[:, 3:6] *= 2.0
     b = oracle.render(w.scene, w.camera, w.params, pix)
     np.testing.assert_allclose(b["rgb"], 2.0 * a["rgb"], rtol=1e-12, atol=1e-15)
 
@@ -415,3 +415,68 @@ def test_per_ray_radiance_of_camera_rays_is_the_pixel():
     o, d = oracle.camera_rays(w.camera, w.params, pix)
     L, m = oracle.radiance(w.scene, w.params, o, d, 0)
     _close(L, out["rgb"], atol=0)
+
+
+# ---------------------------------------------------------------- area lights sampled once per pass (Section V)
+
+def _disk_light_scene(D=4.0, R=2.0, a=2.0, r=0.5):
+    mats = np.stack([S.material((1.0, 1.0, 1.0), k_a=0.0, k_d=1.0, k_s=0.0, k_r=0.0),
+                     S.material((0.5, 0.5, 0.5), k_a=0.0, k_d=1.0, k_s=0.0, k_r=0.0)])
+    light = [0.0, D, 0.0, 1.0, 1.0, 1.0, S.DISK, R, 0.0, 0.0, 0.0, 0.0, R]
+    return S.make_scene(spheres=[[0.0, a, 0.0, r]], sphere_mat=[1], planes=[[0.0, 1.0, 0.0, 0.0]], plane_mat=[0],
+                        materials=mats, lights=[light])
+
+
+def test_disk_light_shadow_of_a_sphere_converges_to_the_area_integral():
+    """A Lambert point under a disk light of radius R at height D, with a sphere of radius r at height a on the
+    axis between them: a light point at distance rho from the axis is blocked iff rho < (D - e) tan(asin(r /
+    (a - e))) (e: the origin offset of the shadow ray), and it contributes N.L = D / sqrt(D^2 + rho^2).  For
+    uniform sampling of the disk the pass average converges to
+    (2 D / R^2) (sqrt(D^2 + R^2) - sqrt(D^2 + rho0^2))."""
+    D, R, a, r = 4.0, 2.0, 2.0, 0.5
+    sc = _disk_light_scene(D, R, a, r)
+    cam = S.Camera((6.0, 2.0, 0.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 30.0, 1, 1)
+    K = 4095                                    # not a square: every sample goes through the pixel centre
+    p = S.Params(spp=K, max_depth=0, jitter=0, seed=11)
+    out = oracle.render(sc, cam, p)
+    assert (out["ids"][0] == 1).all()          # the plane (id = 1 sphere + 0) at the origin
+    e = 1e-3
+    rho0 = (D - e) * math.tan(math.asin(r / (a - e)))
+    expect = 2.0 * D / R ** 2 * (math.sqrt(D * D + R * R) - math.sqrt(D * D + rho0 * rho0))
+    vals = out["rgb_s"][0, :, 0]
+    sem = vals.std() / math.sqrt(K)
+    assert abs(vals.mean() - expect) < 4.0 * sem, (vals.mean(), expect, sem)
+    # the blocked fraction is the area fraction of the inner disk, (rho0 / R)^2
+    assert abs((vals == 0.0).mean() - (rho0 / R) ** 2) < 4.0 * math.sqrt(0.25 / K)
+    # a point light at the disk centre: fully blocked
+    sc0 = _disk_light_scene(D, R, a, r)
+    sc0.lights[0, 6] = S.POINT
+    assert oracle.render(sc0, cam, S.Params(spp=1, max_depth=0, jitter=0))["rgb"][0, 0] == 0.0
+
+
+def test_light_points_cover_their_shapes_uniformly():
+    n = 20000
+    disk = np.array([1.0, 2.0, 3.0, 1, 1, 1, S.DISK, 0.0, 2.0, 0.0, 0.0, 0.0, 2.0], np.float32)
+    quad = np.array([1.0, 2.0, 3.0, 1, 1, 1, S.PARALLELOGRAM, 4.0, 0.0, 0.0, 1.0, 0.0, 3.0], np.float32)
+    pd = np.array([oracle.light_point(disk, 7, 3, s, 2) for s in range(n)])
+    pq = np.array([oracle.light_point(quad, 7, 3, s, 0) for s in range(n)])
+    # disk: in the plane x = 1 around (1, 2, 3), radius 2; P(rho < t) = (t / 2)^2; centred
+    assert np.abs(pd[:, 0] - 1.0).max() < 1e-6
+    rho = np.hypot(pd[:, 1] - 2.0, pd[:, 2] - 3.0)
+    assert rho.max() <= 2.0 + 1e-5
+    for t in (0.5, 1.0, 1.5):
+        assert abs((rho < t).mean() - (t / 2.0) ** 2) < 4 * math.sqrt(0.25 / n)
+    assert np.abs(pd[:, 1:].mean(0) - [2.0, 3.0]).max() < 0.05
+    # parallelogram: coordinates (a, b) = ((x - 1 - (z - 3) / 3) / 4, (z - 3) / 3) uniform in [0, 1)^2
+    b = (pq[:, 2] - 3.0) / 3.0
+    a = (pq[:, 0] - 1.0 - 1.0 * b) / 4.0
+    assert a.min() >= -1e-6 and a.max() < 1 + 1e-6 and b.min() >= -1e-6 and b.max() < 1 + 1e-6
+    assert np.abs(pq[:, 1] - 2.0).max() < 1e-6
+    for q in (0.25, 0.5, 0.75):
+        assert abs((a < q).mean() - q) < 4 * math.sqrt(0.25 / n) and abs((b < q).mean() - q) < 4 * math.sqrt(0.25 / n)
+    # different lights, frames and samples draw different points; a point light is its position
+    assert not np.allclose(oracle.light_point(disk, 7, 3, 0, 0), oracle.light_point(disk, 7, 3, 0, 1))
+    assert not np.allclose(oracle.light_point(disk, 7, 3, 0, 0), oracle.light_point(disk, 7, 4, 0, 0))
+    pt = disk.copy()
+    pt[6] = S.POINT
+    assert (oracle.light_point(pt, 7, 3, 5, 0) == [1.0, 2.0, 3.0]).all()
