@@ -60,9 +60,18 @@ typedef struct {
     int32_t type;
 } rt_material;
 
+enum { RT_LIGHT_POINT = 0, RT_LIGHT_PARALLELOGRAM = 1, RT_LIGHT_DISK = 2 };
+/* A light.  A point light sits at pos.  An area light is sampled at one point
+ * per pass (frame, sample index) for every pixel, the paper's progressive
+ * scheme (Section V): the parallelogram pos + a u + b v, or the ellipse (disk)
+ * pos + sqrt(a) (cos(2 pi b) u + sin(2 pi b) v), with (a, b) the PCG hash
+ * values of the camera jitter taken with the pixel slot 0xFFFFFFFF - (light
+ * index); the sample point then acts as a point light of this intensity. */
 typedef struct {
     float pos[3];
     float intensity[3];
+    int32_t shape;               /* RT_LIGHT_* */
+    float u[3], v[3];            /* area lights: edge or semi-axis vectors (ignored for points) */
 } rt_light;
 
 /* Scene arrays (host memory, copied by rt_build_scene). */
@@ -78,7 +87,7 @@ typedef struct {
     const int32_t* plane_mat;    /* [n_planes] */
     const rt_material* materials;
     int32_t n_materials;
-    const rt_light* lights;      /* point lights */
+    const rt_light* lights;      /* point and area lights */
     int32_t n_lights;
 } rt_scene_desc;
 

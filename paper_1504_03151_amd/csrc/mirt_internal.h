@@ -24,6 +24,7 @@ struct SceneHost {
     int64_t n_nodes = 0;
     int depth = 0, stack_size = 0;
     int layout = 0;               // RT_LAYOUT_* of the node section
+    bool area_lights = false;     // some light is an area light (sampled per pass)
     std::vector<Node> bvh2;       // the binary tree as built (depth-first), source of every layout
     float scale = 1.0f;           // max(1, max |coordinate|) of the scene
     rt_scene_info info{};

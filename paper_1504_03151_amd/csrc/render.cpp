@@ -103,6 +103,8 @@ struct ShadeConst {
     uint32_t acc_off;   // first accumulation slot of the scene
     int32_t* out_ids;   // [H][W][spp] or NULL
     int defer_shadow;   // 1: shadow rays of all depths go to one queue, traced after the last bounce
+    uint64_t seed;      // hash seed of the frame (area-light sample points)
+    const float4* light_pts;   // [spp][n_lights] sample points of the frame's passes, or NULL (point lights)
     // deferred shadows are binned by (light, origin cell) before they are traced:
     // cell = floor((x - bin_lo) * bin_inv) per axis on a bin_c^3 grid over the scene
     float bin_lo[3], bin_inv[3];
@@ -119,6 +121,7 @@ struct BatchScene {
     int tiles_x;
     float inv_spp;
     float* out_rgb;
+    uint32_t lpt_first, lpt_count;   // area lights: entries of the batch's light-point table
 };
 
 template <bool BATCH>
@@ -528,18 +531,75 @@ struct LightTerm {
     bool emit;
 };
 
-// Phong light term (without visibility) of light L at x with facing normal nf.
-__device__ __forceinline__ LightTerm light_term(const DevLight& L, V3 x, V3 nf, V3 d, V3 alb, float kd, float ks,
-                                                float shin) {
+// Point of light l for pass (frame, sample s): the light's position, or for an
+// area light one point of its parallelogram or ellipse from the camera-jitter
+// hash with the pixel slot 0xFFFFFFFF - l (the same for every pixel of the
+// pass), computed in FP64 and rounded once.
+__device__ __forceinline__ V3 light_point(const DevLight& L, uint64_t seed, uint32_t frame, uint32_t s, int l) {
+    const int shape = (int)L.pos.w;
+    if (shape == RT_LIGHT_POINT) return xyz(L.pos);
+    const double a = jitter01(seed, frame, 0xFFFFFFFFu - (uint32_t)l, s, 0);
+    const double b = jitter01(seed, frame, 0xFFFFFFFFu - (uint32_t)l, s, 1);
+    double cu = a, cv = b;
+    if (shape == RT_LIGHT_DISK) {
+        const double r = sqrt(a);
+        double sn, cs;
+        sincos(2.0 * M_PI * b, &sn, &cs);
+        cu = r * cs;
+        cv = r * sn;
+    }
+    return v3((float)((double)L.pos.x + cu * (double)L.u.x + cv * (double)L.v.x),
+              (float)((double)L.pos.y + cu * (double)L.u.y + cv * (double)L.v.y),
+              (float)((double)L.pos.z + cu * (double)L.u.z + cv * (double)L.v.z));
+}
+
+// Sample points of every light for every pass of a frame: out[s * n + l].
+// The frame number is read on the device (a replayed graph sees the new one).
+__global__ void k_light_points(const DevLight* lights, int n, int spp, uint64_t seed, const uint32_t* frame_p,
+                               float4* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * spp) return;
+    const V3 p = light_point(lights[i % n], seed, *frame_p, (uint32_t)(i / n), i % n);
+    out[i] = make_float4(p.x, p.y, p.z, 0.0f);
+}
+
+// Batched frames: every scene's light-point table, scenes found by binary
+// search over their first entries (everything read from the device table).
+__global__ void k_light_points_batch(const BatchScene* tab, int n_scenes, uint32_t total) {
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int lo = 0, hi = n_scenes - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].lpt_first <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchScene& B = tab[lo];
+    const uint32_t i = e - B.lpt_first;
+    if (i >= B.lpt_count) return;
+    const int n = B.sc.n_lights;
+    const V3 p = light_point(B.sc.lights[i % n], B.shc.seed, B.cam.frame, i / n, (int)(i % n));
+    const_cast<float4*>(B.shc.light_pts)[i] = make_float4(p.x, p.y, p.z, 0.0f);
+}
+
+// Light l's point for pass s: from the frame's table, or the light itself.
+__device__ __forceinline__ V3 light_at(const DevScene& S, const ShadeConst& C, uint32_t s, int l) {
+    return C.light_pts ? xyz(C.light_pts[(size_t)s * S.n_lights + l]) : xyz(S.lights[l].pos);
+}
+
+// Phong light term (without visibility) of a light of intensity I at point lp,
+// seen from x with facing normal nf.
+__device__ __forceinline__ LightTerm light_term(V3 lp, float4 intensity, V3 x, V3 nf, V3 d, V3 alb, float kd,
+                                                float ks, float shin) {
     LightTerm t{0.0f, 0.0f, 0.0f, false};
-    V3 lv = xyz(L.pos) - x;
+    V3 lv = lp - x;
     lv = lv * (1.0f / sqrtf(dot(lv, lv)));
     const float ndl = dot(nf, lv);
     if (ndl <= 0.0f) return t;
     const V3 rr = (2.0f * ndl) * nf - lv;
     const float rv = fmaxf(0.0f, -dot(rr, d));
     const float spec = ks * pow_spec(rv, shin);
-    const V3 I = xyz(L.intensity);
+    const V3 I = xyz(intensity);
     t.cr = I.x * (kd * alb.x * ndl + spec);
     t.cg = I.y * (kd * alb.y * ndl + spec);
     t.cb = I.z * (kd * alb.z * ndl + spec);
@@ -553,13 +613,13 @@ __device__ __forceinline__ uint32_t bin_axis(float x, float lo, float inv, int c
 }
 
 __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, uint32_t cap, uint32_t* ctr, V3 xs,
-                                             const DevLight& L, V3 w, const LightTerm& lt, uint32_t pix,
-                                             uint32_t sid, const ShadeConst& C, int l) {
+                                             V3 lp, V3 w, const LightTerm& lt, uint32_t pix, uint32_t sid,
+                                             const ShadeConst& C, int l) {
     if (slot >= cap) {
         atomicOr(ctr + kCtrStatus, 2u);
         return;
     }
-    V3 sd = xyz(L.pos) - xs;
+    V3 sd = lp - xs;
     const float dist = sqrtf(dot(sd, sd));
     sd = sd * (1.0f / dist);
     sq.ox[slot] = xs.x;
@@ -618,6 +678,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
         const uint32_t sid = BATCH ? (meta >> 20) : 0u;
         const DevScene& S = scene_of<BATCH>(sc, tab, sid);
         const ShadeConst& C = shade_of<BATCH>(c0, tab, sid);
+        const uint32_t smp = (meta >> 4) & 0xFFFFu;   // the ray's pass: selects the area lights' points
         if (active && depth == 0 && C.out_ids) {
             int oid = -1;
             if (prim >= S.n_bvh) oid = prim;
@@ -670,7 +731,8 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
         uint32_t emit_mask = 0, n_sh = 0;
         if (shade) {
             for (int l = 0; l < S.n_lights; ++l) {
-                const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
+                const LightTerm lt = light_term(light_at(S, C, smp, l), S.lights[l].intensity, x, nf, d, alb, kd, ks,
+                                                shin);
                 if (lt.emit) {
                     n_sh++;
                     if (l < 32) emit_mask |= 1u << l;
@@ -692,17 +754,19 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
                 if (e) {
                     const uint32_t slot = run + __builtin_amdgcn_mbcnt_hi(
                                                     (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
-                    write_shadow(sq, slot, scap, ctr, xs, S.lights[l], w, lt, pix, sid, C, l);
+                    const V3 lp = light_at(S, C, smp, l);
+                    const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
+                    write_shadow(sq, slot, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
                 }
                 run += (uint32_t)__popcll(bal);
             }
         } else if (n_sh) {
             uint32_t slot = wave_base + lane_off;   // lane-major (more than 32 lights)
             for (int l = 0; l < S.n_lights; ++l) {
-                const LightTerm lt = light_term(S.lights[l], x, nf, d, alb, kd, ks, shin);
+                const V3 lp = light_at(S, C, smp, l);
+                const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
                 if (!lt.emit) continue;
-                write_shadow(sq, slot++, scap, ctr, xs, S.lights[l], w, lt, pix, sid, C, l);
+                write_shadow(sq, slot++, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
             }
         }
         // ---- secondary rays
@@ -1090,7 +1154,7 @@ struct Plan {
     int64_t n_primary = 0;   // rays of a full pass
     uint32_t qcap = 0, scap = 0;
     size_t off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_s2 = 0, off_bins = 0,
-           off_stack = 0, stack_bytes = 0, total = 0;
+           off_lpts = 0, off_stack = 0, stack_bytes = 0, total = 0;
 };
 
 // persistent traversal grids are capped at this many threads; each owns a
@@ -1164,6 +1228,8 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     }
     pl.off_bins = off;   // per-bin counts and first slots of the deferred shadow queue
     off = a256(off + 2 * 4 * (size_t)kBinMax);
+    pl.off_lpts = off;   // area lights: sample point of every light for every pass of the frame
+    if (s.area_lights) off = a256(off + 16 * (size_t)p.spp * (size_t)std::max(1, s.n_lights));
     pl.off_stack = off;   // overflow stacks: closest-hit and shadow traversals
     pl.stack_bytes = a256(4 * (size_t)kMaxPersistentThreads * std::max(0, s.stack_size - kSplitLds));
     off += 2 * pl.stack_bytes;
@@ -1391,6 +1457,11 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     seg.grid = A.gs;
     const int64_t n3 = 3 * pl.nacc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
+    if (A.shc.light_pts) {
+        const int n = A.spp * A.sc.n_lights;
+        hipLaunchKernelGGL(k_light_points, dim3((n + 255) / 256), dim3(256), 0, st, A.sc.lights, A.sc.n_lights,
+                           A.spp, A.shc.seed, ctr + kCtrFrame, const_cast<float4*>(A.shc.light_pts));
+    }
     const int tiles_x = (int)tiles_x_of(A.cam.W, A.tile), tiles_y = (int)tiles_y_of(A.cam.H, A.tile);
     for (int pass = 0; pass < pl.passes; ++pass) {
         const int s0 = pass * pl.spp_pass;
@@ -1506,6 +1577,8 @@ struct BatchPlan {
     uint32_t qcap = 0, scap = 0;
     int dmax = 0, stack_max = 0;
     size_t off_tab = 0, off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_stack = 0, total = 0;
+    size_t off_lpts = 0;
+    uint32_t n_lpts = 0;        // light-point entries of the scenes with area lights
 };
 
 static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params, int32_t n,
@@ -1518,7 +1591,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
     }
     const rt_params& p0 = params[0];
     const bool per_sample = (p0.flags & RT_FLAG_PER_SAMPLE) != 0;
-    uint64_t rays = 0, acc = 0;
+    uint64_t rays = 0, acc = 0, lpts = 0;
     int max_lights = 1;
     if (table) table->resize(n);
     for (int i = 0; i < n; ++i) {
@@ -1554,6 +1627,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
             B.sc = h.dev_view();
             for (int c = 0; c < 3; ++c) B.shc.bg[c] = p.bg[c];
             B.shc.eps = p.eps;
+            B.shc.seed = p.seed;
             B.shc.max_depth = p.max_depth;
             B.shc.spp = p.spp;
             B.shc.per_sample = per_sample ? 1 : 0;
@@ -1567,7 +1641,11 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
             B.tiles_x = (int)tiles_x;
             B.inv_spp = per_sample ? 1.0f : 1.0f / (float)p.spp;
             B.out_rgb = out_rgb[i];
+            B.shc.seed = p.seed;
+            B.lpt_first = (uint32_t)lpts;
+            B.lpt_count = h.area_lights ? (uint32_t)(p.spp * h.n_lights) : 0u;
         }
+        if (h.area_lights) lpts += (uint64_t)p.spp * h.n_lights;
         rays += nr;
         acc += na;
         bp.dmax = std::max(bp.dmax, p.max_depth);
@@ -1602,7 +1680,15 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
     off = a256(off + 12 * a256(4 * (size_t)bp.scap));
     bp.off_stack = off;
     off = a256(off + 4 * (size_t)kMaxPersistentThreads * std::max(0, bp.stack_max - kSplitLds));
+    bp.off_lpts = off;
+    bp.n_lpts = (uint32_t)std::min<uint64_t>(lpts, 0xFFFFFFFFu);
+    off = a256(off + 16 * (size_t)lpts);
     bp.total = off;
+    if (table && p0.workspace)
+        for (BatchScene& B : *table)
+            B.shc.light_pts = B.lpt_count ? reinterpret_cast<const float4*>(
+                                                static_cast<uint8_t*>(p0.workspace) + bp.off_lpts) + B.lpt_first
+                                          : nullptr;
     return true;
 }
 
@@ -1675,6 +1761,8 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
     const uint64_t n3 = 3 * pl.n_acc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, (int64_t)n3, 0.0f);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+    if (pl.n_lpts)
+        hipLaunchKernelGGL(k_light_points_batch, dim3((pl.n_lpts + 255) / 256), dim3(256), 0, st, tab, pl.n, pl.n_lpts);
     hipLaunchKernelGGL(k_raygen_batch, dim3((pl.n_rays + 255) / 256), dim3(256), 0, st, tab, pl.n, pl.n_rays, q[0], ctr,
                        pl.qcap);
     for (int k = 0; k <= pl.dmax; ++k) {
@@ -1945,6 +2033,11 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ctr + kCtrRec, 1);
+    if (A.shc.light_pts) {
+        const int n = A.spp * A.sc.n_lights;
+        hipLaunchKernelGGL(k_light_points, dim3((n + 255) / 256), dim3(256), 0, st, A.sc.lights, A.sc.n_lights,
+                           A.spp, A.shc.seed, ctr + kCtrFrame, const_cast<float4*>(A.shc.light_pts));
+    }
     const int tiles_x = (int)tiles_x_of(A.cam.W, A.tile), tiles_y = (int)tiles_y_of(A.cam.H, A.tile);
     const uint32_t nthreads = (uint32_t)((int64_t)tiles_x * tiles_y * A.spp * 64);
     hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, 0, A.spp, tiles_x, nthreads,
@@ -2135,6 +2228,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.cam.frame = 0;   // the frame number is read from the workspace, not baked into a captured graph
     for (int i = 0; i < 3; ++i) A.shc.bg[i] = p.bg[i];
     A.shc.eps = p.eps;
+    A.shc.seed = p.seed;
     A.shc.max_depth = p.max_depth;
     A.shc.spp = p.spp;
     A.shc.qcap = pl.qcap;
@@ -2145,6 +2239,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     defer_and_bin_shadows(A, scene->h);
     A.pl = pl;
     A.ws = static_cast<uint8_t*>(p.workspace);
+    A.shc.light_pts = scene->h.area_lights ? reinterpret_cast<const float4*>(A.ws + A.pl.off_lpts) : nullptr;
     A.stats = static_cast<rt_stats*>(p.stats);
     A.out_rgb = out_rgb;
     A.out_ids = out_hit_ids;
@@ -2328,6 +2423,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     A.cam.frame = 0;
     for (int i = 0; i < 3; ++i) A.shc.bg[i] = p.bg[i];
     A.shc.eps = p.eps;
+    A.shc.seed = p.seed;
     A.shc.max_depth = p.max_depth;
     A.shc.spp = p.spp;
     A.shc.qcap = C.cp.base.qcap;
@@ -2338,6 +2434,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     defer_and_bin_shadows(A, scene->h);
     A.pl = C.cp.base;
     A.ws = static_cast<uint8_t*>(p.workspace);
+    A.shc.light_pts = scene->h.area_lights ? reinterpret_cast<const float4*>(A.ws + A.pl.off_lpts) : nullptr;
     A.stats = static_cast<rt_stats*>(p.stats);
     A.out_rgb = out_rgb;
     A.out_ids = out_hit_ids;

@@ -82,8 +82,9 @@ struct alignas(16) DevMaterial {
 };
 
 struct alignas(16) DevLight {
-    float4 pos;
+    float4 pos;        // xyz; w = shape (RT_LIGHT_*) as a float
     float4 intensity;
+    float4 u, v;       // area lights: edge or semi-axis vectors
 };
 
 // Device view of one scene (pointers into the uploaded blob).

@@ -488,11 +488,14 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
                 return RT_ERR_INVALID_ARG;
             }
         }
-        for (int l = 0; l < nl; ++l)
-            if (!finite3(desc->lights[l].pos) || !finite3(desc->lights[l].intensity)) {
-                set_error("rt_build_scene: non-finite light " + std::to_string(l));
+        for (int l = 0; l < nl; ++l) {
+            const rt_light& L = desc->lights[l];
+            if (!finite3(L.pos) || !finite3(L.intensity) || L.shape < RT_LIGHT_POINT || L.shape > RT_LIGHT_DISK ||
+                (L.shape != RT_LIGHT_POINT && (!finite3(L.u) || !finite3(L.v)))) {
+                set_error("rt_build_scene: invalid light " + std::to_string(l) + " (non-finite or unknown shape)");
                 return RT_ERR_INVALID_ARG;
             }
+        }
         float scale = 1.0f;
         for (int64_t i = 0; i < ns; ++i) {
             const float* s = desc->spheres + 4 * i;
@@ -601,6 +604,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         h.depth = B.depth_reached;
         h.stack_size = stack_size;
         h.layout = o.node_layout;
+        for (int l = 0; l < nl; ++l) h.area_lights = h.area_lights || desc->lights[l].shape != RT_LIGHT_POINT;
         h.scale = scale;
         const int64_t nb = ns + nt;
         size_t off = 0;
@@ -665,8 +669,11 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         DevLight* lights = reinterpret_cast<DevLight*>(base + h.off_lights);
         for (int l = 0; l < nl; ++l) {
             const rt_light& L = desc->lights[l];
-            lights[l].pos = make_float4(L.pos[0], L.pos[1], L.pos[2], 0.0f);
+            lights[l].pos = make_float4(L.pos[0], L.pos[1], L.pos[2], (float)L.shape);
             lights[l].intensity = make_float4(L.intensity[0], L.intensity[1], L.intensity[2], 0.0f);
+            const bool area = L.shape != RT_LIGHT_POINT;
+            lights[l].u = area ? make_float4(L.u[0], L.u[1], L.u[2], 0.0f) : make_float4(0, 0, 0, 0);
+            lights[l].v = area ? make_float4(L.v[0], L.v[1], L.v[2], 0.0f) : make_float4(0, 0, 0, 0);
         }
         rt_scene_info& I = h.info;
         I.n_nodes = h.n_nodes;

@@ -37,7 +37,8 @@ class Material(C.Structure):
 
 
 class Light(C.Structure):
-    _fields_ = [("pos", C.c_float * 3), ("intensity", C.c_float * 3)]
+    _fields_ = [("pos", C.c_float * 3), ("intensity", C.c_float * 3), ("shape", C.c_int32), ("u", C.c_float * 3),
+                ("v", C.c_float * 3)]
 
 
 class SceneDesc(C.Structure):
@@ -189,6 +190,10 @@ class Scene:
         for i, l in enumerate(np.asarray(scene.lights, np.float32)):
             lights[i].pos[:] = [float(x) for x in l[0:3]]
             lights[i].intensity[:] = [float(x) for x in l[3:6]]
+            if len(l) > 6:
+                lights[i].shape = int(l[6])
+                lights[i].u[:] = [float(x) for x in l[7:10]]
+                lights[i].v[:] = [float(x) for x in l[10:13]]
         d = SceneDesc()
         d.spheres, d.n_spheres, d.sphere_mat = arr(scene.spheres, np.float32), len(scene.spheres), arr(
             scene.sphere_mat, np.int32)

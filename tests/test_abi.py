@@ -193,3 +193,19 @@ def test_tile_shapes_are_validated_and_size_the_workspace():
     p = rt.params_c(w.params, tile=4)
     assert rt.lib().rt_render_workspace_bytes(s.handle, C.byref(cam), C.byref(p)) == 0
     assert b"tile" in rt.lib().rt_last_error()
+
+
+def test_area_light_records_are_validated():
+    good = S.config0().scene
+    li = np.zeros((1, 13), np.float32)
+    li[0, :6] = [0, 5, 0, 1, 1, 1]
+    li[0, 6] = 7                                   # unknown shape
+    _bad(S.make_scene(spheres=good.spheres, sphere_mat=good.sphere_mat, materials=good.materials, lights=li),
+         "INVALID_ARG")
+    li[0, 6] = S.DISK
+    li[0, 7:10] = [np.inf, 0, 0]
+    _bad(S.make_scene(spheres=good.spheres, sphere_mat=good.sphere_mat, materials=good.materials, lights=li),
+         "INVALID_ARG")
+    li[0, 7:10] = [1, 0, 0]
+    li[0, 10:13] = [0, 0, 1]
+    rt.Scene(S.make_scene(spheres=good.spheres, sphere_mat=good.sphere_mat, materials=good.materials, lights=li))
