@@ -33,15 +33,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, area_radius=0.0):
     from paper_1504_03151_amd import scenes
     if name == "c0":
-        return scenes.config0()
-    if name == "c1":
-        return scenes.config1()
-    if name == "c2":
-        return scenes.config2()
-    raise SystemExit(f"unknown workload {name}")
+        w = scenes.config0()
+    elif name == "c1":
+        w = scenes.config1()
+    elif name == "c2":
+        w = scenes.config2()
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    if area_radius > 0.0:
+        w = scenes.with_disk_lights(w, area_radius)
+    return w
 
 
 def cpu_baseline(w, budget_s: float, seed: int = 5, scene=None):
@@ -110,6 +114,56 @@ def traffic_record(kernel, workload, tile, layout, chunk):
                     if all(rec.get(k) == v for k, v in want.items()):
                         return int(rec["bytes_per_launch"])
     return None
+
+
+def bench_progressive(args):
+    """Progressive rendering, the shape of the paper's pass-by-pass experiment (Section V, Fig. 5-6): every pass
+    samples each area light once and adds into the accumulator.  Reports passes per second (graph replays) and
+    the relative MSE of the running average after 1, 4, 16, 64 and 256 passes against a 1024-pass average."""
+    import numpy as np
+    import torch
+    from paper_1504_03151_amd import rt
+    w = workload(args.workload, args.area_lights or 2.0)
+    w.params.spp, w.params.jitter = 1, 1
+    sc = rt.Scene(w.scene, node_layout=rt.LAYOUT_BVH4Q).upload()
+    r = rt.Renderer(sc, w.camera, w.params, with_ids=False)
+    ref_passes = 1024
+    for f in range(ref_passes):
+        w.params.frame = f
+        img, _ = r.render(accum_frames=f)
+    torch.cuda.synchronize()
+    ref = img.clone().double()
+
+    def rel_mse(x):
+        return float(((x.double() - ref) ** 2 / (ref ** 2 + 0.01)).mean())
+
+    curve = {}
+    for f in range(256):
+        w.params.frame = 100000 + f
+        img, _ = r.render(accum_frames=f)
+        if f + 1 in (1, 4, 16, 64, 256):
+            torch.cuda.synchronize()
+            curve[str(f + 1)] = rel_mse(img)
+    n = max(args.steps, 64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(n):
+        w.params.frame = 200000 + f
+        r.render(accum_frames=f)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = r.read_stats()
+    assert st["status"] == 0, st
+    rays = sum(st["rays"]) + sum(st["shadow"])
+    log(f"progressive {w.name}: {n / dt:.1f} passes/s, rel-MSE vs {ref_passes} passes {curve}")
+    print(json.dumps({
+        "metric": "passes/s of progressive rendering with area lights sampled once per pass", "value": round(n / dt, 2),
+        "unit": "passes/s", "n_gpus": 1, "steps": n, "warmup": ref_passes + 256, "ms_per_step": round(dt * 1e3 / n, 4),
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "mrays_per_s": round(rays / (dt / n) / 1e6, 1), "rel_mse_vs_passes": curve,
+        "config": {"workload": w.name, "width": w.camera.width, "height": w.camera.height, "spp_per_pass": 1,
+                   "max_depth": w.params.max_depth, "lights": len(w.scene.lights), "reference_passes": ref_passes}}),
+          flush=True)
 
 
 def fixed_config(args) -> bool:
@@ -307,6 +361,11 @@ def main():
     ap.add_argument("--queue-chunk", type=int, default=0, help="0 = library default")
     ap.add_argument("--n-scenes", type=int, default=256, help="scenes of the c3 batch")
     ap.add_argument("--no-cache", action="store_true", help="skip the learned-form comparison")
+    ap.add_argument("--progressive", action="store_true",
+                    help="progressive passes with disk lights (radius --area-lights, default 2) instead of frames")
+    ap.add_argument("--area-lights", type=float, default=0.0, metavar="R",
+                    help="replace the point lights by disks of radius R facing the scene centre (sampled once per "
+                         "light per pass)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the given (or default) tile, queue chunk and node layout instead of tuning them")
     ap.add_argument("--tile", type=int, default=None, help="primary-ray tile (0 8x8, 1 16x4, 2 32x2, 3 4x16); "
@@ -339,7 +398,9 @@ def main():
     rt.lib()
     if args.workload == "c3":
         return bench_batch(args)
-    w = workload(args.workload)
+    if args.progressive:
+        return bench_progressive(args)
+    w = workload(args.workload, args.area_lights)
     log(f"workload {w.name}: {len(w.scene.spheres)} spheres, {len(w.scene.tris)} triangles, "
         f"{len(w.scene.planes)} planes, {len(w.scene.lights)} lights")
     t0 = time.perf_counter()
@@ -406,7 +467,7 @@ def main():
                 "kernel_ms_per_frame": {k: round(v[0] / args.steps, 3) for k, v in kt.items()}}
 
     cache = None
-    if not args.no_cache and w.name.startswith("c2"):
+    if not args.no_cache and w.name.startswith("c2") and not args.area_lights:
         log("learned form (radiance cache below depth 2) vs plain depth 8")
         cache = bench_cache(w, sc, r, args)
 
@@ -416,7 +477,8 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds, scene=sc)
 
     out = {
-        "metric": "Mrays/s (closest-hit + shadow rays per second), plain depth-8 Whitted frame",
+        "metric": "Mrays/s (closest-hit + shadow rays per second), plain depth-8 Whitted frame" +
+                  (f", disk lights of radius {args.area_lights:g}" if args.area_lights else ""),
         "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "ms_per_frame": round(ms, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",

@@ -125,7 +125,11 @@ enum {
     RT_FLAG_NO_GRAPH = 4,    /* launch kernels one by one instead of replaying a captured HIP graph */
     RT_FLAG_TIME_KERNELS = 8, /* record HIP events around every traversal and shading launch on the
                                  frame's stream (implies RT_FLAG_NO_GRAPH); read with rt_kernel_times */
-    RT_FLAG_PER_SAMPLE = 16   /* keep every sample: out_rgb is [H][W][spp][3], not averaged */
+    RT_FLAG_PER_SAMPLE = 16,  /* keep every sample: out_rgb is [H][W][spp][3], not averaged */
+    RT_FLAG_ACCUMULATE = 32   /* progressive rendering (rt_render only): add this frame to the accumulator
+                                 left in the workspace by the previous rt_params.accum_frames frames (0: start
+                                 afresh) and output the average over all of them, the paper's pass-by-pass
+                                 image update (Section V) */
 };
 
 enum { RT_TILE_8X8 = 0, RT_TILE_16X4 = 1, RT_TILE_32X2 = 2, RT_TILE_4X16 = 3 };
@@ -145,6 +149,7 @@ typedef struct {
     int32_t queue_chunk;      /* queue entries a traversal wave takes per fetch (0 = 128; multiple of 64) */
     int32_t tile;             /* pixels of one wave's primary rays: RT_TILE_8X8 (0), RT_TILE_16X4,
                                  RT_TILE_32X2, RT_TILE_4X16 */
+    uint32_t accum_frames;    /* with RT_FLAG_ACCUMULATE: frames already in the workspace's accumulator */
     void* workspace;          /* device, rt_render_workspace_bytes() bytes */
     size_t workspace_bytes;
     void* stats;              /* device rt_stats or NULL; accumulated, caller zeroes it */

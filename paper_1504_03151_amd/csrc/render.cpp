@@ -66,6 +66,7 @@ constexpr int kCtrShadowAll = 66; // shadow rays of every depth of a pass (defer
 constexpr int kCtrShadowAllCur = 67;
 constexpr int kCtrWords = 128;     // words cleared at the start of every pass
 constexpr int kCtrFrame = 128;     // frame number, written by the host before each launch
+constexpr int kCtrAccum = 130;     // frames already in the accumulator (progressive mode), written likewise
 constexpr int kCtrRec = 129;       // learned form: cache queries recorded this frame (cleared per frame)
 constexpr int kCtrTotal = 256;
 
@@ -1029,9 +1030,15 @@ __global__ void k_cache_select(const uint32_t* ctr, CacheRec rec, RayQ qsrc, uin
     t_pix[j] = rec.pix[src];
 }
 
-__global__ void k_resolve(const float* acc, float* out, int64_t n3, float inv_spp) {
+__global__ void k_resolve(const float* acc, float* out, int64_t n3, float inv_spp, const uint32_t* accum) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n3) out[i] = acc[i] * inv_spp;
+    if (i < n3) out[i] = acc[i] * (inv_spp / (float)(*accum + 1u));
+}
+
+// clears the accumulator unless the frame adds to earlier ones (progressive mode)
+__global__ void k_clear_acc(float* acc, int64_t n, const uint32_t* accum) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && *accum == 0u) acc[i] = 0.0f;
 }
 
 // fold a pass's queue counters into the caller's statistics
@@ -1456,7 +1463,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     seg.overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes);
     seg.grid = A.gs;
     const int64_t n3 = 3 * pl.nacc;
-    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
+    hipLaunchKernelGGL(k_clear_acc, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, ctr + kCtrAccum);
     if (A.shc.light_pts) {
         const int n = A.spp * A.sc.n_lights;
         hipLaunchKernelGGL(k_light_points, dim3((n + 255) / 256), dim3(256), 0, st, A.sc.lights, A.sc.n_lights,
@@ -1492,7 +1499,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
         hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, A.shc.max_depth, 0);
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
-                       A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp);
+                       A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp, ctr + kCtrAccum);
     HIP_TRY(hipGetLastError());
     return RT_OK;
 }
@@ -2107,7 +2114,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         }
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
-                       A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp);
+                       A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp, ctr + kCtrAccum);
     HIP_TRY(hipGetLastError());
     return RT_OK;
 }
@@ -2253,6 +2260,9 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     hipStream_t st = static_cast<hipStream_t>(p.stream);
     const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
     HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + pl.off_ctr + 4 * kCtrFrame), (int)p.frame, 1,
+                              st));
+    const uint32_t accum = (p.flags & RT_FLAG_ACCUMULATE) ? p.accum_frames : 0u;
+    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + pl.off_ctr + 4 * kCtrAccum), (int)accum, 1,
                               st));
     rs = launch_frame(A, st, graph, h.uid);
     if (rs != RT_OK) return rs;
@@ -2449,6 +2459,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     hipStream_t st = static_cast<hipStream_t>(p.stream);
     HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + A.pl.off_ctr + 4 * kCtrFrame), (int)p.frame, 1,
                               st));
+    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + A.pl.off_ctr + 4 * kCtrAccum), 0, 1, st));
     const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
     rs = launch_cached(C, st, graph, h.uid);
     if (rs != RT_OK) return rs;

@@ -22,6 +22,7 @@ RT_OK = 0
 RT_ERR = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP", -4: "BVH_DEPTH", -5: "CAPACITY",
           -6: "DEVICE_STATUS", -7: "NOT_UPLOADED"}
 FLAG_SYNC, FLAG_COUNT_WORK, FLAG_NO_GRAPH, FLAG_TIME_KERNELS, FLAG_PER_SAMPLE = 1, 2, 4, 8, 16
+FLAG_ACCUMULATE = 32
 STATS_MAX_DEPTH = 16
 
 
@@ -63,8 +64,8 @@ class ParamsC(C.Structure):
     _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("jitter", C.c_int32), ("frame", C.c_uint32),
                 ("seed", C.c_uint64), ("bg", C.c_float * 3), ("eps", C.c_float),
                 ("samples_per_pass", C.c_int32), ("flags", C.c_int32), ("queue_factor", C.c_float),
-                ("queue_chunk", C.c_int32), ("tile", C.c_int32), ("workspace", C.c_void_p),
-                ("workspace_bytes", C.c_size_t),
+                ("queue_chunk", C.c_int32), ("tile", C.c_int32), ("accum_frames", C.c_uint32),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stats", C.c_void_p), ("stream", C.c_void_p)]
 
 
@@ -319,13 +320,18 @@ class Renderer:
         self.ids = torch.empty((H, W, self.params.spp), dtype=torch.int32, device=self.device) if with_ids else None
         self.stats = torch.zeros(C.sizeof(Stats) + 64, dtype=torch.uint8, device=self.device)
 
-    def render(self, flags=0, stream=None, reset_stats=True):
+    def render(self, flags=0, stream=None, reset_stats=True, accum_frames=None):
+        """One frame.  accum_frames=n: progressive mode, add this frame to the n frames already accumulated in
+        this renderer's workspace (0 starts afresh) and return the running average."""
         if reset_stats:
             self.stats.zero_()
         if not self.graph:
             flags |= FLAG_NO_GRAPH
+        if accum_frames is not None:
+            flags |= FLAG_ACCUMULATE
         p = params_c(self.params, flags | self.base_flags, self.samples_per_pass, self.queue_factor,
                      self.queue_chunk, self.tile)
+        p.accum_frames = int(accum_frames or 0)
         p.workspace, p.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
         p.stats = self.stats.data_ptr()
         p.stream = _stream_ptr(stream)

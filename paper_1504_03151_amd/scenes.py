@@ -380,6 +380,27 @@ def pixel_subset(cam: Camera, n: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(cam.n_pixels, size=n, replace=False)).astype(np.int64)
 
 
+def with_disk_lights(w: Workload, radius: float) -> Workload:
+    """The same workload with each point light replaced by a disk of the given radius centred on it and
+    facing the scene origin (area lights sampled once per pass)."""
+    import copy
+    w = copy.deepcopy(w)
+    L = w.scene.lights.copy()
+    for i in range(len(L)):
+        n = -L[i, :3].astype(np.float64)
+        n /= max(np.linalg.norm(n), 1e-30)
+        a = np.array([1.0, 0.0, 0.0]) if abs(n[0]) < 0.9 else np.array([0.0, 1.0, 0.0])
+        u = np.cross(n, a)
+        u /= np.linalg.norm(u)
+        v = np.cross(n, u)
+        L[i, 6] = DISK
+        L[i, 7:10] = radius * u
+        L[i, 10:13] = radius * v
+    w.scene.lights = L.astype(np.float32)
+    w.name = w.name + f"_disk{radius:g}"
+    return w
+
+
 def mlp_init_weights(seed: int):
     """He-uniform FP32 initial weights of the radiance-cache network from a seeded RNG:
     [W1 .. W5] (64 x 64, row-major out x in), W6 (3 x 64).  The fan-in of W1 counts the

@@ -98,3 +98,37 @@ def test_batch_with_area_lights_equals_sequential_frames(rt):
         torch.cuda.synchronize()
         assert torch.equal(ids, ib)
         assert torch.allclose(rgb, rb, rtol=1e-5, atol=1e-6), (rgb - rb).abs().max().item()
+
+
+def test_progressive_passes_average_the_frames(rt):
+    """Progressive mode (the paper's pass-by-pass image update): frame f added to the f frames already in the
+    accumulator gives the mean of frames 0..f, also through graph replays; the mean of the area-lit passes
+    matches the oracle's mean of the same passes."""
+    w = area_tiny(0, size=32)
+    w.params.spp, w.params.jitter = 1, 1
+    sc = rt.Scene(w.scene).upload()
+    single = rt.Renderer(sc, w.camera, w.params)
+    prog = rt.Renderer(sc, w.camera, w.params)
+    frames = []
+    for f in range(6):
+        w.params.frame = f
+        img, _ = single.render(rt.FLAG_SYNC)
+        frames.append(img.clone())
+        acc, _ = prog.render(rt.FLAG_SYNC, accum_frames=f)
+        torch.cuda.synchronize()
+        expect = torch.stack(frames).mean(0)
+        assert torch.allclose(acc, expect, rtol=1e-5, atol=1e-6), (f, (acc - expect).abs().max().item())
+    refs = []
+    for f in range(6):
+        w.params.frame = f
+        refs.append(oracle.render(w.scene, w.camera, w.params))
+    rob = np.all([r["margin"] > ROBUST for r in refs], axis=0)
+    assert rob.mean() > 0.85
+    ref_mean = np.mean([r["rgb"] for r in refs], axis=0)
+    err = np.abs(acc.reshape(-1, 3).double().cpu().numpy() - ref_mean).max(axis=1)
+    assert err[rob].max() <= RGB_TOL
+    # starting afresh discards the accumulator
+    w.params.frame = 2
+    again, _ = prog.render(rt.FLAG_SYNC, accum_frames=0)
+    torch.cuda.synchronize()
+    assert torch.allclose(again, frames[2], rtol=1e-5, atol=1e-6)
