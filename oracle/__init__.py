@@ -55,7 +55,7 @@ class _Camera(C.Structure):
 
 
 class _Params(C.Structure):
-    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("jitter", C.c_int32), ("pad0", C.c_int32),
+    _fields_ = [("spp", C.c_int32), ("max_depth", C.c_int32), ("jitter", C.c_int32), ("gi", C.c_int32),
                 ("seed", C.c_uint64), ("frame", C.c_uint32), ("pad1", C.c_uint32),
                 ("bg", C.c_double * 3), ("eps", C.c_double)]
 
@@ -94,6 +94,8 @@ def lib():
             L.or_pcg.argtypes = [C.c_uint32]
             L.or_jitter.restype = C.c_double
             L.or_jitter.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
+            L.or_path_rand.restype = C.c_double
+            L.or_path_rand.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32]
             _lib = L
     return _lib
 
@@ -139,6 +141,7 @@ def _camera(cam) -> _Camera:
 def _params(p) -> _Params:
     q = _Params()
     q.spp, q.max_depth, q.jitter = int(p.spp), int(p.max_depth), int(p.jitter)
+    q.gi = int(getattr(p, "gi", 0))
     q.seed, q.frame = int(p.seed) & (2 ** 64 - 1), int(p.frame) & (2 ** 32 - 1)
     q.bg[:] = [float(x) for x in p.bg]
     q.eps = float(p.eps)
@@ -255,6 +258,11 @@ def pcg(v: int) -> int:
 
 def jitter(seed: int, frame: int, pixel: int, s: int, dim: int) -> float:
     return float(lib().or_jitter(seed & (2 ** 64 - 1), frame, pixel, s, dim))
+
+
+def path_rand(seed: int, frame: int, pixel: int, s: int, depth: int, k: int) -> float:
+    """Random number k of the bounce at `depth` of sample s of a pixel (global illumination paths)."""
+    return float(lib().or_path_rand(seed & (2 ** 64 - 1), frame, pixel, s, depth, k))
 
 
 ROBUST = 1e-4

@@ -85,7 +85,8 @@ typedef struct {
 } or_camera;
 
 typedef struct {
-    int32_t spp, max_depth, jitter, pad0;
+    int32_t spp, max_depth, jitter;
+    int32_t gi;       /* 1: diffuse global illumination by path tracing (see trace) */
     uint64_t seed;
     uint32_t frame, pad1;
     double bg[3];
@@ -126,6 +127,20 @@ double or_jitter(uint64_t seed, uint32_t frame, uint32_t pixel, uint32_t s, uint
     h = or_pcg(h ^ frame);
     h = or_pcg(h ^ pixel);
     h = or_pcg(h ^ (s * 2u + dim));
+    return (double)(h >> 8) * (1.0 / 16777216.0);
+}
+
+/* Random numbers of a path: number k of the bounce at depth `depth` of sample
+ * s of a pixel.  The camera-jitter hash chain through the pixel, then the
+ * sample and a word with the top bit set (no camera-jitter word has it) that
+ * holds depth and k.  24 random bits, exact in FP32 and FP64. */
+double or_path_rand(uint64_t seed, uint32_t frame, uint32_t pixel, uint32_t s, uint32_t depth, uint32_t k) {
+    uint32_t h = or_pcg((uint32_t)seed);
+    h = or_pcg(h ^ (uint32_t)(seed >> 32));
+    h = or_pcg(h ^ frame);
+    h = or_pcg(h ^ pixel);
+    h = or_pcg(h ^ s);
+    h = or_pcg(h ^ (0x80000000u | (depth << 2) | k));
     return (double)(h >> 8) * (1.0 / 16777216.0);
 }
 
@@ -559,6 +574,8 @@ typedef struct {
     int64_t cache_cap;
     int64_t list_index;
     int32_t sample;    /* sample (pass) index: selects the area lights' sample points */
+    int64_t pixel;     /* pixel index (row-major): with sample and depth, keys the path's random numbers */
+    double gmax;       /* bound on the weight factor of one bounce (1 without global illumination) */
 } pctx;
 
 /* A decision whose worst-case effect on the sample's radiance is at most
@@ -581,10 +598,30 @@ static void note_margin(pctx* P, double m, double effect) {
 }
 
 /* bound on the radiance of a ray at depth k: local radiance at most lloc per
- * level (reflection weights k_r <= 1, F + (1 - F) = 1), plus the background */
+ * level, each level's weight factor at most gmax (1 for Whitted recursion:
+ * k_r <= 1, F + (1 - F) = 1), plus the background */
 static double radiance_bound(const pctx* P, int k) {
     const double* bg = P->p->bg;
-    return (P->p->max_depth - k + 1) * P->lloc + fmax(bg[0], fmax(bg[1], bg[2]));
+    double b = 0.0, g = 1.0;
+    for (int j = k; j <= P->p->max_depth; ++j) {
+        b += g * P->lloc;
+        g *= P->gmax;
+    }
+    return b + g / P->gmax * fmax(bg[0], fmax(bg[1], bg[2]));
+}
+
+/* bound on one bounce's weight factor with global illumination: the sum of
+ * the branch weights of the material (see trace), at least 1 */
+static double bounce_bound(const or_scene* sc, const or_params* p) {
+    double g = 1.0;
+    if (!p->gi) return g;
+    for (int m = 0; m < sc->n_materials; ++m) {
+        const float* M = sc->materials + 10 * m;
+        const double am = fmax(M[0], fmax(M[1], M[2]));
+        const double spec = ((int)M[9] == MAT_DIELECTRIC) ? 1.0 : fmax(0.0, (double)M[7]);
+        g = fmax(g, fmax(0.0, (double)M[4]) * am + spec);
+    }
+    return g;
 }
 
 static double local_bound(const or_scene* sc) {
@@ -602,7 +639,7 @@ static double local_bound(const or_scene* sc) {
     return amb + lsum * mat;
 }
 
-/* ray log record: kind (0 camera, 1 reflected, 2 refracted, 3 shadow), depth,
+/* ray log record: kind (0 camera, 1 reflected, 2 refracted, 3 shadow, 4 diffuse), depth,
  * o[3], d[3], tmax, t (closest hit) or blocked (shadow), id, margin */
 #define RECW 12
 static void log_ray(pctx* P, int kind, int depth, const oray* r, double t_or_occ, int64_t id, double margin) {
@@ -646,6 +683,120 @@ static double geom_normal(const or_scene* sc, int64_t id, const double* x, doubl
         load3f(n, pl);
         normalize3(n);
         return EA;
+    }
+}
+
+static void trace(pctx* P, const oray* ray, int kind, int k, const double* w, double* out, int64_t* primary_id);
+
+/* Global illumination (Eq. 8, the hemisphere integral, Section II) by path
+ * tracing: where Whitted recursion follows every specular branch, a path
+ * follows one branch per bounce, chosen at random among
+ *   diffuse  weight W_d = k_d * albedo (per channel): the Lambertian part,
+ *            BRDF k_d * albedo / pi, sampled with the cosine-weighted density
+ *            cos(theta) / pi, so that the estimator's factor is W_d;
+ *   reflect  weight k_r (mirror), or F (dielectric);
+ *   refract  weight 1 - F (dielectric, no total internal reflection);
+ * with probability m_x / S, m_x the largest channel of branch x's weight and
+ * S the sum of the m_x, and factor W_x * S / m_x: the expectation is the sum
+ * of W_x times the branch's radiance, the full branching sum.  The branch is
+ * the first (in the order above, among branches with m_x > 0) with
+ * u S < m_1 + ... + m_x, else the last; u = or_path_rand(.., k, 0).
+ * The diffuse direction is normalize(N_f + s), s uniform on the unit sphere
+ * (z = 1 - 2 xi1, phi = 2 pi xi2; xi = or_path_rand(.., k, 1 and 2)): a point
+ * uniform on the unit sphere that touches the surface at the hit point, seen
+ * from the hit point, is cosine-distributed about N_f.  The light sources are
+ * reached only by the shadow rays (they are not geometry), so nothing is
+ * counted twice. */
+static void gi_bounce(pctx* P, const oray* ray, int k, const double* w, const double* x, const double* xs,
+                      const double* nf, double sn, double so2, double eps_s, int entering, const float* m,
+                      double* out) {
+    const or_params* p = P->p;
+    const double alb[3] = {m[0], m[1], m[2]};
+    const double kd = m[4], kr = m[7], ior = m[8];
+    const int type = (int)m[9];
+    const double cosi = -dot3(ray->d, nf);
+    const double wmax = fmax(w[0], fmax(w[1], w[2]));
+    /* the specular branches: directions and weights as in Whitted recursion */
+    double F = 0.0, T = 0.0;
+    oray rf, tr;
+    for (int i = 0; i < 3; ++i) {
+        rf.o[i] = xs[i];
+        rf.d[i] = ray->d[i] + 2.0 * cosi * nf[i];
+    }
+    normalize3(rf.d);
+    rf.tmax = OR_INF;
+    rf.so = so2;
+    rf.sd = ray->sd + 2.0 * sn + EA;
+    if (type == MAT_DIELECTRIC) {
+        const double eta = entering ? 1.0 / ior : ior;
+        const double k2 = 1.0 - eta * eta * (1.0 - cosi * cosi);
+        note_margin(P, 1e-4 * fabs(k2) / (2.0 * eta * eta * (ray->sd + sn) + EA), wmax * radiance_bound(P, k + 1));
+        const double r0 = ((ior - 1.0) / (ior + 1.0)) * ((ior - 1.0) / (ior + 1.0));
+        F = 1.0;
+        if (k2 >= 0.0) {
+            const double ck = sqrt(k2);
+            const double cc = entering ? cosi : ck;
+            const double om = 1.0 - cc;
+            F = r0 + (1.0 - r0) * om * om * om * om * om;
+            T = 1.0 - F;
+            for (int i = 0; i < 3; ++i) {
+                tr.o[i] = x[i] - eps_s * nf[i];
+                tr.d[i] = eta * ray->d[i] + (eta * cosi - ck) * nf[i];
+            }
+            normalize3(tr.d);
+            tr.tmax = OR_INF;
+            tr.so = so2;
+            tr.sd = (ray->sd + 2.0 * sn) * (1.0 + eta / fmax(ck, 1e-2)) + EA;
+        }
+    } else if (kr > 0.0) {
+        F = kr;
+    }
+    const double md = kd > 0.0 ? kd * fmax(alb[0], fmax(alb[1], alb[2])) : 0.0;
+    const double mx[3] = {md, F, T};
+    const double S = md + F + T;
+    if (!(S > 0.0)) return;
+    const uint32_t pix = (uint32_t)P->pixel, smp = (uint32_t)P->sample;
+    const double u = or_path_rand(p->seed, p->frame, pix, smp, (uint32_t)k, 0);
+    int last = -1, pick = -1;
+    double cum = 0.0, gap = OR_INF;
+    for (int b = 0; b < 3; ++b) {
+        if (!(mx[b] > 0.0)) continue;
+        if (last >= 0) gap = fmin(gap, fabs(u * S - cum) / S);   /* the boundary between two branches */
+        cum += mx[b];
+        if (pick < 0 && u * S < cum) pick = b;
+        last = b;
+    }
+    if (pick < 0) pick = last;
+    double f[3];
+    if (gap < OR_INF) note_margin(P, gap, wmax * S * radiance_bound(P, k + 1));
+    if (pick == 0) {
+        for (int i = 0; i < 3; ++i) f[i] = kd * alb[i] * S / md;
+        const double xi1 = or_path_rand(p->seed, p->frame, pix, smp, (uint32_t)k, 1);
+        const double xi2 = or_path_rand(p->seed, p->frame, pix, smp, (uint32_t)k, 2);
+        const double z = 1.0 - 2.0 * xi1, r = sqrt(fmax(0.0, 1.0 - z * z)), phi = 2.0 * M_PI * xi2;
+        const double sph[3] = {r * cos(phi), r * sin(phi), z};
+        oray dr;
+        for (int i = 0; i < 3; ++i) {
+            dr.o[i] = xs[i];
+            dr.d[i] = nf[i] + sph[i];
+        }
+        const double len = norm3(dr.d);
+        /* the direction is ill-conditioned where s is nearly -N_f */
+        note_margin(P, fmin(len, 1e-4 * len / (sn + 4.0 * EA)), wmax * S * radiance_bound(P, k + 1));
+        if (!(len > 0.0)) return;
+        for (int i = 0; i < 3; ++i) dr.d[i] /= len;
+        dr.tmax = OR_INF;
+        dr.so = so2;
+        dr.sd = (sn + 4.0 * EA) / len + EA;
+        double wc[3], lc[3];
+        for (int i = 0; i < 3; ++i) wc[i] = w[i] * f[i];
+        trace(P, &dr, 4, k + 1, wc, lc, NULL);
+        for (int i = 0; i < 3; ++i) out[i] += f[i] * lc[i];
+    } else {
+        double wc[3], lc[3];
+        for (int i = 0; i < 3; ++i) wc[i] = w[i] * S;
+        trace(P, pick == 1 ? &rf : &tr, pick == 1 ? 1 : 2, k + 1, wc, lc, NULL);
+        for (int i = 0; i < 3; ++i) out[i] += S * lc[i];
     }
 }
 
@@ -741,6 +892,10 @@ static void trace(pctx* P, const oray* ray, int kind, int k, const double* w, do
     }
     for (int i = 0; i < 3; ++i) out[i] = local[i];
     if (k >= p->max_depth) return;
+    if (p->gi) {
+        gi_bounce(P, ray, k, w, x, xs, nf, sn, so2, eps_s, entering, m, out);
+        return;
+    }
 
     const double cosi = -dot3(ray->d, nf);   /* > 0 */
     oray rf;
@@ -852,7 +1007,7 @@ static void render_one(void* vctx, int64_t i) {
     int32_t local_counts[2 * 64];
     memset(local_counts, 0, sizeof local_counts);
     pctx P = {J->S, J->sc, J->p, MARGIN_CAP, local_counts, NULL, 0, 0, local_bound(J->sc), 0.0,
-              J->cache_depth, J->cache_rec, J->cache_n, J->cache_cap, i};
+              J->cache_depth, J->cache_rec, J->cache_n, J->cache_cap, i, 0, J->pixels[i], bounce_bound(J->sc, J->p)};
     const double one[3] = {1.0, 1.0, 1.0};
     double acc[3] = {0, 0, 0};
     const int64_t pix = J->pixels[i];
@@ -964,7 +1119,8 @@ int64_t or_ray_tree(const or_scene* sc, const or_camera* cam, const or_params* p
     if (oscene_init(&S, sc) != 0) return -2;
     int32_t counts[2 * 64];
     memset(counts, 0, sizeof counts);
-    pctx P = {&S, sc, p, MARGIN_CAP, counts, rec, 0, cap, local_bound(sc), 0.0, -1, NULL, NULL, 0, 0};
+    pctx P = {&S, sc, p, MARGIN_CAP, counts, rec, 0, cap, local_bound(sc), 0.0, -1, NULL, NULL, 0, 0, 0, pixel,
+              bounce_bound(sc, p)};
     const double one[3] = {1.0, 1.0, 1.0};
     oray r;
     or_camera_ray(cam, p, pixel, sample, r.o, r.d);
@@ -1005,13 +1161,15 @@ typedef struct {
     double* L;
     double* margin;
     int32_t sample;
+    const int64_t* pixels;   /* pixel of each ray (keys its path's random numbers), or NULL: the ray's index */
 } radiance_job;
 
 static void radiance_one(void* vctx, int64_t i) {
     radiance_job* J = (radiance_job*)vctx;
     int32_t counts[2 * 64];
     memset(counts, 0, sizeof counts);
-    pctx P = {J->S, J->S->in, J->p, MARGIN_CAP, counts, NULL, 0, 0, local_bound(J->S->in), 0.0, -1, NULL, NULL, 0, 0};
+    pctx P = {J->S, J->S->in, J->p, MARGIN_CAP, counts, NULL, 0, 0, local_bound(J->S->in), 0.0, -1, NULL, NULL, 0, 0,
+              0, J->pixels ? J->pixels[i] : i, bounce_bound(J->S->in, J->p)};
     oray r;
     load_ray(J->rays + 9 * i, &r);
     const double one[3] = {1.0, 1.0, 1.0};
@@ -1028,7 +1186,7 @@ int or_radiance(const or_scene* sc, const or_params* p, const double* rays, int6
     if (p->max_depth < 0 || p->max_depth > 63 || start_depth < 0 || start_depth > p->max_depth) return -1;
     oscene S;
     if (oscene_init(&S, sc) != 0) return -2;
-    radiance_job J = {&S, p, rays, start_depth, L, margin, sample};
+    radiance_job J = {&S, p, rays, start_depth, L, margin, sample, NULL};
     run_parallel(n, nthreads, radiance_one, &J);
     oscene_free(&S);
     return 0;

@@ -85,6 +85,7 @@ class Params:
     frame: int = 0
     bg: Tuple[float, float, float] = (0.1, 0.2, 0.3)
     eps: float = 1e-3
+    gi: int = 0          # 1: diffuse global illumination by path tracing
 
 
 @dataclasses.dataclass
