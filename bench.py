@@ -41,6 +41,8 @@ def workload(name, area_radius=0.0):
         w = scenes.config1()
     elif name == "c2":
         w = scenes.config2()
+    elif name == "gi":
+        w = scenes.config_gi()
     else:
         raise SystemExit(f"unknown workload {name}")
     if area_radius > 0.0:
@@ -353,7 +355,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c2", help="c0, c1, c2 (default), c3 (the batch) or gi (diffuse global "
+                                                         "illumination in a closed room, depth 6)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--graph", action="store_true", help="time graph replays (no per-kernel events)")
@@ -477,7 +480,9 @@ def main():
         cpu = cpu_baseline(w, args.cpu_seconds, scene=sc)
 
     out = {
-        "metric": "Mrays/s (closest-hit + shadow rays per second), plain depth-8 Whitted frame" +
+        "metric": "Mrays/s (closest-hit + shadow rays per second), " +
+                  (f"depth-{w.params.max_depth} path-traced frame with diffuse global illumination" if w.params.gi
+                   else f"plain depth-{w.params.max_depth} Whitted frame") +
                   (f", disk lights of radius {args.area_lights:g}" if args.area_lights else ""),
         "value": round(value, 2), "unit": "Mrays/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 3), "ms_per_frame": round(ms, 3), "higher_is_better": True, "scaling": "weak",

@@ -126,10 +126,23 @@ enum {
     RT_FLAG_TIME_KERNELS = 8, /* record HIP events around every traversal and shading launch on the
                                  frame's stream (implies RT_FLAG_NO_GRAPH); read with rt_kernel_times */
     RT_FLAG_PER_SAMPLE = 16,  /* keep every sample: out_rgb is [H][W][spp][3], not averaged */
-    RT_FLAG_ACCUMULATE = 32   /* progressive rendering (rt_render only): add this frame to the accumulator
+    RT_FLAG_ACCUMULATE = 32,  /* progressive rendering (rt_render only): add this frame to the accumulator
                                  left in the workspace by the previous rt_params.accum_frames frames (0: start
                                  afresh) and output the average over all of them, the paper's pass-by-pass
                                  image update (Section V) */
+    RT_FLAG_GI = 64           /* diffuse global illumination (Eq. 8, the hemisphere integral of Section II) by
+                                 path tracing (rt_render and rt_render_batch; per scene in a batch): every
+                                 hit still adds its Phong local terms through shadow rays, and the path
+                                 continues with ONE ray while depth < max_depth, chosen at random among the
+                                 diffuse bounce (weight k_d * albedo: a Lambertian BRDF k_d * albedo / pi,
+                                 cosine-weighted direction normalize(N_f + s), s uniform on the unit sphere),
+                                 the mirror reflection (k_r, or F for a dielectric) and the refraction
+                                 (1 - F), each with probability proportional to the largest channel of its
+                                 weight, and weighted by weight / probability.  Random numbers: the PCG hash
+                                 chain of the camera jitter through (seed, frame, pixel), then the sample,
+                                 then the word 0x80000000 | depth << 2 | k (k = 0 branch, 1 and 2 the
+                                 direction); 24 bits each.  Not supported by rt_render_cached
+                                 (RT_ERR_INVALID_ARG). */
 };
 
 enum { RT_TILE_8X8 = 0, RT_TILE_16X4 = 1, RT_TILE_32X2 = 2, RT_TILE_4X16 = 3 };

@@ -110,6 +110,7 @@ struct ShadeConst {
     // cell = floor((x - bin_lo) * bin_inv) per axis on a bin_c^3 grid over the scene
     float bin_lo[3], bin_inv[3];
     int bin_c;
+    int gi;   // 1: global illumination, one randomly chosen continuation per hit (path tracing)
 };
 
 // One scene of a batched frame (device table, one entry per scene).
@@ -649,7 +650,8 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
 // slots are reserved with one atomic per block and queue; shadow rays are laid
 // out light-major inside each wave (consecutive entries go to the same light)
 // so the shadow kernel's waves traverse coherently.
-template <bool BATCH>
+// GI: compiled with the path-tracing branch (taken where the scene's ShadeConst has gi set).
+template <bool BATCH, bool GI>
 __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const BatchScene* tab, RayQ qin, HitQ hit,
                                                uint32_t* ctr, int depth, RayQ qout, ShadowQ sq, float* acc) {
     __shared__ uint32_t lds_res[4];
@@ -772,7 +774,7 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
         }
         // ---- secondary rays
         bool want_r = false, want_t = false;
-        float wr_s = 0.0f, wt_s = 0.0f;
+        float wr_s = 0.0f, wt_s = 0.0f;   // Whitted branch weights (scalars)
         V3 dr = v3(0, 0, 0), dt = v3(0, 0, 0);
         const float cosi = entering ? -dn : dn;   // = -d.nf >= 0
         if (shade && depth < C.max_depth) {
@@ -800,6 +802,57 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
                 wr_s = kr;
             }
         }
+        V3 fr = v3(wr_s, wr_s, wr_s), ft = v3(wt_s, wt_s, wt_s);   // factors of the spawned rays' weights
+        if (GI && C.gi && shade && depth < C.max_depth) {
+            // path tracing: one branch among diffuse (k_d albedo), reflect and refract, chosen with
+            // probability m_x / S (m_x: largest channel of the branch weight), weighted by weight * S / m_x
+            const uint32_t frame = BATCH ? tab[sid].cam.frame : ctr[kCtrFrame];
+            const uint32_t local = pix - C.acc_off;
+            const uint32_t pixel = C.per_sample ? local / (uint32_t)C.spp : local;
+            const float md = kd > 0.0f ? kd * fmaxf(alb.x, fmaxf(alb.y, alb.z)) : 0.0f;
+            const float mr = want_r ? wr_s : 0.0f, mt = want_t ? wt_s : 0.0f;
+            const float ssum = md + mr + mt;
+            int pick = -1;
+            if (ssum > 0.0f) {
+                const float us = path_rand(C.seed, frame, pixel, smp, (uint32_t)depth, 0u) * ssum;
+                float cum = 0.0f;
+                int last = -1;
+                if (md > 0.0f) {
+                    cum += md;
+                    last = 0;
+                    if (us < cum) pick = 0;
+                }
+                if (mr > 0.0f) {
+                    cum += mr;
+                    last = 1;
+                    if (pick < 0 && us < cum) pick = 1;
+                }
+                if (mt > 0.0f) {
+                    cum += mt;
+                    last = 2;
+                    if (pick < 0 && us < cum) pick = 2;
+                }
+                if (pick < 0) pick = last;
+            }
+            want_r = pick == 0 || pick == 1;
+            want_t = pick == 2;
+            fr = v3(ssum, ssum, ssum);
+            ft = fr;
+            if (pick == 0) {
+                // cosine-weighted: N_f plus a point uniform on the unit sphere, normalized
+                const float z = 1.0f - 2.0f * path_rand(C.seed, frame, pixel, smp, (uint32_t)depth, 1u);
+                const float phi = 6.28318530717958647692f * path_rand(C.seed, frame, pixel, smp, (uint32_t)depth, 2u);
+                const float r = sqrtf(fmaxf(0.0f, 1.0f - z * z));
+                float sp, cp;
+                sincosf(phi, &sp, &cp);
+                const V3 dd = nf + v3(r * cp, r * sp, z);
+                const float len = sqrtf(dot(dd, dd));
+                want_r = len > 0.0f;
+                dr = dd * (1.0f / len);
+                const float g = kd * (ssum / md);
+                fr = v3(g * alb.x, g * alb.y, g * alb.z);
+            }
+        }
         const uint32_t nsec = (want_r ? 1u : 0u) + (want_t ? 1u : 0u);
         uint32_t sec_tot;
         const uint32_t sec_off = wave_scan(nsec, sec_tot);
@@ -813,9 +866,9 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
                 qout.dx[qslot] = dr.x;
                 qout.dy[qslot] = dr.y;
                 qout.dz[qslot] = dr.z;
-                qout.wr[qslot] = w.x * wr_s;
-                qout.wg[qslot] = w.y * wr_s;
-                qout.wb[qslot] = w.z * wr_s;
+                qout.wr[qslot] = w.x * fr.x;
+                qout.wg[qslot] = w.y * fr.y;
+                qout.wb[qslot] = w.z * fr.z;
                 qout.pix[qslot] = pix;
                 qout.meta[qslot] = meta_next;
             } else {
@@ -832,9 +885,9 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
                 qout.dx[qslot] = dt.x;
                 qout.dy[qslot] = dt.y;
                 qout.dz[qslot] = dt.z;
-                qout.wr[qslot] = w.x * wt_s;
-                qout.wg[qslot] = w.y * wt_s;
-                qout.wb[qslot] = w.z * wt_s;
+                qout.wr[qslot] = w.x * ft.x;
+                qout.wg[qslot] = w.y * ft.y;
+                qout.wb[qslot] = w.z * ft.z;
                 qout.pix[qslot] = pix;
                 qout.meta[qslot] = meta_next;
             } else {
@@ -1193,16 +1246,23 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
         why = "too many pixels";
         return false;
     }
+    // Path tracing (RT_FLAG_GI) continues a path with at most one ray, so a depth's queue never holds more
+    // than the pass's primary rays, and the deferred shadow queue at most (max_depth + 1) x lights per
+    // primary ray: exact capacities.  Whitted trees branch; their queues are sized by queue_factor.
+    const bool gi = (p.flags & RT_FLAG_GI) != 0;
+    const int64_t n_lights = std::max(1, s.n_lights);
     const int64_t target = 32 << 20;   // primary rays per pass when chosen automatically
-    int spp_pass = p.samples_per_pass > 0 ? std::min(p.samples_per_pass, p.spp)
-                                           : (int)std::max<int64_t>(1, std::min<int64_t>(p.spp, target / pl.npix));
+    const int64_t shadow_target = 512 << 20;   // path tracing: deferred shadow entries per pass, likewise
+    int64_t auto_spp = std::min<int64_t>(p.spp, target / pl.npix);
+    if (gi) auto_spp = std::min<int64_t>(auto_spp, shadow_target / (pl.npix * (p.max_depth + 1) * n_lights));
+    int spp_pass = p.samples_per_pass > 0 ? std::min(p.samples_per_pass, p.spp) : (int)std::max<int64_t>(1, auto_spp);
     pl.spp_pass = spp_pass;
     pl.passes = (p.spp + spp_pass - 1) / spp_pass;
     // ray slots of a full pass: every pixel tile is padded to 64 slots
     pl.n_primary = tiles_x_of(cam.width, p.tile) * tiles_y_of(cam.height, p.tile) * 64 * spp_pass;
-    const double qf = p.queue_factor > 0.0f ? std::max(1.0f, p.queue_factor) : 2.0;
+    const double qf = p.queue_factor > 0.0f ? std::max(1.0f, p.queue_factor) : (gi ? 1.0 : 2.0);
     const double qcap = std::ceil(pl.n_primary * qf);
-    const double scap = qcap * std::max(1, s.n_lights);
+    const double scap = gi ? (double)pl.n_primary * (p.max_depth + 1) * n_lights : qcap * n_lights;
     if (qcap > 4.0e9 || scap > 4.0e9) {
         why = "queue capacity exceeds 2^32; lower samples_per_pass or queue_factor";
         return false;
@@ -1491,8 +1551,12 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
             }
             {
                 KernelTimer kt(A.time_kernels, st, 1);
-                hipLaunchKernelGGL(k_shade<false>, dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr, qi, hq,
-                                   ctr, k, qo, sq, acc);
+                if (A.shc.gi)
+                    hipLaunchKernelGGL((k_shade<false, true>), dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc,
+                                       nullptr, qi, hq, ctr, k, qo, sq, acc);
+                else
+                    hipLaunchKernelGGL((k_shade<false, false>), dim3(shade_blocks), dim3(256), 0, st, A.sc, A.shc,
+                                       nullptr, qi, hq, ctr, k, qo, sq, acc);
             }
         }
         enqueue_shadow_segment(A, sq, seg, nb, acc, swork, st);
@@ -1583,6 +1647,7 @@ struct BatchPlan {
     uint64_t n_acc = 0;
     uint32_t qcap = 0, scap = 0;
     int dmax = 0, stack_max = 0;
+    bool any_gi = false;        // some scene renders with global illumination
     size_t off_tab = 0, off_ctr = 0, off_acc = 0, off_q[2] = {0, 0}, off_hit = 0, off_s = 0, off_stack = 0, total = 0;
     size_t off_lpts = 0;
     uint32_t n_lpts = 0;        // light-point entries of the scenes with area lights
@@ -1641,6 +1706,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
             B.shc.acc_off = (uint32_t)acc;
             B.shc.out_ids = out_ids ? out_ids[i] : nullptr;
             B.shc.defer_shadow = 1;   // one shadow queue for every scene and depth, traced after the bounces
+            B.shc.gi = (p.flags & RT_FLAG_GI) ? 1 : 0;
             camera_consts(cam, p, B.cam);
             B.ray_off = (uint32_t)rays;
             B.n_rays = (uint32_t)nr;
@@ -1656,11 +1722,14 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
         rays += nr;
         acc += na;
         bp.dmax = std::max(bp.dmax, p.max_depth);
+        bp.any_gi = bp.any_gi || (p.flags & RT_FLAG_GI);
         bp.stack_max = std::max(bp.stack_max, h.stack_size);
         max_lights = std::max(max_lights, h.n_lights);
     }
     const double qf = p0.queue_factor > 0.0f ? std::max(1.0f, p0.queue_factor) : 2.0;
-    const double qcap = std::ceil((double)rays * qf), scap = qcap * max_lights;
+    const double qcap = std::ceil((double)rays * qf);
+    // scenes in path tracing need room for a shadow ray per light at every depth of every path
+    const double scap = std::max(qcap * max_lights, bp.any_gi ? (double)rays * (bp.dmax + 1) * max_lights : 0.0);
     if (rays >= (1ull << 32) || acc >= (1ull << 32) || qcap > 4.0e9 || scap > 4.0e9) {
         why = "batch too large for one wavefront (more than 2^32 rays or queue entries)";
         return false;
@@ -1786,8 +1855,12 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
         }
         {
             KernelTimer kt(B.time_kernels, st, 1);
-            hipLaunchKernelGGL(k_shade<true>, dim3(B.shade_blocks), dim3(256), 0, st, none, c0, tab, qi, hq, ctr, k,
-                               qo, sq, acc);
+            if (B.pl.any_gi)
+                hipLaunchKernelGGL((k_shade<true, true>), dim3(B.shade_blocks), dim3(256), 0, st, none, c0, tab, qi, hq,
+                                   ctr, k, qo, sq, acc);
+            else
+                hipLaunchKernelGGL((k_shade<true, false>), dim3(B.shade_blocks), dim3(256), 0, st, none, c0, tab, qi,
+                                   hq, ctr, k, qo, sq, acc);
         }
     }
     {   // the deferred shadow rays of every scene and depth
@@ -2015,8 +2088,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         }
         {
             KernelTimer kt(A.time_kernels, st, 1);
-            hipLaunchKernelGGL(k_shade<false>, dim3(A.shade_blocks), dim3(256), 0, st, A.sc, shc, nullptr, qi, h, c_, k,
-                               qo, sh, acc_);
+            hipLaunchKernelGGL((k_shade<false, false>), dim3(A.shade_blocks), dim3(256), 0, st, A.sc, shc, nullptr, qi,
+                               h, c_, k, qo, sh, acc_);
         }
     };
     // the deferred shadow queue of a chain, binned and traced once
@@ -2243,6 +2316,7 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
     A.shc.acc_off = 0;
     A.shc.out_ids = out_hit_ids;
+    A.shc.gi = (p.flags & RT_FLAG_GI) ? 1 : 0;
     defer_and_bin_shadows(A, scene->h);
     A.pl = pl;
     A.ws = static_cast<uint8_t*>(p.workspace);
@@ -2411,6 +2485,10 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     std::string why;
     if (!make_cache_plan(h, *cam, p, cache, C.cp, why)) {
         set_error("rt_render_cached: " + why);
+        return RT_ERR_INVALID_ARG;
+    }
+    if (p.flags & RT_FLAG_GI) {
+        set_error("rt_render_cached: RT_FLAG_GI is not supported by the learned form");
         return RT_ERR_INVALID_ARG;
     }
     if (C.cp.c.depth > p.max_depth) {

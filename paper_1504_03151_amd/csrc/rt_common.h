@@ -507,4 +507,18 @@ HD double jitter01(uint64_t seed, uint32_t frame, uint32_t pixel, uint32_t s, ui
     return (double)(h >> 8) * (1.0 / 16777216.0);
 }
 
+// Random number k of the path bounce at `depth` of sample s of a pixel (global
+// illumination): the jitter chain through the pixel, then the sample, then a
+// word with the top bit set (no jitter word has it) holding depth and k.
+// 24 bits, exact as a float.
+HD float path_rand(uint64_t seed, uint32_t frame, uint32_t pixel, uint32_t s, uint32_t depth, uint32_t k) {
+    uint32_t h = pcg_hash((uint32_t)seed);
+    h = pcg_hash(h ^ (uint32_t)(seed >> 32));
+    h = pcg_hash(h ^ frame);
+    h = pcg_hash(h ^ pixel);
+    h = pcg_hash(h ^ s);
+    h = pcg_hash(h ^ (0x80000000u | (depth << 2) | k));
+    return (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
 }  // namespace mirt

@@ -23,6 +23,7 @@ RT_ERR = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP", -4: "BVH_DEPTH", -5: 
           -6: "DEVICE_STATUS", -7: "NOT_UPLOADED"}
 FLAG_SYNC, FLAG_COUNT_WORK, FLAG_NO_GRAPH, FLAG_TIME_KERNELS, FLAG_PER_SAMPLE = 1, 2, 4, 8, 16
 FLAG_ACCUMULATE = 32
+FLAG_GI = 64            # diffuse global illumination by path tracing (set from Params.gi)
 STATS_MAX_DEPTH = 16
 
 
@@ -272,7 +273,7 @@ def params_c(p, flags=0, samples_per_pass=0, queue_factor=0.0, queue_chunk=0, ti
     q.bg[:] = [float(x) for x in p.bg]
     q.eps = float(p.eps)
     q.samples_per_pass = int(samples_per_pass)
-    q.flags = int(flags)
+    q.flags = int(flags) | (FLAG_GI if getattr(p, "gi", 0) else 0)
     q.queue_factor = float(queue_factor)
     q.queue_chunk = int(queue_chunk)
     q.tile = int(tile)
@@ -384,7 +385,7 @@ class BatchRenderer:
         if not self.graph:
             flags |= FLAG_NO_GRAPH
         p0 = self._params[0]
-        p0.flags = flags | self.base_flags
+        p0.flags = flags | self.base_flags | (FLAG_GI if getattr(self.params[0], "gi", 0) else 0)
         p0.workspace, p0.workspace_bytes = self.ws.data_ptr(), self.ws_bytes
         p0.stats = self.stats.data_ptr()
         p0.stream = _stream_ptr(stream)

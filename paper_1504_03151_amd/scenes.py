@@ -427,4 +427,25 @@ def config4(seed: int = 2, **kw) -> Workload:
     return w
 
 
-WORKLOADS = {"c0": config0, "c1": config1, "c2": config2, "c4": config4}
+def config_gi(seed: int = 2, max_depth: int = 6, **kw) -> Workload:
+    """Diffuse global illumination at path depth 6 (the depth of the paper's global-illumination image): the
+    c2 scene, camera, lights and samples inside a closed room of six Lambert walls (x = +-80, y = +-80,
+    z = -160 and 80; grey, one red and one green side wall), so that no path escapes before its last bounce."""
+    w = config2(seed, **kw)
+    sc = w.scene
+    n_mat = len(sc.materials)
+    walls = np.stack([material((0.75, 0.25, 0.25), k_a=0.05, k_d=1.0, k_s=0.0),
+                      material((0.25, 0.75, 0.25), k_a=0.05, k_d=1.0, k_s=0.0),
+                      material((0.75, 0.75, 0.75), k_a=0.05, k_d=1.0, k_s=0.0)])
+    planes = [[1.0, 0.0, 0.0, -80.0], [1.0, 0.0, 0.0, 80.0], [0.0, 1.0, 0.0, -80.0], [0.0, 1.0, 0.0, 80.0],
+              [0.0, 0.0, 1.0, -160.0], [0.0, 0.0, 1.0, 80.0]]
+    plane_mat = [n_mat, n_mat + 1, n_mat + 2, n_mat + 2, n_mat + 2, n_mat + 2]
+    scene = make_scene(tris=sc.tris, tri_mat=sc.tri_mat, planes=planes, plane_mat=plane_mat,
+                       materials=np.concatenate([sc.materials, walls]), lights=sc.lights, name="gi_room_icospheres")
+    p = w.params
+    p.gi, p.max_depth = 1, max_depth
+    cam = w.camera
+    return Workload(scene, cam, p, f"gi_room_icospheres_{cam.width}x{cam.height}x{p.spp}spp_depth{max_depth}")
+
+
+WORKLOADS = {"c0": config0, "c1": config1, "c2": config2, "c4": config4, "gi": config_gi}
