@@ -87,7 +87,7 @@ def lib():
                                           C.c_int64]
             L.or_radiance.restype = C.c_int
             L.or_radiance.argtypes = [C.POINTER(_Scene), C.POINTER(_Params), C.c_void_p, C.c_int64, C.c_int32,
-                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+                                      C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
             L.or_light_point.restype = None
             L.or_light_point.argtypes = [C.c_void_p, C.c_uint64, C.c_uint32, C.c_int32, C.c_int32, C.c_void_p]
             L.or_pcg.restype = C.c_uint32
@@ -290,17 +290,19 @@ def render_cache(scene, camera, params, cache_depth: int, pixels=None, nthreads:
     return dict(rgb=rgb, margin=margin, records=rec[:m].copy(), pixels=pixels)
 
 
-def radiance(scene, params, o, d, start_depth: int, so=0.0, sd=0.0, nthreads: int = 0, sample: int = 0):
+def radiance(scene, params, o, d, start_depth: int, so=0.0, sd=0.0, nthreads: int = 0, sample: int = 0,
+             pixels=None):
     """Radiance of rays starting at recursion depth start_depth: (L [n,3], margin [n]); area lights take their
-    points of pass `sample`."""
+    points of pass `sample`; with global illumination ray i's path is keyed by pixels[i] (default: i)."""
     Lb = lib()
     R = _rays9(o, d, None, so, sd)
     n = len(R)
     out = np.zeros((n, 3), np.float64)
     m = np.zeros(n, np.float64)
     sc, p = OScene(scene), _params(params)
+    px = None if pixels is None else np.ascontiguousarray(pixels, np.int64).reshape(n)
     rc = Lb.or_radiance(C.byref(sc.c), C.byref(p), R.ctypes.data, n, int(start_depth), int(sample), nthreads,
-                        out.ctypes.data, m.ctypes.data)
+                        out.ctypes.data, m.ctypes.data, None if px is None else px.ctypes.data)
     if rc != 0:
         raise ValueError(f"or_radiance failed ({rc})")
     return out, m

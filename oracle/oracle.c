@@ -1180,13 +1180,15 @@ static void radiance_one(void* vctx, int64_t i) {
 
 /* Radiance L(ray) of n rays that start at recursion depth start_depth (so
  * secondary rays spawn while depth < max_depth): the training targets of the
- * learned form.  rays [n][9] as or_closest; L [n][3]; margin [n]. */
+ * learned form.  rays [n][9] as or_closest; L [n][3]; margin [n].  With global
+ * illumination the path of ray i draws its random numbers with the pixel key
+ * pixels[i] (NULL: i) and the given sample. */
 int or_radiance(const or_scene* sc, const or_params* p, const double* rays, int64_t n, int32_t start_depth,
-                int32_t sample, int32_t nthreads, double* L, double* margin) {
+                int32_t sample, int32_t nthreads, double* L, double* margin, const int64_t* pixels) {
     if (p->max_depth < 0 || p->max_depth > 63 || start_depth < 0 || start_depth > p->max_depth) return -1;
     oscene S;
     if (oscene_init(&S, sc) != 0) return -2;
-    radiance_job J = {&S, p, rays, start_depth, L, margin, sample, NULL};
+    radiance_job J = {&S, p, rays, start_depth, L, margin, sample, pixels};
     run_parallel(n, nthreads, radiance_one, &J);
     oscene_free(&S);
     return 0;

@@ -157,3 +157,35 @@ def test_path_random_numbers_are_uniform_and_keyed():
     for args in ((1, 2, 5, 3, 4, 1), (1, 2, 5, 3, 5, 0), (1, 2, 5, 4, 4, 0), (1, 3, 5, 3, 4, 0), (2, 2, 5, 3, 4, 0)):
         assert oracle.path_rand(*args) != base
     assert oracle.path_rand(1, 2, 5, 3, 4, 0) != oracle.jitter(1, 2, 5, 3, 0)
+
+
+def test_cut_off_plus_keyed_depth2_paths_is_the_full_path_traced_render():
+    """A path is linear in what its depth-2 ray returns: the image cut off at depth 2 plus, for every depth-2
+    hit, its path weight times the radiance of a path restarted there with the same pixel key (and sample)
+    equals the full path-traced image.  Pins the cut-off and the keying of the learned form's targets."""
+    w = S.random_tiny(11, size=40, depth=5)
+    w.camera.height = 37
+    w.params.gi = 1
+    assert w.params.spp == 1
+    full = oracle.render(w.scene, w.camera, w.params)
+    cut = oracle.render_cache(w.scene, w.camera, w.params, 2)
+    rec = cut["records"]
+    assert len(rec) > 30
+    x, v, wt = rec[:, 1:4], rec[:, 7:10], rec[:, 10:13]
+    d = -v
+    idx = rec[:, 0].astype(int)
+    L, m = oracle.radiance(w.scene, w.params, x - 1e-2 * d, d, 2, pixels=idx, sample=0)
+    recon = cut["rgb"].copy()
+    np.add.at(recon, idx, wt * L)
+    ok = (full["margin"] > 1e-4) & (cut["margin"] > 1e-4)
+    bad = np.zeros(len(ok), bool)
+    bad[idx[m <= 1e-4]] = True
+    ok &= ~bad
+    assert ok.mean() > 0.9
+    np.testing.assert_allclose(recon[ok], full["rgb"][ok], rtol=0, atol=1e-9)
+    touched = np.zeros(len(ok), bool)
+    touched[idx] = True
+    assert (np.abs(full["rgb"] - cut["rgb"]).max(axis=1)[ok & touched] > 1e-6).sum() > 20
+    # another key draws another continuation
+    L2, _ = oracle.radiance(w.scene, w.params, x - 1e-2 * d, d, 2, pixels=idx + 1, sample=0)
+    assert np.abs(L2 - L).max() > 1e-3
