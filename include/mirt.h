@@ -141,8 +141,9 @@ enum {
                                  weight, and weighted by weight / probability.  Random numbers: the PCG hash
                                  chain of the camera jitter through (seed, frame, pixel), then the sample,
                                  then the word 0x80000000 | depth << 2 | k (k = 0 branch, 1 and 2 the
-                                 direction); 24 bits each.  Not supported by rt_render_cached
-                                 (RT_ERR_INVALID_ARG). */
+                                 direction); 24 bits each.  rt_render_cached: the image's paths
+                                 end at the cache depth; the training targets are paths from the
+                                 selected queries keyed by (training index, sample 0). */
 };
 
 enum { RT_TILE_8X8 = 0, RT_TILE_16X4 = 1, RT_TILE_32X2 = 2, RT_TILE_4X16 = 3 };

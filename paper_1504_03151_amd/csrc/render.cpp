@@ -2003,6 +2003,8 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
         if (!(c.bounds_hi[k] > c.bounds_lo[k])) c.bounds_hi[k] = c.bounds_lo[k] + 1.0f;
     rt_params q = p;
     q.samples_per_pass = p.spp;   // cache frames trace every sample in one pass
+    // path tracing: the image's paths are shaded only above the cache depth, which bounds their shadow rays
+    if (p.flags & RT_FLAG_GI) q.max_depth = std::max(0, std::min(p.max_depth, c.depth - 1));
     if (!make_plan(h, cam, q, cp.base, why)) return false;
     cp.c = c;
     if (!cache_layout(c.train_samples, cp.L)) {
@@ -2013,6 +2015,11 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
     cp.rec_cap = pl.qcap;
     cp.tcap = (uint32_t)std::min<uint64_t>(4000000000ull, (uint64_t)c.train_samples * kTargetGrowth);
     cp.tscap = (uint32_t)std::min<uint64_t>(4000000000ull, (uint64_t)cp.tcap * std::max(1, h.n_lights));
+    if (p.flags & RT_FLAG_GI) {   // target paths: one ray per depth, a shadow ray per light at each of their hits
+        cp.tcap = (uint32_t)c.train_samples;
+        cp.tscap = (uint32_t)std::min<uint64_t>(
+            4000000000ull, (uint64_t)c.train_samples * (c.full_depth - c.depth + 1) * std::max(1, h.n_lights));
+    }
     size_t off = pl.total;
     cp.off_rec = off;
     off = a256(off + (size_t)cp.rec_cap * (128 + 4 + 12 + 4) + 4 * 256);
@@ -2088,8 +2095,12 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         }
         {
             KernelTimer kt(A.time_kernels, st, 1);
-            hipLaunchKernelGGL((k_shade<false, false>), dim3(A.shade_blocks), dim3(256), 0, st, A.sc, shc, nullptr, qi,
-                               h, c_, k, qo, sh, acc_);
+            if (shc.gi)
+                hipLaunchKernelGGL((k_shade<false, true>), dim3(A.shade_blocks), dim3(256), 0, st, A.sc, shc, nullptr,
+                                   qi, h, c_, k, qo, sh, acc_);
+            else
+                hipLaunchKernelGGL((k_shade<false, false>), dim3(A.shade_blocks), dim3(256), 0, st, A.sc, shc, nullptr,
+                                   qi, h, c_, k, qo, sh, acc_);
         }
     };
     // the deferred shadow queue of a chain, binned and traced once
@@ -2487,10 +2498,6 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
         set_error("rt_render_cached: " + why);
         return RT_ERR_INVALID_ARG;
     }
-    if (p.flags & RT_FLAG_GI) {
-        set_error("rt_render_cached: RT_FLAG_GI is not supported by the learned form");
-        return RT_ERR_INVALID_ARG;
-    }
     if (C.cp.c.depth > p.max_depth) {
         set_error("rt_render_cached: cache depth must not exceed max_depth");
         return RT_ERR_INVALID_ARG;
@@ -2519,6 +2526,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     A.shc.per_sample = (p.flags & RT_FLAG_PER_SAMPLE) ? 1 : 0;
     A.shc.acc_off = 0;
     A.shc.out_ids = out_hit_ids;
+    A.shc.gi = (p.flags & RT_FLAG_GI) ? 1 : 0;
     defer_and_bin_shadows(A, scene->h);
     A.pl = C.cp.base;
     A.ws = static_cast<uint8_t*>(p.workspace);
@@ -2538,6 +2546,9 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + A.pl.off_ctr + 4 * kCtrFrame), (int)p.frame, 1,
                               st));
     HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + A.pl.off_ctr + 4 * kCtrAccum), 0, 1, st));
+    // the target paths' counters carry the frame number too (it keys their random numbers)
+    HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + C.cp.off_tctr + 4 * kCtrFrame), (int)p.frame, 1,
+                              st));
     const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
     rs = launch_cached(C, st, graph, h.uid);
     if (rs != RT_OK) return rs;

@@ -143,13 +143,77 @@ def test_batch_with_some_scenes_in_gi_equals_single_frames(rt):
         assert err[rob].max() <= RGB_TOL
 
 
-def test_learned_form_rejects_gi(rt):
-    w = _gi(S.random_tiny(1, size=16, depth=4))
+def _tiny_room(seed, size=40, depth=5):
+    """A tiny mixed scene closed by six grey Lambert walls: paths keep bouncing until their last depth."""
+    w = S.random_tiny(seed, size=size, depth=depth)
+    sc = w.scene
+    planes = [[0.0, 1.0, 0.0, -4.0], [0.0, 1.0, 0.0, 10.0], [1.0, 0.0, 0.0, -8.0], [1.0, 0.0, 0.0, 8.0],
+              [0.0, 0.0, 1.0, -14.0], [0.0, 0.0, 1.0, 8.0]]
+    w.scene = S.make_scene(spheres=sc.spheres, sphere_mat=sc.sphere_mat, tris=sc.tris, tri_mat=sc.tri_mat,
+                           planes=planes, plane_mat=[3] * 6, materials=sc.materials, lights=sc.lights,
+                           name=f"tiny_room_{seed}")
+    w.params.gi = 1
+    return w
+
+
+def test_learned_form_with_gi_matches_the_oracle(rt):
+    """Paths cut at depth 2: the GPU frame is the oracle's cut-off path-traced render plus the path weight
+    times max(network, 0) of each depth-2 hit (fixed weights), on robust pixels."""
+    from oracle import mlp as M
+    w = _tiny_room(11)
+    w.camera.height = 37
     sc = rt.Scene(w.scene).upload()
-    cache = rt.RadianceCache(S.mlp_init_weights(0), capacity=1024)
-    r = rt.CachedRenderer(sc, w.camera, w.params, cache, full_depth=4)
-    with pytest.raises(rt.RTError):
-        r.render(rt.FLAG_SYNC)
+    bounds = (np.array(sc.info["bounds_lo"]) - 1.0, np.array(sc.info["bounds_hi"]) + 1.0)
+    ws = S.mlp_init_weights(7)
+    ws[5] = np.abs(ws[5])
+    cache = rt.RadianceCache(ws, capacity=4096)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_INFER, depth=2, full_depth=5, bounds=bounds)
+    rgb, ids = r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    st = r.read_stats()
+    assert st["status"] == 0 and st["rays"][3] == 0
+    ref = oracle.render_cache(w.scene, w.camera, w.params, 2)
+    rec = ref["records"]
+    assert len(rec) > 500
+    feats = M.encode(rec[:, 1:4], rec[:, 4:7], rec[:, 7:10], bounds[0].astype(np.float32),
+                     bounds[1].astype(np.float32))
+    y, _ = M.forward(ws, feats)
+    term = rec[:, 10:13] * np.maximum(y, 0.0)
+    img = ref["rgb"].copy()
+    mag = np.zeros_like(img)
+    np.add.at(img, rec[:, 0].astype(int), term)
+    np.add.at(mag, rec[:, 0].astype(int), np.abs(term))
+    rob = ref["margin"] > ROBUST
+    assert rob.mean() > 0.9
+    err = np.abs(rgb.reshape(-1, 3).double().cpu().numpy() - img)
+    tol = 1e-3 + 3e-2 * mag
+    assert (err[rob] <= tol[rob]).all(), (err - tol)[rob].max()
+    assert (mag[rob] > 1e-3).sum() > 300
+
+
+def test_learned_form_targets_with_gi_are_keyed_paths(rt):
+    """Training targets: the path traced from each selected depth-2 ray, keyed by its training index (sample 0)
+    and the frame, equals the oracle's radiance of the same ray with the same key."""
+    w = _tiny_room(11)
+    w.params.frame = 3
+    sc = rt.Scene(w.scene).upload()
+    cache = rt.RadianceCache(S.mlp_init_weights(3), capacity=2048)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2, full_depth=5,
+                          train_samples=2048, train_steps=2)
+    r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert r.read_stats()["status"] == 0
+    c = cache.counters()
+    assert c["steps"] == 2 and c["n_train"] == 40 * 40      # every path of the closed room reaches depth 2
+    rays, feats, targets, pix = [t.cpu().numpy() for t in cache.training_batch()]
+    idx = np.arange(0, c["n_train"], 4)
+    o, d = rays[idx, :3].astype(np.float64), rays[idx, 3:6].astype(np.float64)
+    L, m = oracle.radiance(w.scene, w.params, o, d, 2, so=float(np.abs(o).max()) * 4e-7, sd=4e-7, pixels=idx,
+                           sample=0)
+    rob = m > ROBUST
+    assert rob.mean() > 0.8, rob.mean()
+    np.testing.assert_allclose(targets[idx][rob], L[rob], atol=1e-3, rtol=0)
+    assert np.abs(L[rob]).max() > 0.05
 
 
 def test_gi_room_full_frame_sampled(rt):
