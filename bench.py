@@ -250,11 +250,13 @@ MLP_TRAIN_FLOP = MLP_FWD_FLOP + MLP_FWD_FLOP + 2 * (4 * 64 * 64 + 64 * 3)  # for
 
 
 def bench_cache(w, sc, plain, args):
-    """Learned form vs the plain depth-8 frame on the same scene, camera, samples and frame numbers.
+    """Learned form vs the plain full-depth frame on the same scene, camera, samples and frame numbers.
 
-    32 frames of online training (65,536 samples, 4 Adam steps each) warm the network up; the next 16 frames
-    are timed (training included) beside plain depth-8 frames of the same frame numbers, which are the judge
-    of the relative MSE.  Depth-2 truncation (the network replaced by zero) shows what the network gains.
+    32 frames of online training (65,536 samples, 4 Adam steps each; 96 for path-traced frames) warm the
+    network up; the next 16 frames are timed (training included) beside plain frames of the same frame
+    numbers, which are the judge of the relative MSE for Whitted frames; path-traced frames are judged
+    against a converged mean of plain frames.  Depth-2 truncation (the network replaced by zero) shows what
+    the network gains.
     """
     import numpy as np
     import torch
@@ -266,12 +268,13 @@ def bench_cache(w, sc, plain, args):
                            queue_chunk=plain.queue_chunk, tile=plain.tile, with_ids=False)
     log(f"cache workspace {cr.ws_bytes / 2 ** 30:.2f} GiB")
     f0 = 1000
-    for f in range(args.cache_warmup):
+    warm = args.cache_warmup if args.cache_warmup is not None else (96 if w.params.gi else 32)
+    for f in range(warm):
         w.params.frame = f0 + f
         cr.render()
     torch.cuda.synchronize()
     c = cache.counters()
-    log(f"cache warm-up: {args.cache_warmup} frames, {c['steps']} Adam steps, last loss "
+    log(f"cache warm-up: {warm} frames, {c['steps']} Adam steps, last loss "
         f"{float(c['loss_sums'][:4].sum()) / (3 * max(1, c['n_train'])):.4f}")
 
     def rel_mse(x, ref, mask=None):
@@ -306,7 +309,7 @@ def bench_cache(w, sc, plain, args):
     kt_c = {}
     kt_p = {}
     for f in range(args.cache_frames):
-        w.params.frame = f0 + args.cache_warmup + f
+        w.params.frame = f0 + warm + f
         ms_c, kc, st_c, img_c = timed(cr)
         assert st_c["status"] == 0, st_c
         img_c = img_c.clone()
@@ -351,7 +354,7 @@ def bench_cache(w, sc, plain, args):
         "mrays_per_s": round((mean("rays") + mean("target_rays")) / (ms_c / 1e3) / 1e6, 1),
         "rays_per_frame": int(mean("rays")), "target_rays_per_frame": int(mean("target_rays")),
         "plain_rays_per_frame": int(mean("plain_rays")), "queries_per_frame": int(q),
-        "warmup_frames": args.cache_warmup, "frames": n, "train_samples": 65536, "train_steps": 4, "lr": 1e-3,
+        "warmup_frames": warm, "frames": n, "train_samples": 65536, "train_steps": 4, "lr": 1e-3,
         "kernel_ms_per_frame": {k: round(v[0] / n, 3) for k, v in kt_c.items()},
         "plain_kernel_ms_per_frame": {k: round(v[0] / n, 3) for k, v in kt_p.items()},
         "mlp_roofline": {"bound": "mfma", "kernel": "k_mlp_forward<1> (inference)",
@@ -393,7 +396,9 @@ def main():
                                                            "with --layout and --queue-chunk: no tuning")
     ap.add_argument("--layout", type=int, default=None, help="BVH node layout (0 depth-first, 1 breadth-first, "
                                                              "2 treelets)")
-    ap.add_argument("--cache-warmup", type=int, default=32, help="online-training frames before measuring")
+    ap.add_argument("--cache-warmup", type=int, default=None,
+                    help="online-training frames before measuring (default 32; 96 for path-traced frames, whose "
+                         "targets are single noisy paths)")
     ap.add_argument("--cache-frames", type=int, default=16, help="measured learned-form frames")
     ap.add_argument("--gi-ref-frames", type=int, default=8,
                     help="plain path-traced frames averaged into the reference of the learned form (workload gi)")
