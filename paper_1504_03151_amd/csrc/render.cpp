@@ -68,7 +68,18 @@ constexpr int kCtrWords = 128;     // words cleared at the start of every pass
 constexpr int kCtrFrame = 128;     // frame number, written by the host before each launch
 constexpr int kCtrAccum = 130;     // frames already in the accumulator (progressive mode), written likewise
 constexpr int kCtrRec = 129;       // learned form: cache queries recorded this frame (cleared per frame)
-constexpr int kCtrTotal = 256;
+// XCD-aware fetching: each fetch cursor above (kCtrRayCur .. kCtrShadowAllCur) is backed by kXcd segment
+// cursors, kXcdStride words apart, in the block at kCtrXcd (cleared with the counters).
+constexpr int kXcd = 8;            // XCDs of the chip; workgroups are dispatched to them round-robin
+constexpr int kXcdStride = 16;
+constexpr int kCtrXcd = 256;
+constexpr int kCurSlots = kCtrShadowAllCur - kCtrRayCur + 1;
+constexpr int kCtrTotal = kCtrXcd + kCurSlots * kXcd * kXcdStride;
+
+// the segment cursors of fetch cursor c (one of kCtrRayCur + k, kCtrShadowCur + k, kCtrShadowAllCur)
+__host__ __device__ inline uint32_t* xcd_cursor(uint32_t* ctr, int c) {
+    return ctr + kCtrXcd + (c - kCtrRayCur) * kXcd * kXcdStride;
+}
 
 struct CamConst {
     double eye[3], f[3], r[3], u[3];
@@ -251,6 +262,13 @@ __global__ void k_fill_f32(float* p, int64_t n, float v) {
     if (i < n) p[i] = v;
 }
 
+// Clear a pass's counters and the XCD segment cursors of its fetch cursors.
+static void clear_counters(uint32_t* ctr, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+    constexpr int n = kCtrTotal - kCtrXcd;
+    hipLaunchKernelGGL(k_zero_u32, dim3((n + 255) / 256), dim3(256), 0, st, ctr + kCtrXcd, n);
+}
+
 // Ray slots of a pass map 1:1 to threads: a wave covers one 64-pixel tile
 // (8x8, 16x4, 32x2 or 4x16) of one sample, so primary rays of a wave are
 // coherent and no atomic is needed.
@@ -350,6 +368,36 @@ __global__ __launch_bounds__(256) void k_raygen_batch(const BatchScene* tab, int
 // Persistent traversal kernels: each wave takes `chunk` consecutive queue
 // entries per atomic on the fetch cursor (a multiple of 64) and traces them 64
 // at a time until the queue is drained.
+// XCD-aware queue fetch.  The queue [0, count) is cut into kXcd contiguous
+// segments; a wave takes `chunk` entries at a time from the segment of its own
+// XCD (blockIdx modulo kXcd), so each XCD's L2 serves rays that are adjacent in
+// the queue (neighbouring pixels, or one shadow bin), then helps the other
+// segments in turn until all are drained.  Wave-uniform.
+struct QueueFetch {
+    uint32_t* cur;   // kXcd segment cursors, kXcdStride words apart
+    uint32_t count, chunk;
+    int x, left;
+    __device__ QueueFetch(uint32_t* c, uint32_t n, uint32_t ch)
+        : cur(c), count(n), chunk(ch), x((int)(blockIdx.x % kXcd)), left(kXcd) {}
+    __device__ bool next(uint32_t& base, uint32_t& end) {
+        while (left > 0) {
+            const uint32_t lo = (uint32_t)((uint64_t)count * x / kXcd);
+            const uint32_t hi = (uint32_t)((uint64_t)count * (x + 1) / kXcd);
+            uint32_t b = 0;
+            if (lane_id() == 0) b = lo < hi ? atomicAdd(cur + kXcdStride * x, chunk) : hi - lo;
+            b = __shfl(b, 0, 64);
+            if (b < hi - lo) {
+                base = lo + b;
+                end = min(base + chunk, hi);
+                return true;
+            }
+            x = x + 1 == kXcd ? 0 : x + 1;
+            --left;
+        }
+        return false;
+    }
+};
+
 template <bool COUNT, bool BATCH>
 __global__ __launch_bounds__(256) void k_extend(DevScene sc, const BatchScene* tab, RayQ q, HitQ hit,
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
@@ -358,12 +406,9 @@ __global__ __launch_bounds__(256) void k_extend(DevScene sc, const BatchScene* t
     SplitStack stk = split_stack(smem, overflow);
     const uint32_t count = min(*count_p, cap);   // a producer that overflowed still bumped the tail
     Work w{0, 0, 0};
-    for (;;) {
-        uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(cursor, chunk);
-        base = __shfl(base, 0, 64);
-        if (base >= count) break;
-        const uint32_t end = min(base + chunk, count);
+    QueueFetch f(cursor, count, chunk);
+    uint32_t base, end;
+    while (f.next(base, end)) {
         for (uint32_t b = base; b < end; b += 64) {
             const uint32_t i = b + lane_id();
             if (i < end) {
@@ -397,12 +442,9 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* t
     const uint32_t begin = begin_p ? min(*begin_p, end_all) : 0u;
     const uint32_t count = end_all - begin;
     Work w{0, 0, 0};
-    for (;;) {
-        uint32_t base = 0;
-        if (lane_id() == 0) base = atomicAdd(cursor, chunk);
-        base = __shfl(base, 0, 64);
-        if (base >= count) break;
-        const uint32_t end = min(base + chunk, count);
+    QueueFetch f(cursor, count, chunk);
+    uint32_t base, end;
+    while (f.next(base, end)) {
         for (uint32_t b = base; b < end; b += 64) {
             const uint32_t j = b + lane_id();
             if (j < end) {
@@ -1517,7 +1559,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     seg.begin_p = nullptr;
     seg.cap = pl.scap;
     seg.end_p = ctr + kCtrShadowAll;
-    seg.cursor = ctr + kCtrShadowAllCur;
+    seg.cursor = xcd_cursor(ctr, kCtrShadowAllCur);
     seg.perm = A.bin_shadows ? reinterpret_cast<uint32_t*>(A.ws + pl.off_s2 + stride) : nullptr;
     seg.bins = bins;
     seg.overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack + pl.stack_bytes);
@@ -1533,7 +1575,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     for (int pass = 0; pass < pl.passes; ++pass) {
         const int s0 = pass * pl.spp_pass;
         const int ns = std::min(pl.spp_pass, A.spp - s0);
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+        clear_counters(ctr, st);
         const uint32_t nthreads = (uint32_t)((int64_t)tiles_x * tiles_y * ns * 64);
         hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, s0, ns, tiles_x,
                            nthreads, q[0], ctr, pl.qcap, A.shc.per_sample);
@@ -1544,10 +1586,12 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
                 KernelTimer kt(A.time_kernels, st, 0);
                 if (A.count_work)
                     hipLaunchKernelGGL((k_extend<true, false>), dim3(gx), dim3(256), A.lds, st, A.sc, nullptr, qi, hq,
-                                       ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
+                                       ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk,
+                                       overflow, work);
                 else
                     hipLaunchKernelGGL((k_extend<false, false>), dim3(gx), dim3(256), A.lds, st, A.sc, nullptr, qi,
-                                       hq, ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, A.chunk, overflow, work);
+                                       hq, ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk,
+                                       overflow, work);
             }
             {
                 KernelTimer kt(A.time_kernels, st, 1);
@@ -1836,7 +1880,7 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
     c0.scap = pl.scap;
     const uint64_t n3 = 3 * pl.n_acc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, (int64_t)n3, 0.0f);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+    clear_counters(ctr, st);
     if (pl.n_lpts)
         hipLaunchKernelGGL(k_light_points_batch, dim3((pl.n_lpts + 255) / 256), dim3(256), 0, st, tab, pl.n, pl.n_lpts);
     hipLaunchKernelGGL(k_raygen_batch, dim3((pl.n_rays + 255) / 256), dim3(256), 0, st, tab, pl.n, pl.n_rays, q[0], ctr,
@@ -1848,10 +1892,12 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
             KernelTimer kt(B.time_kernels, st, 0);
             if (B.count_work)
                 hipLaunchKernelGGL((k_extend<true, true>), dim3(B.gx), dim3(256), 0, st, none, tab, qi, hq,
-                                   ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, B.chunk, overflow, work);
+                                   ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, B.chunk, overflow,
+                                   work);
             else
                 hipLaunchKernelGGL((k_extend<false, true>), dim3(B.gx), dim3(256), 0, st, none, tab, qi, hq,
-                                   ctr + kCtrRays + k, ctr + kCtrRayCur + k, pl.qcap, B.chunk, overflow, work);
+                                   ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, B.chunk, overflow,
+                                   work);
         }
         {
             KernelTimer kt(B.time_kernels, st, 1);
@@ -1867,10 +1913,12 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
         KernelTimer kt(B.time_kernels, st, 2);
         if (B.count_work)
             hipLaunchKernelGGL((k_shadow<true, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
-                               ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, B.chunk, acc, overflow, swork);
+                               ctr + kCtrShadowAll, xcd_cursor(ctr, kCtrShadowAllCur), pl.scap, B.chunk, acc,
+                               overflow, swork);
         else
             hipLaunchKernelGGL((k_shadow<false, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
-                               ctr + kCtrShadowAll, ctr + kCtrShadowAllCur, pl.scap, B.chunk, acc, overflow, swork);
+                               ctr + kCtrShadowAll, xcd_cursor(ctr, kCtrShadowAllCur), pl.scap, B.chunk, acc,
+                               overflow, swork);
     }
     hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, B.stats, pl.dmax, 0);
     hipLaunchKernelGGL(k_resolve_batch, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, tab, pl.n, acc, n3);
@@ -2088,10 +2136,12 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
             KernelTimer kt(A.time_kernels, st, 0);
             if (A.count_work)
                 hipLaunchKernelGGL((k_extend<true, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, qi, h,
-                                   c_ + kCtrRays + k, c_ + kCtrRayCur + k, shc.qcap, A.chunk, overflow, work);
+                                   c_ + kCtrRays + k, xcd_cursor(c_, kCtrRayCur + k), shc.qcap, A.chunk, overflow,
+                                   work);
             else
                 hipLaunchKernelGGL((k_extend<false, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, qi, h,
-                                   c_ + kCtrRays + k, c_ + kCtrRayCur + k, shc.qcap, A.chunk, overflow, work);
+                                   c_ + kCtrRays + k, xcd_cursor(c_, kCtrRayCur + k), shc.qcap, A.chunk, overflow,
+                                   work);
         }
         {
             KernelTimer kt(A.time_kernels, st, 1);
@@ -2110,7 +2160,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         g.begin_p = nullptr;
         g.end_p = c_ + kCtrShadowAll;
         g.cap = cap;
-        g.cursor = c_ + kCtrShadowAllCur;
+        g.cursor = xcd_cursor(c_, kCtrShadowAllCur);
         g.perm = perm;
         g.bins = bins;
         g.overflow = overflow;
@@ -2122,7 +2172,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
 
     const int64_t n3 = 3 * pl.nacc;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, ctr, kCtrWords);
+    clear_counters(ctr, st);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ctr + kCtrRec, 1);
     if (A.shc.light_pts) {
         const int n = A.spp * A.sc.n_lights;
@@ -2140,7 +2190,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     {
         KernelTimer kt(A.time_kernels, st, 0);
         hipLaunchKernelGGL((k_extend<false, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, q[cd & 1], hq,
-                           ctr + kCtrRays + cd, ctr + kCtrRayCur + cd, pl.qcap, A.chunk, overflow, nullptr);
+                           ctr + kCtrRays + cd, xcd_cursor(ctr, kCtrRayCur + cd), pl.qcap, A.chunk, overflow,
+                           nullptr);
     }
     const float ie[3] = {1.0f / (cc.bounds_hi[0] - cc.bounds_lo[0]), 1.0f / (cc.bounds_hi[1] - cc.bounds_lo[1]),
                          1.0f / (cc.bounds_hi[2] - cc.bounds_lo[2])};
@@ -2163,7 +2214,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         uint16_t* t_feats = reinterpret_cast<uint16_t*>(S + L.train_feats);
         float* t_rays = reinterpret_cast<float*>(S + L.train_rays);
         const uint32_t T = (uint32_t)cc.train_samples;
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(kCtrWords), 0, st, tctr, kCtrWords);
+        clear_counters(tctr, st);
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, counters + 2, 16);
         hipLaunchKernelGGL(k_fill_f32, dim3((3 * T + 255) / 256), dim3(256), 0, st, targets, (int64_t)3 * T, 0.0f);
         hipLaunchKernelGGL(k_cache_select, dim3((T + 255) / 256), dim3(256), 0, st, ctr, rec, q[cd & 1], T, cd,
