@@ -663,12 +663,14 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
         atomicOr(ctr + kCtrStatus, 2u);
         return;
     }
-    V3 sd = lp - xs;
+    // The segment is traced from the light towards the offset surface point: the rays of one light in a
+    // wave then leave from one point and share their first node visits (occlusion is symmetric).
+    V3 sd = xs - lp;
     const float dist = sqrtf(dot(sd, sd));
     sd = sd * (1.0f / dist);
-    sq.ox[slot] = xs.x;
-    sq.oy[slot] = xs.y;
-    sq.oz[slot] = xs.z;
+    sq.ox[slot] = lp.x;
+    sq.oy[slot] = lp.y;
+    sq.oz[slot] = lp.z;
     sq.dx[slot] = sd.x;
     sq.dy[slot] = sd.y;
     sq.dz[slot] = sd.z;
