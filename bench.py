@@ -112,7 +112,10 @@ def traffic_record(kernel, workload, tile, layout, chunk):
         with open(f) as fh:
             for line in fh:
                 if line.startswith("traffic-record:"):
-                    rec = json.loads(line.split(":", 1)[1])
+                    try:
+                        rec = json.loads(line.split(":", 1)[1])
+                    except ValueError:
+                        continue
                     if all(rec.get(k) == v for k, v in want.items()):
                         return int(rec["bytes_per_launch"])
     return None
