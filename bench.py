@@ -374,6 +374,95 @@ def bench_cache(w, sc, plain, args):
     return out
 
 
+def bench_refit(args):
+    """Dynamic scene (f4): every icosphere of the c2 scene moves each frame and the BVH is refit on the GPU
+    (rt_scene_refit, same tree) instead of rebuilt on the host.  value = refit time per frame (HIP events around
+    the refit launches); beside it the host SAH build of the same scene, and the frame time through the refit
+    tree against a tree built for the final positions (the refit tree's quality loss)."""
+    import numpy as np
+    import torch
+    from paper_1504_03151_amd import rt, scenes
+    w = workload("c2")
+    layout = args.layout if args.layout is not None else rt.LAYOUT_BVH4Q
+    tile = args.tile or 0
+    chunk = args.queue_chunk or 128
+    t0 = time.perf_counter()
+    sc = rt.Scene(w.scene, node_layout=layout)
+    build_s = time.perf_counter() - t0
+    sc.upload()
+    n_obj = 1000
+    tris0 = torch.from_numpy(w.scene.tris.reshape(n_obj, -1, 9)).cuda()
+    rng = np.random.default_rng(9)
+    vel = torch.from_numpy(rng.uniform(-0.25, 0.25, (n_obj, 1, 3)).astype(np.float32)).cuda()
+    frames = max(args.steps, 1) * 4
+
+    def positions(f):
+        return (tris0 + (vel * f).repeat(1, 1, 3)).reshape(-1).contiguous()
+
+    for f in range(args.warmup + 1):
+        sc.refit(None, positions(f))
+    torch.cuda.synchronize()
+    ms = []
+    for f in range(1, frames + 1):
+        p = positions(f)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        sc.refit(None, p)
+        b.record()
+        torch.cuda.synchronize()
+        ms.append(a.elapsed_time(b))
+    refit_ms = float(np.median(ms))
+    # frames through the refit tree vs a tree built for the final positions
+    final = positions(frames).cpu().numpy().reshape(-1, 3, 3)
+    moved = scenes.make_scene(tris=final, tri_mat=w.scene.tri_mat, materials=w.scene.materials,
+                              lights=w.scene.lights)
+
+    def frame_ms(scene):
+        r = rt.Renderer(scene, w.camera, w.params, queue_chunk=chunk, tile=tile)
+        r.render(rt.FLAG_COUNT_WORK | rt.FLAG_SYNC | rt.FLAG_NO_GRAPH)
+        st = r.read_stats()
+        for _ in range(2):
+            r.render()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            r.render()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / args.steps, st["node_visits"] + st["shadow_node_visits"]
+
+    refit_frame_ms, refit_visits = frame_ms(sc)
+    t0 = time.perf_counter()
+    sm = rt.Scene(moved, node_layout=layout)
+    rebuild_s = time.perf_counter() - t0
+    sm.upload()
+    fresh_frame_ms, fresh_visits = frame_ms(sm)
+    # algorithmic bytes of one refit: positions read (36 B per triangle), primitive records read and written
+    # (2 x 48 B) and normals written (16 B), each node's box written (node bytes) plus its side box (24 B)
+    n_tri = len(w.scene.tris)
+    nb = rt.NODE_BYTES[layout]
+    algo = n_tri * (36 + 96 + 16) + sc.info["n_nodes"] * (nb + 24) + n_tri * 48
+    achieved = algo / (refit_ms / 1e3) / 1e9
+    log(f"refit {refit_ms:.3f} ms (host build {build_s:.2f} s); frame through refit tree {refit_frame_ms:.2f} ms "
+        f"vs rebuilt {fresh_frame_ms:.2f} ms; node visits {refit_visits} vs {fresh_visits}")
+    out = {
+        "metric": "ms per BVH refit on the GPU (c2 scene, 1.28M triangles, every object moving)",
+        "value": round(refit_ms, 4), "unit": "ms", "n_gpus": 1, "steps": frames, "warmup": args.warmup + 1,
+        "ms_per_step": round(refit_ms, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "c2_icospheres_moving", "triangles": n_tri, "node_layout": layout,
+                   "nodes": sc.info["n_nodes"], "frames": frames},
+        "host_build_seconds": round(build_s, 3), "host_rebuild_seconds": round(rebuild_s, 3),
+        "speedup_vs_host_build": round(build_s * 1e3 / refit_ms, 1),
+        "frame_ms_refit_tree": round(refit_frame_ms, 3), "frame_ms_rebuilt_tree": round(fresh_frame_ms, 3),
+        "node_visits_refit_tree": int(refit_visits), "node_visits_rebuilt_tree": int(fresh_visits),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "refit (all launches)",
+                     "bytes_per_refit": int(algo)},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -390,6 +479,8 @@ def main():
     ap.add_argument("--no-cache", action="store_true", help="skip the learned-form comparison")
     ap.add_argument("--progressive", action="store_true",
                     help="progressive passes with disk lights (radius --area-lights, default 2) instead of frames")
+    ap.add_argument("--refit", action="store_true",
+                    help="dynamic c2 scene: GPU BVH refit per frame vs the host build")
     ap.add_argument("--area-lights", type=float, default=0.0, metavar="R",
                     help="replace the point lights by disks of radius R facing the scene centre (sampled once per "
                          "light per pass)")
@@ -431,6 +522,8 @@ def main():
         return bench_batch(args)
     if args.progressive:
         return bench_progressive(args)
+    if args.refit:
+        return bench_refit(args)
     w = workload(args.workload, args.area_lights)
     log(f"workload {w.name}: {len(w.scene.spheres)} spheres, {len(w.scene.tris)} triangles, "
         f"{len(w.scene.planes)} planes, {len(w.scene.lights)} lights")

@@ -215,11 +215,34 @@ rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* out);
  * RT_ERR_INVALID_ARG (NULL scene, unknown layout), RT_ERR_BVH_DEPTH. */
 rt_status rt_scene_set_layout(rt_scene* scene, int32_t node_layout);
 
-/* Bytes of the device blob (nodes | primitives | normals | planes | materials | lights). */
+/* Bytes of the device blob (nodes | primitives | normals | planes | materials | lights | refit order). */
 size_t rt_scene_device_bytes(const rt_scene* scene);
 /* Copy the blob into caller-owned device memory dev_ptr (>= rt_scene_device_bytes)
  * on stream; the scene keeps dev_ptr, which must stay valid while it is used. */
 rt_status rt_scene_upload(rt_scene* scene, void* dev_ptr, size_t bytes, void* stream);
+
+/* BVH refit on the GPU, for dynamic scenes (moving primitives, same tree; the
+ * acceleration structure of Section II kept valid without a host rebuild).
+ * spheres: device float [n_spheres][4] (centre, radius) and tris: device float
+ * [n_tris][3][3], the scene's primitives in the order it was built with (NULL
+ * when the count is 0); materials, planes and lights are kept.  Enqueued on
+ * stream: rewrites the uploaded blob's primitive records and triangle normals,
+ * then the child boxes of every node level by level from the deepest (any
+ * node layout; quantized nodes are requantized), with the build's outward
+ * padding from the new scene scale.  Refitting to the positions the scene was
+ * built with reproduces the uploaded blob bit for bit.  The tree's quality
+ * falls as primitives move from where it was built (more node visits, never a
+ * wrong hit).  workspace: device, >= rt_scene_refit_workspace_bytes (a box per
+ * node), 256-byte aligned; not shared with a concurrent call.  Only the device
+ * copy changes: rt_scene_upload, rt_scene_set_layout, rt_host_trace and
+ * rt_scene_get_info keep the geometry the scene was built with.  With
+ * RT_FLAG_SYNC in flags the call waits and returns RT_ERR_INVALID_ARG if a
+ * position is non-finite or a radius <= 0 (the kernels then change nothing);
+ * without it such input is skipped the same way but not reported.  Errors:
+ * RT_ERR_INVALID_ARG, RT_ERR_NOT_UPLOADED, RT_ERR_CAPACITY, RT_ERR_HIP. */
+size_t rt_scene_refit_workspace_bytes(const rt_scene* scene);
+rt_status rt_scene_refit(rt_scene* scene, const float* spheres, const float* tris, void* workspace,
+                         size_t workspace_bytes, int32_t flags, void* stream);
 
 /* Workspace bytes rt_render needs for this camera and parameters (queues,
  * accumulator, counters).  Returns 0 and sets the last error for invalid input. */

@@ -18,8 +18,8 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libmirt.so")
 OBJDIR = os.path.join(ROOT, "_build", "mirt")
 
-SOURCES = ["scene.cpp", "render.cpp", "mlp.cpp"]
-HEADERS = ["rt_common.h", "mirt_internal.h", os.path.join("..", "..", "include", "mirt.h")]
+SOURCES = ["scene.cpp", "render.cpp", "mlp.cpp", "refit.cpp"]
+HEADERS = ["rt_common.h", "mirt_internal.h", "bvh_quant.h", os.path.join("..", "..", "include", "mirt.h")]
 
 ARCH = os.environ.get("MIRT_ARCH", "gfx950")
 COMMON = [

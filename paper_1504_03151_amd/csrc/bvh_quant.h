@@ -1,0 +1,78 @@
+// bvh_quant.h -- 8-bit quantization of a four-wide node's child boxes
+// (RT_LAYOUT_BVH4Q), shared by the host build and the device refit so that
+// both produce the same bits from the same boxes.
+#pragma once
+
+#include "rt_common.h"
+
+namespace mirt {
+
+// Per axis: origin p = the lowest child plane, scale 2^e the smallest power of
+// two with 255 * 2^e >= the node's extent; a lower plane takes the largest q
+// whose decoded fma(q, 2^e, p) is <= the true plane, an upper plane the
+// smallest q whose decoded value is >= it (checked with the same fma the
+// traversal decodes with), so every decoded box contains its child's padded
+// box.  lo/hi: child boxes; valid: used slots; child: the four references.
+// Returns false if an axis cannot be covered (non-finite extents).
+HD bool quantize_children(const float (&lo)[4][3], const float (&hi)[4][3], const bool (&valid)[4], int4 child,
+                          Node4q& q) {
+#pragma clang fp contract(off)
+    float p[3] = {0.0f, 0.0f, 0.0f};
+    uint32_t ebytes = 0, qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
+    for (int a = 0; a < 3; ++a) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int i = 0; i < 4; ++i)
+            if (valid[i]) {
+                mn = lo[i][a] < mn ? lo[i][a] : mn;
+                mx = hi[i][a] > mx ? hi[i][a] : mx;
+            }
+        if (!(mn <= mx)) {
+            mn = 0.0f;
+            mx = 0.0f;
+        }
+        p[a] = mn;
+        const double ext = (double)mx - mn;
+        int e = -126;
+        if (ext > 0.0) {
+            // ceil(log2(ext / 255)) exactly: v = m 2^x with m in [0.5, 1)
+            int x = 0;
+            const double m = frexp(ext / 255.0, &x);
+            const int c = m == 0.5 ? x - 1 : x;
+            e = c > -126 ? c : -126;
+        }
+        for (;; ++e) {
+            if (e > 127) return false;
+            const float sc = as_float_i((e + 127) << 23);   // 2^e, a normal float
+            bool ok = true;
+            uint32_t wl = 0, wh = 0;
+            for (int i = 0; i < 4 && ok; ++i) {
+                if (!valid[i]) continue;
+                double ql = floor(((double)lo[i][a] - mn) / sc);
+                ql = ql > 0.0 ? ql : 0.0;
+                while (ql > 0.0 && fmaf((float)ql, sc, mn) > lo[i][a]) ql -= 1.0;
+                double qh = ceil(((double)hi[i][a] - mn) / sc);
+                qh = qh > 0.0 ? qh : 0.0;
+                while (qh <= 255.0 && fmaf((float)qh, sc, mn) < hi[i][a]) qh += 1.0;
+                if (qh > 255.0 || ql > 255.0) ok = false;
+                wl |= (uint32_t)ql << (8 * i);
+                wh |= (uint32_t)qh << (8 * i);
+            }
+            if (ok) {
+                ebytes |= (uint32_t)(e + 127) << (8 * a);
+                qlo[a] = wl;
+                qhi[a] = wh;
+                break;
+            }
+        }
+    }
+    uint32_t mask = 0;
+    for (int i = 0; i < 4; ++i) mask |= valid[i] ? (1u << i) : 0u;
+    ebytes |= mask << 24;
+    q.origin = make_float4(p[0], p[1], p[2], as_float_i((int)ebytes));
+    q.qa = make_uint4(qlo[0], qhi[0], qlo[1], qhi[1]);
+    q.qb = make_uint4(qlo[2], qhi[2], (uint32_t)child.x, (uint32_t)child.y);
+    q.qc = make_int4(child.z, child.w, 0, 0);
+    return true;
+}
+
+}  // namespace mirt

@@ -13,13 +13,17 @@
 namespace mirt {
 
 void set_error(const std::string& msg);
+struct SceneHost;
+// Writes the refit order of the node section (blob section off_refit) and refit_levels.
+void refit_schedule(SceneHost& h);
 
 // Host copy of a built scene: one contiguous blob laid out exactly as it is
 // uploaded, plus the offsets of each section inside it.
 struct SceneHost {
     std::vector<uint8_t> blob;
     size_t off_nodes = 0, off_prims = 0, off_normals = 0, off_planes = 0, off_plane_mat = 0, off_mats = 0,
-           off_lights = 0;
+           off_lights = 0, off_refit = 0;
+    std::vector<int64_t> refit_levels;   // device refit: first entry of each level of the refit order (+ end)
     int n_spheres = 0, n_tris = 0, n_planes = 0, n_lights = 0, n_materials = 0;
     int64_t n_nodes = 0;
     int depth = 0, stack_size = 0;

@@ -12,6 +12,7 @@
 #include <thread>
 #include <vector>
 
+#include "bvh_quant.h"
 #include "mirt_internal.h"
 
 namespace mirt {
@@ -327,12 +328,8 @@ int32_t collapse4(const std::vector<Node>& n2, int32_t idx, int depth, std::vect
     return me;
 }
 
-// 8-bit quantization of a four-wide node's child boxes (RT_LAYOUT_BVH4Q).
-// Per axis: origin p = the lowest child plane, scale 2^e the smallest power of
-// two with 255 * 2^e >= the node's extent; a lower plane takes the largest q
-// whose decoded fma(q, 2^e, p) is <= the true plane, an upper plane the
-// smallest q whose decoded value is >= it (checked with the same fma the
-// traversal uses), so every decoded box contains its child's padded box.
+// 8-bit quantization of a four-wide node's child boxes (RT_LAYOUT_BVH4Q): the
+// shared quantizer of bvh_quant.h (the device refit uses the same code).
 float f4c(const float4& v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
 
 bool quantize4(const Node4& n, Node4q& q) {
@@ -347,54 +344,7 @@ bool quantize4(const Node4& n, Node4q& q) {
         }
         valid[i] = std::isfinite(lo[i][0]) && std::isfinite(hi[i][0]);
     }
-    float p[3] = {0.0f, 0.0f, 0.0f};
-    uint32_t ebytes = 0, qlo[3] = {0, 0, 0}, qhi[3] = {0, 0, 0};
-    for (int a = 0; a < 3; ++a) {
-        float mn = INFINITY, mx = -INFINITY;
-        for (int i = 0; i < 4; ++i)
-            if (valid[i]) {
-                mn = std::min(mn, lo[i][a]);
-                mx = std::max(mx, hi[i][a]);
-            }
-        if (!(mn <= mx)) {
-            mn = 0.0f;
-            mx = 0.0f;
-        }
-        p[a] = mn;
-        const double ext = (double)mx - mn;
-        int e = -126;
-        if (ext > 0.0) e = std::max(-126, (int)std::ceil(std::log2(ext / 255.0)));
-        for (;; ++e) {
-            if (e > 127) return false;
-            const float sc = std::ldexp(1.0f, e);
-            bool ok = true;
-            uint32_t wl = 0, wh = 0;
-            for (int i = 0; i < 4 && ok; ++i) {
-                if (!valid[i]) continue;
-                double ql = std::max(0.0, std::floor(((double)lo[i][a] - mn) / sc));
-                while (ql > 0.0 && std::fmaf((float)ql, sc, mn) > lo[i][a]) ql -= 1.0;
-                double qh = std::max(0.0, std::ceil(((double)hi[i][a] - mn) / sc));
-                while (qh <= 255.0 && std::fmaf((float)qh, sc, mn) < hi[i][a]) qh += 1.0;
-                if (qh > 255.0 || ql > 255.0) ok = false;
-                wl |= (uint32_t)ql << (8 * i);
-                wh |= (uint32_t)qh << (8 * i);
-            }
-            if (ok) {
-                ebytes |= (uint32_t)(e + 127) << (8 * a);
-                qlo[a] = wl;
-                qhi[a] = wh;
-                break;
-            }
-        }
-    }
-    uint32_t mask = 0;
-    for (int i = 0; i < 4; ++i) mask |= valid[i] ? (1u << i) : 0u;
-    ebytes |= mask << 24;
-    q.origin = make_float4(p[0], p[1], p[2], as_float_i((int)ebytes));
-    q.qa = make_uint4(qlo[0], qhi[0], qlo[1], qhi[1]);
-    q.qb = make_uint4(qlo[2], qhi[2], (uint32_t)n.child.x, (uint32_t)n.child.y);
-    q.qc = make_int4(n.child.z, n.child.w, 0, 0);
-    return true;
+    return quantize_children(lo, hi, valid, n.child, q);
 }
 
 // Node section of a layout (bytes), with the node count and the traversal
@@ -434,9 +384,58 @@ bool layout_nodes(const std::vector<Node>& dfs, int layout, int depth2, std::vec
 
 bool finite3(const float* p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
 
+// Child references of node i of a node section in the given layout (4 slots; binary nodes fill 2).
+int node_children(const uint8_t* nodes, int layout, int64_t i, int32_t (&ch)[4]) {
+    if (layout == RT_LAYOUT_BVH4) {
+        const int4 c = reinterpret_cast<const Node4*>(nodes)[i].child;
+        ch[0] = c.x, ch[1] = c.y, ch[2] = c.z, ch[3] = c.w;
+        return 4;
+    }
+    if (layout == RT_LAYOUT_BVH4Q) {
+        const Node4q& q = reinterpret_cast<const Node4q*>(nodes)[i];
+        ch[0] = (int32_t)q.qb.z, ch[1] = (int32_t)q.qb.w, ch[2] = q.qc.x, ch[3] = q.qc.y;
+        return 4;
+    }
+    const int4 d = reinterpret_cast<const Node*>(nodes)[i].d;
+    ch[0] = d.x, ch[1] = d.y;
+    return 2;
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
+
+// Refit order: node indices grouped by depth below the root, deepest level
+// first, so that a level's children were refit by an earlier level.
+void refit_schedule(SceneHost& h) {
+    const int64_t n = h.n_nodes;
+    const uint8_t* nb = h.blob.data() + h.off_nodes;
+    std::vector<int32_t> depth(n, -1), bfs;
+    bfs.reserve(n);
+    bfs.push_back(0);
+    depth[0] = 0;
+    int maxd = 0;
+    for (size_t k = 0; k < bfs.size(); ++k) {
+        int32_t ch[4];
+        const int nc = node_children(nb, h.layout, bfs[k], ch);
+        for (int c = 0; c < nc; ++c)
+            if (ch[c] >= 0) {
+                if (ch[c] >= n || depth[ch[c]] >= 0) throw std::runtime_error("refit schedule: malformed tree");
+                depth[ch[c]] = depth[bfs[k]] + 1;
+                maxd = std::max(maxd, depth[ch[c]]);
+                bfs.push_back(ch[c]);
+            }
+    }
+    if ((int64_t)bfs.size() != n) throw std::runtime_error("refit schedule: tree does not reach every node");
+    h.refit_levels.assign(maxd + 2, 0);
+    for (int64_t i = 0; i < n; ++i) h.refit_levels[maxd - depth[i] + 1]++;
+    for (int l = 0; l <= maxd; ++l) h.refit_levels[l + 1] += h.refit_levels[l];
+    std::vector<int64_t> next(h.refit_levels.begin(), h.refit_levels.end() - 1);
+    h.blob.resize(h.off_refit + align256(4 * (size_t)n));
+    int32_t* order = reinterpret_cast<int32_t*>(h.blob.data() + h.off_refit);
+    for (int64_t i = 0; i < n; ++i) order[next[maxd - depth[i]]++] = (int32_t)i;
+}
+
 }  // namespace mirt
 
 using namespace mirt;
@@ -622,6 +621,8 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         off = align256(off + sizeof(DevMaterial) * (size_t)std::max(nm, 1));
         h.off_lights = off;
         off = align256(off + sizeof(DevLight) * (size_t)std::max(nl, 1));
+        h.off_refit = off;
+        off = align256(off + 4 * (size_t)n_nodes);
         h.blob.assign(off, 0);
         uint8_t* base = h.blob.data();
         std::memcpy(base + h.off_nodes, node_bytes.data(), node_bytes.size());
@@ -690,6 +691,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
         I.node_layout = o.node_layout;
         h.uid = g_scene_uid.fetch_add(1);
         h.bvh2 = std::move(nodes);
+        refit_schedule(h);
         rt_scene* s = new rt_scene;
         s->h = std::move(h);
         *out = s;
@@ -733,12 +735,14 @@ rt_status rt_scene_set_layout(rt_scene* scene, int32_t node_layout) {
         std::memcpy(blob.data(), node_bytes.data(), node_bytes.size());
         std::memcpy(blob.data() + new_prims, h.blob.data() + h.off_prims, tail);
         const size_t old_prims = h.off_prims;
-        for (size_t* o : {&h.off_prims, &h.off_normals, &h.off_planes, &h.off_plane_mat, &h.off_mats, &h.off_lights})
+        for (size_t* o : {&h.off_prims, &h.off_normals, &h.off_planes, &h.off_plane_mat, &h.off_mats, &h.off_lights,
+                          &h.off_refit})
             *o = *o - old_prims + new_prims;
         h.blob.swap(blob);
         h.n_nodes = n_nodes;
         h.stack_size = stack_size;
         h.layout = node_layout;
+        refit_schedule(h);
         h.info.node_layout = node_layout;
         h.info.n_nodes = n_nodes;
         h.info.stack_size = stack_size;

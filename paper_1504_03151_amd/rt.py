@@ -113,6 +113,8 @@ SIGNATURES = {
     "rt_scene_set_layout": (C.c_int32, [_P, C.c_int32]),
     "rt_scene_device_bytes": (C.c_size_t, [_P]),
     "rt_scene_upload": (C.c_int32, [_P, _P, C.c_size_t, _P]),
+    "rt_scene_refit_workspace_bytes": (C.c_size_t, [_P]),
+    "rt_scene_refit": (C.c_int32, [_P, _P, _P, _P, C.c_size_t, C.c_int32, _P]),
     "rt_render_workspace_bytes": (C.c_size_t, [_P, C.POINTER(CameraC), C.POINTER(ParamsC)]),
     "rt_render": (C.c_int32, [_P, C.POINTER(CameraC), C.POINTER(ParamsC), _P, _P]),
     "rt_render_batch_workspace_bytes": (C.c_size_t, [_P, _P, _P, C.c_int32]),
@@ -242,6 +244,37 @@ class Scene:
         self.blob = torch.empty(n + 256, dtype=torch.uint8, device=device)
         base = (self.blob.data_ptr() + 255) // 256 * 256
         _check(lib().rt_scene_upload(self.handle, base, n, _stream_ptr(stream)), "rt_scene_upload")
+        return self
+
+    @property
+    def device_base(self) -> int:
+        """Device address of the uploaded blob (256-byte aligned inside self.blob)."""
+        return (self.blob.data_ptr() + 255) // 256 * 256
+
+    def device_blob(self):
+        """The uploaded blob as a uint8 tensor view (rt_scene_device_bytes bytes)."""
+        off = self.device_base - self.blob.data_ptr()
+        return self.blob[off:off + self.device_bytes]
+
+    def refit(self, spheres=None, tris=None, sync: bool = False, stream=None):
+        """Refit the uploaded BVH on the GPU to new positions: spheres float32 [ns,4], tris float32 [nt,3,3]
+        (contiguous CUDA tensors in the build order).  The tree is kept; only the device copy changes."""
+        import torch
+        if self.blob is None:
+            raise RTError(-7, "rt_scene_refit", "scene not uploaded")
+        need = int(lib().rt_scene_refit_workspace_bytes(self.handle))
+        ws = getattr(self, "_refit_ws", None)
+        if ws is None or ws.numel() < need + 256:
+            ws = self._refit_ws = torch.empty(need + 256, dtype=torch.uint8, device=self.blob.device)
+        base = (ws.data_ptr() + 255) // 256 * 256
+        ns, nt = len(self.src.spheres), len(self.src.tris)
+        for t, n, what in ((spheres, 4 * ns, "spheres"), (tris, 9 * nt, "tris")):
+            if n and (t is None or t.numel() != n):
+                raise ValueError(f"refit: {what} must hold {n} floats")
+            if t is not None:
+                assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        _check(lib().rt_scene_refit(self.handle, _ptr(spheres), _ptr(tris), base, need, FLAG_SYNC if sync else 0,
+                                    _stream_ptr(stream)), "rt_scene_refit")
         return self
 
     def host_trace(self, rays: np.ndarray, any_hit: bool = False, nthreads: int = 0, with_work: bool = False):
