@@ -1484,6 +1484,10 @@ static rt_status frame_grids(FrameArgs& A) {
     if (s1 != RT_OK) return s1;
     A.gx = std::min<int>(A.gx, (int)(kMaxPersistentThreads / 256));
     A.gs = std::min<int>(A.gs, (int)(kMaxPersistentThreads / 256));
+    // small frames: no more blocks than 256-entry slices of the queue (at least one per XCD), so that a
+    // launch does not start and retire thousands of idle waves
+    A.gx = (int)std::min<int64_t>(A.gx, std::max<int64_t>(kXcd, ((int64_t)A.pl.qcap + 255) / 256));
+    A.gs = (int)std::min<int64_t>(A.gs, std::max<int64_t>(kXcd, ((int64_t)A.pl.scap + 255) / 256));
     DevInfo di;
     s1 = device_info(di);
     if (s1 != RT_OK) return s1;
@@ -1831,6 +1835,8 @@ static rt_status batch_grids(BatchArgs& B) {
     if (s1 != RT_OK) return s1;
     B.gx = std::min<int>(B.gx, (int)(kMaxPersistentThreads / 256));
     B.gs = std::min<int>(B.gs, (int)(kMaxPersistentThreads / 256));
+    B.gx = (int)std::min<int64_t>(B.gx, std::max<int64_t>(kXcd, ((int64_t)B.pl.qcap + 255) / 256));
+    B.gs = (int)std::min<int64_t>(B.gs, std::max<int64_t>(kXcd, ((int64_t)B.pl.scap + 255) / 256));
     DevInfo di;
     s1 = device_info(di);
     if (s1 != RT_OK) return s1;

@@ -209,3 +209,18 @@ def test_area_light_records_are_validated():
     li[0, 7:10] = [1, 0, 0]
     li[0, 10:13] = [0, 0, 1]
     rt.Scene(S.make_scene(spheres=good.spheres, sphere_mat=good.sphere_mat, materials=good.materials, lights=li))
+
+
+def test_refit_argument_errors_need_no_gpu():
+    """rt_scene_refit checks its arguments on the host before any device work."""
+    w = S.random_tiny(1, n_spheres=3, n_tris=20, size=8)
+    sc = rt.Scene(w.scene)
+    L = rt.lib()
+    need = L.rt_scene_refit_workspace_bytes(sc.handle)
+    assert need >= 24 * sc.info["n_nodes"]
+    # not uploaded
+    assert L.rt_scene_refit(sc.handle, None, None, None, 0, 0, None) == -7      # RT_ERR_NOT_UPLOADED
+    assert L.rt_scene_refit(None, None, None, None, 0, 0, None) == -1           # RT_ERR_INVALID_ARG
+    assert b"NULL scene" in L.rt_last_error()
+    # the refit order is part of the blob: one int32 per node after the lights
+    assert sc.device_bytes >= 4 * sc.info["n_nodes"]

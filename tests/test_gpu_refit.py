@@ -162,3 +162,29 @@ def test_config2_refit_is_exact_and_moved_frame_follows_the_oracle(rt):
     gi = ids.reshape(-1, w.params.spp).cpu().numpy()[pixels]
     assert (gi[rob] == out["ids"][rob]).all()
     assert np.abs(g - out["rgb_s"]).max(axis=2)[rob].max() <= 1e-3
+
+
+def test_spheres_only_and_empty_scenes(rt):
+    w = S.config0()                                          # 8 spheres + a plane, no triangles
+    for layout in (0, 4):
+        sc = rt.Scene(w.scene, node_layout=layout).upload()
+        ref = sc.device_blob().clone()
+        sc.refit(dev(w.scene.spheres), None, sync=True)
+        torch.cuda.synchronize()
+        assert torch.equal(sc.device_blob(), ref)
+        m = moved(w.scene, 3, shift=0.8)
+        sc.refit(dev(m.spheres), None, sync=True)
+        rgb, ids, st = rt.render(sc, w.camera, w.params)
+        torch.cuda.synchronize()
+        out = oracle.render(m, w.camera, w.params)
+        rob = out["margin"] > ROBUST
+        assert rob.mean() > 0.97
+        assert (ids.reshape(-1).cpu().numpy()[rob] == out["ids"][rob, 0]).all()
+        assert np.abs(rgb.reshape(-1, 3).double().cpu().numpy() - out["rgb"]).max(1)[rob].max() <= 1e-3
+    planes = S.make_scene(planes=[[0.0, 1.0, 0.0, -1.0]], plane_mat=[0], materials=w.scene.materials[:1],
+                          lights=w.scene.lights)
+    sc = rt.Scene(planes).upload()
+    ref = sc.device_blob().clone()
+    sc.refit(None, None, sync=True)
+    torch.cuda.synchronize()
+    assert torch.equal(sc.device_blob(), ref)
