@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* t
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
                                                 uint32_t chunk, float* acc, int32_t* overflow,
                                                 unsigned long long* work_out, const uint32_t* perm = nullptr,
-                                                const uint32_t* begin_p = nullptr) {
+                                                const uint32_t* begin_p = nullptr, uint32_t* vis = nullptr) {
     __shared__ int32_t smem[4 * kSplitLds * 64];
     SplitStack stk = split_stack(smem, overflow);
     // entries [begin, end) of the queue; with perm, perm[0, end - begin) lists them in binned order
@@ -453,15 +453,71 @@ __global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* t
                 const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
                 const Hit h = traverse<true, COUNT>(S, r, s.tmax[i], stk, w);
                 if (h.prim < 0) {
-                    const uint32_t p = s.pix[i];
-                    atomicAdd(acc + 3 * p + 0, s.cr[i]);
-                    atomicAdd(acc + 3 * p + 1, s.cg[i]);
-                    atomicAdd(acc + 3 * p + 2, s.cb[i]);
+                    if (vis) {   // binned order visits pixels at random: mark the entry, add in queue order later
+                        atomicOr(vis + (i >> 5), 1u << (i & 31u));
+                    } else {
+                        const uint32_t p = s.pix[i];
+                        atomicAdd(acc + 3 * p + 0, s.cr[i]);
+                        atomicAdd(acc + 3 * p + 1, s.cg[i]);
+                        atomicAdd(acc + 3 * p + 2, s.cb[i]);
+                    }
                 }
             }
         }
     }
     flush_work<COUNT>(w, work_out);
+}
+
+// Visibility bits of the queue entries [begin, end) cleared before a binned shadow launch.
+__global__ void k_vis_clear(uint32_t* vis, const uint32_t* begin_p, const uint32_t* count_p, uint32_t cap) {
+    const uint32_t end = min(*count_p, cap);
+    const uint32_t begin = begin_p ? min(*begin_p, end) : 0u;
+    const uint32_t w1 = (end + 31u) >> 5;
+    for (uint32_t w = (begin >> 5) + blockIdx.x * blockDim.x + threadIdx.x; w < w1; w += gridDim.x * blockDim.x)
+        vis[w] = 0u;
+}
+
+// The unblocked entries of a binned shadow launch added to their pixels in
+// queue order: a block takes 1024 consecutive entries (a few shading waves'
+// rays, light-major), sums them per pixel in an LDS hash table and adds each
+// pixel once per channel (path-traced frames: ~7 entries per ray).
+constexpr int kVisSlots = 2048;
+constexpr uint32_t kVisChunk = 1024;
+__global__ __launch_bounds__(256) void k_vis_resolve(ShadowQ s, const uint32_t* vis, const uint32_t* begin_p,
+                                                     const uint32_t* count_p, uint32_t cap, float* acc) {
+    __shared__ uint32_t key[kVisSlots];
+    __shared__ float val[3][kVisSlots];
+    const uint32_t end = min(*count_p, cap);
+    const uint32_t begin = begin_p ? min(*begin_p, end) : 0u;
+    for (uint32_t b = begin + blockIdx.x * kVisChunk; b < end; b += gridDim.x * kVisChunk) {   // block-uniform
+        for (int k = threadIdx.x; k < kVisSlots; k += blockDim.x) {
+            key[k] = kDeadRay;
+            val[0][k] = val[1][k] = val[2][k] = 0.0f;
+        }
+        __syncthreads();
+        for (uint32_t i = b + threadIdx.x; i < min(b + kVisChunk, end); i += blockDim.x) {
+            if (!((vis[i >> 5] >> (i & 31u)) & 1u)) continue;
+            const uint32_t p = s.pix[i];
+            uint32_t h = (p * 2654435761u) >> 21;   // 11 bits: a slot of the table
+            for (;;) {   // at most 1024 keys in 2048 slots: a free or matching slot is always found
+                const uint32_t old = atomicCAS(&key[h], kDeadRay, p);
+                if (old == kDeadRay || old == p) break;
+                h = (h + 1u) & (kVisSlots - 1u);
+            }
+            atomicAdd(&val[0][h], s.cr[i]);
+            atomicAdd(&val[1][h], s.cg[i]);
+            atomicAdd(&val[2][h], s.cb[i]);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < kVisSlots; k += blockDim.x) {
+            const uint32_t p = key[k];
+            if (p == kDeadRay) continue;
+            atomicAdd(acc + 3 * p + 0, val[0][k]);
+            atomicAdd(acc + 3 * p + 1, val[1][k]);
+            atomicAdd(acc + 3 * p + 2, val[2][k]);
+        }
+        __syncthreads();
+    }
 }
 
 // Binning of the deferred shadow queue (a counting sort by key, keys < nb):
@@ -1532,13 +1588,19 @@ static void enqueue_shadow_segment(const FrameArgs& A, const ShadowQ& sq, const 
         hipLaunchKernelGGL(k_bin_scatter, dim3(1024), dim3(256), 0, st, sq.key, g.begin_p, g.end_p, g.cap,
                            g.bins + kBinMax, g.perm, nb);
     }
-    KernelTimer kt(A.time_kernels, st, 2);
-    if (A.count_work)
-        hipLaunchKernelGGL((k_shadow<true, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq, g.end_p,
-                           g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p);
-    else
-        hipLaunchKernelGGL((k_shadow<false, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq, g.end_p,
-                           g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p);
+    // binned launches mark unblocked entries in the key array (no longer needed once the order is known)
+    uint32_t* vis = g.perm && A.shc.gi ? sq.key : nullptr;   // path-traced frames (many unblocked rays)
+    if (vis) hipLaunchKernelGGL(k_vis_clear, dim3(1024), dim3(256), 0, st, vis, g.begin_p, g.end_p, g.cap);
+    {
+        KernelTimer kt(A.time_kernels, st, 2);
+        if (A.count_work)
+            hipLaunchKernelGGL((k_shadow<true, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq,
+                               g.end_p, g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p, vis);
+        else
+            hipLaunchKernelGGL((k_shadow<false, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq,
+                               g.end_p, g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p, vis);
+    }
+    if (vis) hipLaunchKernelGGL(k_vis_resolve, dim3(2048), dim3(256), 0, st, sq, vis, g.begin_p, g.end_p, g.cap, acc);
 }
 
 // One plain frame.  Per pass: ray generation, then for each depth the
