@@ -122,6 +122,7 @@ struct ShadeConst {
     float bin_lo[3], bin_inv[3];
     int bin_c;
     int gi;   // 1: global illumination, one randomly chosen continuation per hit (path tracing)
+    int sum_depth0;   // 1: the four waves of a block at depth 0 are four samples of one pixel tile
 };
 
 // One scene of a batched frame (device table, one entry per scene).
@@ -755,10 +756,13 @@ template <bool BATCH, bool GI>
 __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const BatchScene* tab, RayQ qin, HitQ hit,
                                                uint32_t* ctr, int depth, RayQ qout, ShadowQ sq, float* acc) {
     __shared__ uint32_t lds_res[4];
+    __shared__ float lds_add[3][256];   // depth 0: the block's background / ambient terms ...
+    __shared__ uint32_t lds_pix[256];   // ... and their pixels
     const uint32_t qcap = c0.qcap, scap = c0.scap;
     const uint32_t count = min(ctr[kCtrRays + depth], qcap);
     const uint32_t stride = gridDim.x * blockDim.x;
     const bool light_major = !BATCH && sc.n_lights <= 32;
+    const bool sum0 = !BATCH && depth == 0 && c0.sum_depth0;
     for (uint32_t bb = blockIdx.x * blockDim.x; bb < count; bb += stride) {   // block-uniform loop
         const uint32_t i = bb + threadIdx.x;
         bool active = i < count;
@@ -790,10 +794,11 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
             C.out_ids[C.per_sample ? (size_t)local : (size_t)local * C.spp + ((meta >> 4) & 0xFFFFu)] = oid;
         }
         const bool shade = active && prim >= 0;
+        V3 add = v3(0.0f, 0.0f, 0.0f);   // background (miss) or ambient (hit) term of this ray
+        bool has_add = false;
         if (active && prim < 0) {
-            atomicAdd(acc + 3 * pix + 0, w.x * C.bg[0]);
-            atomicAdd(acc + 3 * pix + 1, w.y * C.bg[1]);
-            atomicAdd(acc + 3 * pix + 2, w.z * C.bg[2]);
+            add = v3(w.x * C.bg[0], w.y * C.bg[1], w.z * C.bg[2]);
+            has_add = true;
         }
         // hit point, geometric normal, material
         V3 x = v3(0, 0, 0), ng = v3(0, 0, 1);
@@ -826,9 +831,37 @@ __global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const
         const float eps_s = C.eps * fmaxf(1.0f, maxabs(x));
         const V3 xs = x + eps_s * nf;
         if (shade && ka > 0.0f) {
-            atomicAdd(acc + 3 * pix + 0, w.x * ka * alb.x);
-            atomicAdd(acc + 3 * pix + 1, w.y * ka * alb.y);
-            atomicAdd(acc + 3 * pix + 2, w.z * ka * alb.z);
+            add = v3(w.x * ka * alb.x, w.y * ka * alb.y, w.z * ka * alb.z);
+            has_add = true;
+        }
+        if (sum0) {
+            // ray generation order: lane l of the block's four waves is one pixel in four samples, so wave 0
+            // adds their sum once (checked: different pixels are added one by one)
+            lds_pix[threadIdx.x] = has_add ? pix : kDeadRay;
+            lds_add[0][threadIdx.x] = add.x;
+            lds_add[1][threadIdx.x] = add.y;
+            lds_add[2][threadIdx.x] = add.z;
+            __syncthreads();
+            if (threadIdx.x < 64) {
+                const uint32_t l = threadIdx.x, q0 = lds_pix[l];
+                const bool same = q0 != kDeadRay && lds_pix[64 + l] == q0 && lds_pix[128 + l] == q0 &&
+                                  lds_pix[192 + l] == q0;
+                if (same) {
+                    for (int c = 0; c < 3; ++c)
+                        atomicAdd(acc + 3 * q0 + c,
+                                  (lds_add[c][l] + lds_add[c][64 + l]) + (lds_add[c][128 + l] + lds_add[c][192 + l]));
+                } else {
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t q = lds_pix[64 * k + l];
+                        if (q == kDeadRay) continue;
+                        for (int c = 0; c < 3; ++c) atomicAdd(acc + 3 * q + c, lds_add[c][64 * k + l]);
+                    }
+                }
+            }
+        } else if (has_add) {
+            atomicAdd(acc + 3 * pix + 0, add.x);
+            atomicAdd(acc + 3 * pix + 1, add.y);
+            atomicAdd(acc + 3 * pix + 2, add.z);
         }
         // ---- shadow rays: decide per light, reserve, then write
         uint32_t emit_mask = 0, n_sh = 0;
@@ -2449,6 +2482,8 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.shc.acc_off = 0;
     A.shc.out_ids = out_hit_ids;
     A.shc.gi = (p.flags & RT_FLAG_GI) ? 1 : 0;
+    // depth-0 background / ambient terms summed over the four samples of a pixel in a block
+    A.shc.sum_depth0 = (!A.shc.per_sample && pl.spp_pass % 4 == 0) ? 1 : 0;
     defer_and_bin_shadows(A, scene->h);
     A.pl = pl;
     A.ws = static_cast<uint8_t*>(p.workspace);
@@ -2648,6 +2683,8 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     A.shc.acc_off = 0;
     A.shc.out_ids = out_hit_ids;
     A.shc.gi = (p.flags & RT_FLAG_GI) ? 1 : 0;
+    // depth-0 background / ambient terms summed over the four samples of a pixel in a block
+    A.shc.sum_depth0 = (!A.shc.per_sample && C.cp.base.spp_pass % 4 == 0) ? 1 : 0;
     defer_and_bin_shadows(A, scene->h);
     A.pl = C.cp.base;
     A.ws = static_cast<uint8_t*>(p.workspace);
