@@ -400,9 +400,9 @@ struct QueueFetch {
 };
 
 template <bool COUNT, bool BATCH>
-__global__ __launch_bounds__(256) void k_extend(DevScene sc, const BatchScene* tab, RayQ q, HitQ hit,
-                                                const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
-                                                uint32_t chunk, int32_t* overflow, unsigned long long* work_out) {
+__device__ __forceinline__ void extend_queue(const DevScene& sc, const BatchScene* tab, const RayQ& q, const HitQ& hit,
+                                             const uint32_t* count_p, uint32_t* cursor, uint32_t cap, uint32_t chunk,
+                                             int32_t* overflow, unsigned long long* work_out) {
     __shared__ int32_t smem[4 * kSplitLds * 64];
     SplitStack stk = split_stack(smem, overflow);
     const uint32_t count = min(*count_p, cap);   // a producer that overflowed still bumped the tail
@@ -426,6 +426,22 @@ __global__ __launch_bounds__(256) void k_extend(DevScene sc, const BatchScene* t
         }
     }
     flush_work<COUNT>(w, work_out);
+}
+
+template <bool COUNT, bool BATCH>
+__global__ __launch_bounds__(256) void k_extend(DevScene sc, const BatchScene* tab, RayQ q, HitQ hit,
+                                                const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
+                                                uint32_t chunk, int32_t* overflow, unsigned long long* work_out) {
+    extend_queue<COUNT, BATCH>(sc, tab, q, hit, count_p, cursor, cap, chunk, overflow, work_out);
+}
+
+// The same for the bounces after the first: their queues are small and incoherent, so a launch is bound by
+// the latency of each ray's chain of node fetches; eight waves per SIMD (a few spilled registers) hide more
+// of it than the six the register count otherwise allows.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_extend_deep(
+    DevScene sc, RayQ q, HitQ hit, const uint32_t* count_p, uint32_t* cursor, uint32_t cap, uint32_t chunk,
+    int32_t* overflow) {
+    extend_queue<false, false>(sc, nullptr, q, hit, count_p, cursor, cap, chunk, overflow, nullptr);
 }
 
 // Any-hit over the shadow queue; adds the contribution of each unblocked light
@@ -1556,6 +1572,7 @@ struct FrameArgs {
     bool count_work;
     int spp;
     int gx, gs, shade_blocks;   // grid sizes, computed outside any capture
+    int gxd;                    // grid of k_extend_deep
     size_t lds;
     bool time_kernels;
     uint32_t chunk;             // queue entries per fetch of a persistent traversal wave
@@ -1571,6 +1588,10 @@ static rt_status frame_grids(FrameArgs& A) {
     s1 = A.count_work ? persistent_grid(k_shadow<true, false>, 0, A.gs)
                       : persistent_grid(k_shadow<false, false>, 0, A.gs);
     if (s1 != RT_OK) return s1;
+    s1 = persistent_grid(k_extend_deep, 0, A.gxd);
+    if (s1 != RT_OK) return s1;
+    A.gxd = std::min<int>(A.gxd, (int)(kMaxPersistentThreads / 256));
+    A.gxd = (int)std::min<int64_t>(A.gxd, std::max<int64_t>(kXcd, ((int64_t)A.pl.qcap + 255) / 256));
     A.gx = std::min<int>(A.gx, (int)(kMaxPersistentThreads / 256));
     A.gs = std::min<int>(A.gs, (int)(kMaxPersistentThreads / 256));
     // small frames: no more blocks than 256-entry slices of the queue (at least one per XCD), so that a
@@ -1689,6 +1710,9 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
                     hipLaunchKernelGGL((k_extend<true, false>), dim3(gx), dim3(256), A.lds, st, A.sc, nullptr, qi, hq,
                                        ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk,
                                        overflow, work);
+                else if (k > 0)
+                    hipLaunchKernelGGL(k_extend_deep, dim3(A.gxd), dim3(256), 0, st, A.sc, qi, hq, ctr + kCtrRays + k,
+                                       xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk, overflow);
                 else
                     hipLaunchKernelGGL((k_extend<false, false>), dim3(gx), dim3(256), A.lds, st, A.sc, nullptr, qi,
                                        hq, ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk,
@@ -1750,6 +1774,7 @@ static rt_status launch_frame(const FrameArgs& A, hipStream_t st, bool use_graph
     put(key.bytes, A.count_work);
     put(key.bytes, A.spp);
     put(key.bytes, A.gx);
+    put(key.bytes, A.gxd);
     put(key.bytes, A.gs);
     put(key.bytes, A.shade_blocks);
     put(key.bytes, A.chunk);
