@@ -23,6 +23,9 @@
  *     local term from Phong reflection (ambient + diffuse + specular) in place
  *     of the hemisphere integral of Eq. 8.
  *   - Several samples per pixel averaged (anti-aliasing, end of Section III).
+ *   - Optionally (or_params.gi) diffuse global illumination: the hemisphere
+ *     integral of Eq. 8 estimated by path tracing, one randomly chosen
+ *     continuation per hit (see gi_bounce).
  *
  * Besides colours and ids it reports, for every ray it traces, a robustness
  * margin: how far each discrete decision (which primitive is hit, whether a
