@@ -36,11 +36,11 @@ DEFAULT = {"layout": rt.LAYOUT_DFS, "chunk": 128, "tile": rt.TILE_8X8}
 
 
 def signature(scenes: Sequence["rt.Scene"], cameras, params) -> str:
-    """Stable description of a workload: primitive counts, resolutions, samples and depths."""
+    """Stable description of a workload: primitive counts, resolutions, samples, depths and path tracing."""
     h = hashlib.sha256()
     for s, c, p in zip(scenes, cameras, params):
         h.update(f"{len(s.src.spheres)},{len(s.src.tris)},{len(s.src.planes)},{len(s.src.lights)};"
-                 f"{c.width}x{c.height};{p.spp},{p.max_depth};".encode())
+                 f"{c.width}x{c.height};{p.spp},{p.max_depth},{int(getattr(p, 'gi', 0))};".encode())
     return h.hexdigest()[:16]
 
 

@@ -224,3 +224,24 @@ def test_refit_argument_errors_need_no_gpu():
     assert b"NULL scene" in L.rt_last_error()
     # the refit order is part of the blob: one int32 per node after the lights
     assert sc.device_bytes >= 4 * sc.info["n_nodes"]
+
+
+def test_autotune_signature_separates_path_tracing():
+    from paper_1504_03151_amd import autotune
+    w = S.random_tiny(1, size=8)
+
+    class _S:   # the signature only reads the source arrays
+        src = w.scene
+    a = autotune.signature([_S()], [w.camera], [w.params])
+    w.params.gi = 1
+    assert autotune.signature([_S()], [w.camera], [w.params]) != a
+
+
+def test_global_illumination_room_is_closed():
+    """Every camera ray of the path-traced room workload hits something (the walls close it)."""
+    import oracle
+    w = S.config_gi(width=64, height=36, spp=1)
+    o, d = oracle.camera_rays(w.camera, w.params, np.arange(w.camera.n_pixels))
+    t, ids, _ = oracle.closest(w.scene, o, d)
+    assert (ids >= 0).all()
+    assert w.params.gi == 1 and w.params.max_depth == 6
