@@ -255,8 +255,8 @@ MLP_TRAIN_FLOP = MLP_FWD_FLOP + MLP_FWD_FLOP + 2 * (4 * 64 * 64 + 64 * 3)  # for
 def bench_cache(w, sc, plain, args):
     """Learned form vs the plain full-depth frame on the same scene, camera, samples and frame numbers.
 
-    32 frames of online training (65,536 samples, 4 Adam steps each; 96 for path-traced frames) warm the
-    network up; the next 16 frames are timed (training included) beside plain frames of the same frame
+    256 frames of online training (65,536 samples, 4 Adam steps each; 96 for path-traced frames, whose frames
+    take ten times longer) warm the network up; the next 16 frames are timed (training included) beside plain frames of the same frame
     numbers, which are the judge of the relative MSE for Whitted frames; path-traced frames are judged
     against a converged mean of plain frames.  Depth-2 truncation (the network replaced by zero) shows what
     the network gains.
@@ -271,7 +271,7 @@ def bench_cache(w, sc, plain, args):
                            queue_chunk=plain.queue_chunk, tile=plain.tile, with_ids=False)
     log(f"cache workspace {cr.ws_bytes / 2 ** 30:.2f} GiB")
     f0 = 1000
-    warm = args.cache_warmup if args.cache_warmup is not None else (96 if w.params.gi else 32)
+    warm = args.cache_warmup if args.cache_warmup is not None else (96 if w.params.gi else 256)
     for f in range(warm):
         w.params.frame = f0 + f
         cr.render()
@@ -491,8 +491,8 @@ def main():
     ap.add_argument("--layout", type=int, default=None, help="BVH node layout (0 depth-first, 1 breadth-first, "
                                                              "2 treelets)")
     ap.add_argument("--cache-warmup", type=int, default=None,
-                    help="online-training frames before measuring (default 32; 96 for path-traced frames, whose "
-                         "targets are single noisy paths)")
+                    help="online-training frames before measuring (default 256, ~3 s of frames; 96 for "
+                         "path-traced frames)")
     ap.add_argument("--cache-frames", type=int, default=16, help="measured learned-form frames")
     ap.add_argument("--gi-ref-frames", type=int, default=8,
                     help="plain path-traced frames averaged into the reference of the learned form (workload gi)")
