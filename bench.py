@@ -257,8 +257,8 @@ def bench_cache(w, sc, plain, args):
 
     256 frames of online training (65,536 samples, 4 Adam steps each; 96 for path-traced frames, whose frames
     take ten times longer) warm the network up; the next 16 frames are timed (training included) beside plain frames of the same frame
-    numbers, which are the judge of the relative MSE for Whitted frames; path-traced frames are judged
-    against a converged mean of plain frames.  Depth-2 truncation (the network replaced by zero) shows what
+    numbers, which are the reference of the relative MSE for Whitted frames; path-traced frames are compared
+    with a converged mean of plain frames.  Depth-2 truncation (the network replaced by zero) shows what
     the network gains.
     """
     import numpy as np
@@ -286,7 +286,7 @@ def bench_cache(w, sc, plain, args):
             e = e[mask]
         return float(e.mean()) if e.numel() else 0.0
 
-    # Path-traced frames are noisy estimates: their judge is a converged reference, the mean of plain frames
+    # Path-traced frames are noisy estimates: their reference is a converged one, the mean of plain frames
     # with other frame numbers (untimed); a single plain frame's own error against it is reported beside.
     ref = None
     if w.params.gi:
@@ -323,11 +323,11 @@ def bench_cache(w, sc, plain, args):
         cr.cc.state, cr.cc.mode = cache.base, rt.CACHE_TRAIN
         torch.cuda.synchronize()
         aff = ((img_p - img_t).abs() > 1e-6).any(dim=-1)
-        judge = img_p if ref is None else ref
-        rows.append({"ms_cache": ms_c, "ms_plain": ms_p, "rel_mse": rel_mse(img_c, judge),
-                     "rel_mse_affected": rel_mse(img_c, judge, aff), "trunc_rel_mse": rel_mse(img_t, judge),
-                     "trunc_rel_mse_affected": rel_mse(img_t, judge, aff), "affected": float(aff.double().mean()),
-                     "plain_rel_mse": rel_mse(img_p, judge),
+        target = img_p if ref is None else ref
+        rows.append({"ms_cache": ms_c, "ms_plain": ms_p, "rel_mse": rel_mse(img_c, target),
+                     "rel_mse_affected": rel_mse(img_c, target, aff), "trunc_rel_mse": rel_mse(img_t, target),
+                     "trunc_rel_mse_affected": rel_mse(img_t, target, aff), "affected": float(aff.double().mean()),
+                     "plain_rel_mse": rel_mse(img_p, target),
                      "queries": st_c["cache_queries"], "rays": sum(st_c["rays"]) + sum(st_c["shadow"]),
                      "target_rays": st_c["target_rays"] + st_c["target_shadow"],
                      "plain_rays": sum(st_p["rays"]) + sum(st_p["shadow"])})
@@ -351,7 +351,7 @@ def bench_cache(w, sc, plain, args):
         "truncation_rel_mse": mean("trunc_rel_mse"), "truncation_rel_mse_affected": mean("trunc_rel_mse_affected"),
         "affected_pixel_frac": round(mean("affected"), 4),
         "meets_target": bool(mean("rel_mse") <= 1e-2 and ms_c < ms_p),
-        "judge": "the plain frame of the same frame number" if ref is None else
+        "reference": "the plain frame of the same frame number" if ref is None else
                  f"mean of {args.gi_ref_frames} plain path-traced frames (other frame numbers)",
         "plain_rel_mse": None if ref is None else mean("plain_rel_mse"),
         "mrays_per_s": round((mean("rays") + mean("target_rays")) / (ms_c / 1e3) / 1e6, 1),
@@ -511,7 +511,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); the path would shard "
-              f"pixels or sample passes across GPUs, see DESIGN.md", file=sys.stderr)
+              f"pixels or sample passes across GPUs and sum the accumulators", file=sys.stderr)
         sys.exit(2)
 
     import torch
