@@ -101,6 +101,31 @@ def test_jittered_spp_and_graph_replay(rt):
     compare(w, first[0], first[1], min_robust=0.95)
 
 
+def test_pass_splits_give_the_same_frame(rt):
+    """Passes of 4 samples sum each pixel's depth-0 background and ambient terms over a block's four waves;
+    a partial last pass, passes of 3 samples and per-sample output take the per-ray path.  Every split gives
+    the same ids and, up to the order of additions, the same image."""
+    w = S.random_tiny(6, size=37, depth=3)                 # ragged tiles: dead lanes in the blocks
+    w.camera.height = 29
+    w.params.spp, w.params.jitter = 10, 1
+    sc = rt.Scene(w.scene).upload()
+    out = []
+    for spp_pass in (10, 4, 3, 8):
+        r = rt.Renderer(sc, w.camera, w.params, samples_per_pass=spp_pass)
+        rgb, ids = r.render(rt.FLAG_SYNC)
+        torch.cuda.synchronize()
+        out.append((rgb.clone(), ids.clone()))
+    rs = rt.Renderer(sc, w.camera, w.params, per_sample=True)
+    rgb_s, ids_s = rs.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    for rgb, ids in out[1:]:
+        assert torch.equal(ids, out[0][1])
+        assert torch.allclose(rgb, out[0][0], rtol=1e-5, atol=1e-6)
+    assert torch.equal(ids_s, out[0][1])
+    assert torch.allclose(rgb_s.mean(dim=2), out[0][0], rtol=1e-5, atol=2e-6)
+    compare(w, out[1][0], out[1][1], min_robust=0.95)
+
+
 def test_edge_cases(rt):
     # empty scene (only background), a planes-only scene, a 1x1 image, depth 0
     bg = (0.25, 0.5, 0.75)
