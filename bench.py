@@ -444,6 +444,36 @@ def bench_refit(args):
     achieved = algo / (refit_ms / 1e3) / 1e9
     log(f"refit {refit_ms:.3f} ms (host build {build_s:.2f} s); frame through refit tree {refit_frame_ms:.2f} ms "
         f"vs rebuilt {fresh_frame_ms:.2f} ms; node visits {refit_visits} vs {fresh_visits}")
+    # the batch of 256 uneven scenes, every primitive moving: all scenes refit on one stream vs the host build
+    ws = scenes.config3(256)
+    t0 = time.perf_counter()
+    scs = build_scenes(ws, rt)
+    batch_build_s = time.perf_counter() - t0
+    for x in scs:
+        x.upload()
+    moved_pos = []
+    for b, wb in enumerate(ws):
+        g = np.random.default_rng(100 + b)
+        sp = wb.scene.spheres.copy()
+        if len(sp):
+            sp[:, :3] += g.uniform(-0.3, 0.3, (len(sp), 3)).astype(np.float32)
+        tr = (wb.scene.tris + g.uniform(-0.3, 0.3, (len(wb.scene.tris), 1, 3))).astype(np.float32)
+        moved_pos.append((torch.from_numpy(sp).cuda() if len(sp) else None,
+                          torch.from_numpy(np.ascontiguousarray(tr)).cuda() if len(tr) else None))
+    for x, (sp, tr) in zip(scs, moved_pos):   # warm-up (workspaces allocated)
+        x.refit(sp, tr)
+    torch.cuda.synchronize()
+    a, bev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for x, (sp, tr) in zip(scs, moved_pos):
+        x.refit(sp, tr)
+    bev.record()
+    torch.cuda.synchronize()
+    batch_refit_ms = a.elapsed_time(bev)
+    br = rt.BatchRenderer(scs, [wb.camera for wb in ws], [wb.params for wb in ws])
+    br.render(rt.FLAG_SYNC)
+    assert br.read_stats()["status"] == 0
+    log(f"c3 batch: refit of 256 scenes {batch_refit_ms:.2f} ms vs host build {batch_build_s:.2f} s")
     out = {
         "metric": "ms per BVH refit on the GPU (c2 scene, 1.28M triangles, every object moving)",
         "value": round(refit_ms, 4), "unit": "ms", "n_gpus": 1, "steps": frames, "warmup": args.warmup + 1,
@@ -454,6 +484,8 @@ def bench_refit(args):
         "host_build_seconds": round(build_s, 3), "host_rebuild_seconds": round(rebuild_s, 3),
         "speedup_vs_host_build": round(build_s * 1e3 / refit_ms, 1),
         "frame_ms_refit_tree": round(refit_frame_ms, 3), "frame_ms_rebuilt_tree": round(fresh_frame_ms, 3),
+        "c3_batch_refit_ms": round(batch_refit_ms, 3), "c3_batch_host_build_seconds": round(batch_build_s, 3),
+        "c3_batch_triangles": int(sum(len(wb.scene.tris) for wb in ws)),
         "node_visits_refit_tree": int(refit_visits), "node_visits_rebuilt_tree": int(fresh_visits),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "refit (all launches)",

@@ -188,3 +188,24 @@ def test_spheres_only_and_empty_scenes(rt):
     sc.refit(None, None, sync=True)
     torch.cuda.synchronize()
     assert torch.equal(sc.device_blob(), ref)
+
+
+def test_batched_frame_after_refit_equals_single_frames(rt):
+    """Refit scenes render in a batched frame exactly as one by one (the batch reads each refit blob)."""
+    ws = [S.random_tiny(20 + s, n_spheres=5, n_tris=80, size=20 + 3 * s, depth=3) for s in range(3)]
+    scs = [rt.Scene(w.scene, node_layout=4).upload() for w in ws]
+    ms = [moved(w.scene, 40 + i, shift=0.5) for i, w in enumerate(ws)]
+    for sc, m in zip(scs, ms):
+        sc.refit(dev(m.spheres), dev(m.tris), sync=True)
+    b = rt.BatchRenderer(scs, [w.camera for w in ws], [w.params for w in ws])
+    rb, ib = b.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    for w, sc, m, x, u in zip(ws, scs, ms, rb, ib):
+        rgb, ids, _ = rt.render(sc, w.camera, w.params)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, u)
+        assert torch.allclose(rgb, x, rtol=1e-5, atol=1e-6)
+        out = oracle.render(m, w.camera, w.params)
+        rob = out["margin"] > ROBUST
+        assert rob.mean() > 0.95
+        assert (u.reshape(-1).cpu().numpy()[rob] == out["ids"][rob, 0]).all()
