@@ -445,9 +445,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 }
 
 // Any-hit over the shadow queue; adds the contribution of each unblocked light
-// to its pixel.
+// to its pixel.  Eight waves per SIMD (a few spilled registers): more rays in
+// flight hide more of the node-fetch latency than the six the register count
+// otherwise allows.
 template <bool COUNT, bool BATCH>
-__global__ __launch_bounds__(256) void k_shadow(DevScene sc, const BatchScene* tab, ShadowQ s,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_shadow(DevScene sc, const BatchScene* tab, ShadowQ s,
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
                                                 uint32_t chunk, float* acc, int32_t* overflow,
                                                 unsigned long long* work_out, const uint32_t* perm = nullptr,
