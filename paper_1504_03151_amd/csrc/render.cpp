@@ -770,8 +770,9 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
 // out light-major inside each wave (consecutive entries go to the same light)
 // so the shadow kernel's waves traverse coherently.
 // GI: compiled with the path-tracing branch (taken where the scene's ShadeConst has gi set).
+// Six waves per SIMD: the register count lands just above the 80 that allow them.
 template <bool BATCH, bool GI>
-__global__ __launch_bounds__(256) void k_shade(DevScene sc, ShadeConst c0, const BatchScene* tab, RayQ qin, HitQ hit,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_shade(DevScene sc, ShadeConst c0, const BatchScene* tab, RayQ qin, HitQ hit,
                                                uint32_t* ctr, int depth, RayQ qout, ShadowQ sq, float* acc) {
     __shared__ uint32_t lds_res[4];
     __shared__ float lds_add[3][256];   // depth 0: the block's background / ambient terms ...
