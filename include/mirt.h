@@ -295,7 +295,8 @@ rt_status rt_kernel_times(double* ms, int64_t* launches, int32_t reset);
  * the facing normal and the view direction, zero-padded from 42); five hidden
  * layers of 64 with ReLU; 3 outputs; no biases.  Weights are row-major
  * (out, in): W1..W5 [64][64] then W6 [3][64] = rt_mlp_num_params() values.
- * Every pointer below is a device pointer; BF16 values are uint16 bit patterns. */
+ * Every pointer below is a device pointer; BF16 values are uint16 bit patterns.
+ * w_bf16 and x_bf16 must be 16-byte aligned (RT_ERR_INVALID_ARG otherwise). */
 int32_t rt_mlp_num_params(void);
 /* y [n][3] = network(x_bf16 [n][64]). */
 rt_status rt_mlp_forward(const uint16_t* w_bf16, const uint16_t* x_bf16, int64_t n, float* y, void* stream);

@@ -35,6 +35,7 @@ namespace mirt {
     } while (0)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short short8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -89,34 +90,49 @@ __global__ void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* D) {
 // Forward weights: Wf[layer][out m][k-slot kappa], layers 0..4 (64 rows) and
 // the output layer (32 rows, rows >= 3 zero).  Layer 0 takes the input
 // features in natural order; later layers read their inputs through sigma.
+// Rows are kWp = 72 entries apart: a 16-byte operand read is served eight lanes
+// at a time, and 144-byte rows put those eight lanes' rows on distinct banks
+// (64-entry rows would put all eight on the same four).
+constexpr int kWp = kW + 8;
+constexpr int kFwdRows = 5 * kW + 32;
 struct MlpLds {
-    uint16_t wf[5 * kLayerElems + 32 * kW];
+    uint16_t wf[kFwdRows * kWp];
 };
 
+__device__ __forceinline__ uint2 ld4(const uint16_t* p) { return *reinterpret_cast<const uint2*>(p); }
+
+// one unit = 8 consecutive k-slots of one row: two 8-byte reads (sigma keeps
+// runs of four k-slots together) and one 16-byte LDS store.  w: 8-byte aligned.
 __device__ void stage_forward(const uint16_t* __restrict__ w, uint16_t* wf) {
-    for (int e = threadIdx.x; e < 5 * kLayerElems + 32 * kW; e += blockDim.x) {
-        const int layer = e / kLayerElems;
-        const int rem = e - layer * kLayerElems;
-        const int m = rem / kW, kap = rem % kW;
-        uint16_t v;
-        if (layer < 5) {
-            v = w[layer * kLayerElems + m * kW + (layer == 0 ? kap : swap23(kap))];
-        } else {
-            v = m < 3 ? w[5 * kLayerElems + m * kW + swap23(kap)] : (uint16_t)0;
+    for (int u = threadIdx.x; u < kFwdRows * 8; u += blockDim.x) {
+        const int row = u >> 3, g = u & 7;
+        const int layer = row >> 6, m = row & 63;
+        const uint16_t* src = w + layer * kLayerElems + m * kW;
+        uint2 a = make_uint2(0u, 0u), b = make_uint2(0u, 0u);
+        if (layer == 0) {
+            a = ld4(src + 8 * g);
+            b = ld4(src + 8 * g + 4);
+        } else if (layer < 5 || m < 3) {
+            a = ld4(src + swap23(8 * g));
+            b = ld4(src + swap23(8 * g + 4));
         }
-        wf[e] = v;
+        *reinterpret_cast<uint4*>(wf + row * kWp + 8 * g) = make_uint4(a.x, a.y, b.x, b.y);
     }
 }
 
 // Backward weights: Wb[l][in m][k-slot kappa] = W_{l+1}[sigma(kappa)][m] for
-// layers 1..4 (the products g_h_{l} = W_{l+1}^T g_z_{l+1}), and the output
-// layer's transpose Wb6[m][k] = W6[k][m] (k < 3, 16 columns).
+// layers 1..4 (the products g_h_{l} = W_{l+1}^T g_z_{l+1}), rows kWp apart like
+// the forward copy, and the output layer's transpose Wb6[m][k] = W6[k][m] (k < 3,
+// 16 columns).  One unit reads 8 consecutive columns m of a row j of W_{l+1}
+// (16 bytes; sigma is its own inverse, so that row lands in k-slot sigma(j)).
 __device__ void stage_backward(const uint16_t* __restrict__ w, uint16_t* wb, uint16_t* wb6) {
-    for (int e = threadIdx.x; e < 4 * kLayerElems; e += blockDim.x) {
-        const int li = e / kLayerElems;          // 0..3 -> weight layer 2..5 (index 1..4)
-        const int rem = e - li * kLayerElems;
-        const int m = rem / kW, kap = rem % kW;
-        wb[e] = w[(li + 1) * kLayerElems + swap23(kap) * kW + m];
+    for (int u = threadIdx.x; u < 4 * kW * 8; u += blockDim.x) {
+        const int li = u >> 9, j = (u >> 3) & 63, mg = u & 7;   // li 0..3 -> weight layer 2..5 (index 1..4)
+        const uint4 v = *reinterpret_cast<const uint4*>(w + (li + 1) * kLayerElems + j * kW + 8 * mg);
+        const uint32_t q[4] = {v.x, v.y, v.z, v.w};
+        uint16_t* dst = wb + (li * kW + 8 * mg) * kWp + swap23(j);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) dst[i * kWp] = (uint16_t)(q[i >> 1] >> (16 * (i & 1)));
     }
     for (int e = threadIdx.x; e < kW * 16; e += blockDim.x) {
         const int m = e / 16, k = e % 16;
@@ -130,28 +146,38 @@ __device__ void stage_backward(const uint16_t* __restrict__ w, uint16_t* wb, uin
 // b[ks] (ks = 0..3) is the B operand (this lane's sample, k-slots 16ks+8h..+7).
 // Layer output D (two 32-row tiles) is rounded to BF16 after ReLU and packed
 // back into b as bop[ks][j] = D[ks / 2][8 (ks % 2) + j].
+// ReLU and round to BF16 (nearest even, the hardware's packed conversion) of
+// d[base .. base + 7], packed as one B operand.
+__device__ __forceinline__ short8 relu_bf16x8(const f32x16& d, int base) {
+    uint32_t u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float x0 = d[base + 2 * q], x1 = d[base + 2 * q + 1];
+        const bf16x2 v = {(__bf16)(x0 > 0.0f ? x0 : 0.0f), (__bf16)(x1 > 0.0f ? x1 : 0.0f)};
+        u[q] = __builtin_bit_cast(uint32_t, v);
+    }
+    return __builtin_bit_cast(short8, make_uint4(u[0], u[1], u[2], u[3]));
+}
+
 __device__ __forceinline__ void hidden_layer(const uint16_t* wl, short8 (&b)[4], int l) {
     const int h = l >> 5, r = l & 31;
     f32x16 d0 = zero16(), d1 = zero16();
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-        d0 = mfma(lds8(wl + r * kW + 16 * ks + 8 * h), b[ks], d0);
-        d1 = mfma(lds8(wl + (32 + r) * kW + 16 * ks + 8 * h), b[ks], d1);
+        d0 = mfma(lds8(wl + r * kWp + 16 * ks + 8 * h), b[ks], d0);
+        d1 = mfma(lds8(wl + (32 + r) * kWp + 16 * ks + 8 * h), b[ks], d1);
     }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        b[0][j] = (short)f2bf(fmaxf(d0[j], 0.0f));
-        b[1][j] = (short)f2bf(fmaxf(d0[8 + j], 0.0f));
-        b[2][j] = (short)f2bf(fmaxf(d1[j], 0.0f));
-        b[3][j] = (short)f2bf(fmaxf(d1[8 + j], 0.0f));
-    }
+    b[0] = relu_bf16x8(d0, 0);
+    b[1] = relu_bf16x8(d0, 8);
+    b[2] = relu_bf16x8(d1, 0);
+    b[3] = relu_bf16x8(d1, 8);
 }
 
 __device__ __forceinline__ f32x16 output_layer(const uint16_t* w6, const short8 (&b)[4], int l) {
     const int h = l >> 5, r = l & 31;
     f32x16 d = zero16();
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) d = mfma(lds8(w6 + r * kW + 16 * ks + 8 * h), b[ks], d);
+    for (int ks = 0; ks < 4; ++ks) d = mfma(lds8(w6 + r * kWp + 16 * ks + 8 * h), b[ks], d);
     return d;   // lanes 0..31: d[0..2] = y of sample (l % 32)
 }
 
@@ -169,48 +195,97 @@ __device__ __forceinline__ void load_input(const uint16_t* __restrict__ x, int64
     }
 }
 
+constexpr int kFwdWaves = 8;         // waves per block of the inference kernel: two per SIMD
+constexpr int kFwdBlocksPerCu = 1;   // ~240 registers per lane (the weights below) leave room for two waves per SIMD
+
 // mode 0: y [n][3]; mode 1: acc[3 pix + c] += w_c * max(y_c, 0) (cache inference)
+// Every lane holds its A operands of all six layers in registers (44 x 16 bytes,
+// read once from the staged LDS copy), so the tile loop touches no LDS: per
+// 32-sample tile it is 44 matrix-core instructions, the ReLU/BF16 conversions
+// between them and the input read, whose next tile is fetched before the
+// current one is computed.  The second wave on each SIMD overlaps its
+// conversions and loads with this wave's matrix work.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_mlp_forward(const uint16_t* __restrict__ w, const uint16_t* __restrict__ x,
-                                                     int64_t n, float* __restrict__ y, const uint32_t* count_p,
-                                                     const uint32_t* __restrict__ pix, const float* __restrict__ wt,
-                                                     float* __restrict__ acc) {
+__global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const uint16_t* __restrict__ w,
+                                                                const uint16_t* __restrict__ x, int64_t n,
+                                                                float* __restrict__ y, const uint32_t* count_p,
+                                                                const uint32_t* __restrict__ pix,
+                                                                const float* __restrict__ wt, float* __restrict__ acc) {
     __shared__ __attribute__((aligned(16))) MlpLds S;
     stage_forward(w, S.wf);
     __syncthreads();
+    const int l = threadIdx.x & 63, h = l >> 5, r = l & 31;
+    short8 wa[5][2][4], wo[4];
+#pragma unroll
+    for (int layer = 0; layer < 5; ++layer)
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                wa[layer][mt][ks] = lds8(S.wf + (layer * kW + 32 * mt + r) * kWp + 16 * ks + 8 * h);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) wo[ks] = lds8(S.wf + (5 * kW + r) * kWp + 16 * ks + 8 * h);
     if (count_p) n = min((int64_t)*count_p, n);
-    const int l = threadIdx.x & 63;
-    const int64_t tiles = (n + 31) / 32;
-    for (int64_t t = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); t < tiles; t += (int64_t)gridDim.x * 4) {
-        const int64_t s = t * 32 + (l & 31);
+    const int64_t tiles = (n + 31) / 32, stride = (int64_t)gridDim.x * kFwdWaves;
+    int64_t t = (int64_t)blockIdx.x * kFwdWaves + (threadIdx.x >> 6);
+    short8 b[4];
+    if (t < tiles) load_input(x, t * 32 + r, t * 32 + r < n, l, b);
+    for (; t < tiles; t += stride) {
+        const int64_t s = t * 32 + r;
         const bool valid = s < n;
-        short8 b[4];
-        load_input(x, s, valid, l, b);
-        for (int layer = 0; layer < 5; ++layer) hidden_layer(S.wf + layer * kLayerElems, b, l);
-        const f32x16 d = output_layer(S.wf + 5 * kLayerElems, b, l);
+        short8 bn[4];
+        if (t + stride < tiles) load_input(x, s + 32 * stride, s + 32 * stride < n, l, bn);
+        // the accumulation target of this lane's sample, read before the matrix work hides its latency
+        uint32_t p = 0;
+        float w0 = 0.0f, w1 = 0.0f, w2 = 0.0f;
+        if (MODE == 1 && l < 32 && valid) {
+            p = pix[s];
+            w0 = wt[3 * s + 0];
+            w1 = wt[3 * s + 1];
+            w2 = wt[3 * s + 2];
+        }
+#pragma unroll
+        for (int layer = 0; layer < 5; ++layer) {
+            f32x16 d0 = zero16(), d1 = zero16();
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                d0 = mfma(wa[layer][0][ks], b[ks], d0);
+                d1 = mfma(wa[layer][1][ks], b[ks], d1);
+            }
+            b[0] = relu_bf16x8(d0, 0);
+            b[1] = relu_bf16x8(d0, 8);
+            b[2] = relu_bf16x8(d1, 0);
+            b[3] = relu_bf16x8(d1, 8);
+        }
+        f32x16 d = zero16();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) d = mfma(wo[ks], b[ks], d);
         if (l < 32 && valid) {
             if (MODE == 0) {
                 y[s * 3 + 0] = d[0];
                 y[s * 3 + 1] = d[1];
                 y[s * 3 + 2] = d[2];
             } else {
-                const uint32_t p = pix[s];
-                atomicAdd(acc + 3 * p + 0, wt[3 * s + 0] * fmaxf(d[0], 0.0f));
-                atomicAdd(acc + 3 * p + 1, wt[3 * s + 1] * fmaxf(d[1], 0.0f));
-                atomicAdd(acc + 3 * p + 2, wt[3 * s + 2] * fmaxf(d[2], 0.0f));
+                atomicAdd(acc + 3 * p + 0, w0 * fmaxf(d[0], 0.0f));
+                atomicAdd(acc + 3 * p + 1, w1 * fmaxf(d[1], 0.0f));
+                atomicAdd(acc + 3 * p + 2, w2 * fmaxf(d[2], 0.0f));
             }
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) b[q] = bn[q];
     }
 }
 
 // ----------------------------------------------------------------------------
 // forward + backward: accumulates dW (FP32, natural layout) and the loss sum
 // ----------------------------------------------------------------------------
-constexpr int kGradWaves = 2;   // waves per block of the training kernel (LDS budget)
+constexpr int kGradWaves = 2;   // waves per block of the training kernel (LDS budget); one 32-column dW tile each
+
+static_assert(kGradWaves == 2, "each wave of the training kernel reduces one of the two 32-column dW tiles");
 
 struct GradLds {
-    uint16_t wf[5 * kLayerElems + 32 * kW];
-    uint16_t wb[4 * kLayerElems];
+    uint16_t wf[kFwdRows * kWp];
+    uint16_t wb[4 * kW * kWp];
     uint16_t wb6[kW * 16];
     short8 act[kGradWaves][6][4][64];      // per wave, per layer: each lane's packed operand (input, h_1..h_5)
     uint16_t gy[kGradWaves][32 * 32];      // per wave: [channel (32 rows, 3 used)][sample]
@@ -244,23 +319,28 @@ __device__ __forceinline__ void store_input(uint16_t* dst, const short8 (&b)[4],
         for (int j = 0; j < 8; ++j) dst[(16 * ks + 8 * h + j) * 32 + r] = (uint16_t)b[ks][j];
 }
 
-// dW[m][n] += sum over the wave's 32 samples of A[m][s] B[n][s]  (A rows m_rows, B rows 64)
-__device__ __noinline__ void accumulate_dw(const uint16_t* a_fs, int m_rows, const uint16_t* b_fs, float* dw,
-                                           int dw_rows, int l) {
+// dW[m][n] += sum over the block's samples (32 per wave) of A[m][s] B[n][s]
+// (A rows m_rows, B rows 64; wave v's operands at a_fs + v a_stride and
+// b_fs + v b_stride).  This wave reduces the 32-column tile nt of every row
+// tile over all waves' samples, so each dW element takes one atomic add per
+// block rather than one per wave.
+__device__ __noinline__ void accumulate_dw(const uint16_t* a_fs, int a_stride, int m_rows, const uint16_t* b_fs,
+                                           int b_stride, float* dw, int dw_rows, int l, int nt) {
     const int h = l >> 5, r = l & 31;
-    for (int mt = 0; mt * 32 < m_rows; ++mt)
-        for (int nt = 0; nt < 2; ++nt) {
-            f32x16 d = zero16();
+    for (int mt = 0; mt * 32 < m_rows; ++mt) {
+        f32x16 d = zero16();
+#pragma unroll
+        for (int v = 0; v < kGradWaves; ++v)
 #pragma unroll
             for (int ks = 0; ks < 2; ++ks)
-                d = mfma(lds8(a_fs + (32 * mt + r) * 32 + 16 * ks + 8 * h),
-                         lds8(b_fs + (32 * nt + r) * 32 + 16 * ks + 8 * h), d);
+                d = mfma(lds8(a_fs + v * a_stride + (32 * mt + r) * 32 + 16 * ks + 8 * h),
+                         lds8(b_fs + v * b_stride + (32 * nt + r) * 32 + 16 * ks + 8 * h), d);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int m = 32 * mt + 8 * (i >> 2) + 4 * h + (i & 3);
-                if (m < dw_rows) atomicAdd(dw + m * kW + 32 * nt + r, d[i]);
-            }
+        for (int i = 0; i < 16; ++i) {
+            const int m = 32 * mt + 8 * (i >> 2) + 4 * h + (i & 3);
+            if (m < dw_rows) atomicAdd(dw + m * kW + 32 * nt + r, d[i]);
         }
+    }
 }
 
 __device__ __forceinline__ void load_act(const GradLds& S, int wave, int layer, int l, short8 (&b)[4]) {
@@ -295,11 +375,11 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __
 #pragma unroll
         for (int q = 0; q < 4; ++q) S.act[wave][0][q][l] = b[q];
         for (int k = 1; k < 6; ++k) {
-            hidden_layer(S.wf + (k - 1) * kLayerElems, b, l);
+            hidden_layer(S.wf + (k - 1) * kW * kWp, b, l);
 #pragma unroll
             for (int q = 0; q < 4; ++q) S.act[wave][k][q][l] = b[q];
         }
-        const f32x16 d = output_layer(S.wf + 5 * kLayerElems, b, l);
+        const f32x16 d = output_layer(S.wf + 5 * kW * kWp, b, l);
         // loss and g_y on lanes 0..31 (this lane's sample); g_y is BF16 like every product operand
         float gyv[3] = {0.0f, 0.0f, 0.0f};
         float lsum = 0.0f;
@@ -320,7 +400,7 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __
             for (int c = 0; c < 3; ++c) S.gy[wave][c * 32 + r] = f2bf(gyv[c]);
         store_dlayout(S.ht[wave], b, l);
         __syncthreads();
-        accumulate_dw(S.gy[wave], 32, S.ht[wave], dw + 5 * kLayerElems, 3, l);
+        accumulate_dw(S.gy[0], 32 * 32, 32, S.ht[0], kW * 32, dw + 5 * kLayerElems, 3, l, wave);
         // g_h5 = W6^T g_y  (K = channels, padded to 16)
         short8 bgy;
 #pragma unroll
@@ -343,15 +423,15 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __
             if (L - 1 >= 1) store_dlayout(S.ht[wave], hp, l);
             else store_input(S.ht[wave], hp, l);
             __syncthreads();
-            accumulate_dw(S.gz[wave], 64, S.ht[wave], dw + (L - 1) * kLayerElems, 64, l);
+            accumulate_dw(S.gz[0], kW * 32, 64, S.ht[0], kW * 32, dw + (L - 1) * kLayerElems, 64, l, wave);
             if (L > 1) {
-                const uint16_t* wbl = S.wb + (L - 2) * kLayerElems;
+                const uint16_t* wbl = S.wb + (L - 2) * kW * kWp;
                 gh0 = zero16();
                 gh1 = zero16();
 #pragma unroll
                 for (int ks = 0; ks < 4; ++ks) {
-                    gh0 = mfma(lds8(wbl + r * kW + 16 * ks + 8 * h), gz[ks], gh0);
-                    gh1 = mfma(lds8(wbl + (32 + r) * kW + 16 * ks + 8 * h), gz[ks], gh1);
+                    gh0 = mfma(lds8(wbl + r * kWp + 16 * ks + 8 * h), gz[ks], gh0);
+                    gh1 = mfma(lds8(wbl + (32 + r) * kWp + 16 * ks + 8 * h), gz[ks], gh1);
                 }
             }
         }
@@ -401,7 +481,8 @@ __global__ void k_mlp_adam(float* __restrict__ w, uint16_t* __restrict__ wb, flo
     g[i] = 0.0f;
 }
 
-static int grid_for(int64_t tiles, int per_block) {
+// blocks for `tiles` 32-sample tiles at per_block tiles per round, at most per_cu resident blocks per CU
+static int grid_for(int64_t tiles, int per_block, int per_cu) {
     static std::atomic<int> cu_count[64];   // per device, 0 = not queried yet
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
@@ -413,13 +494,14 @@ static int grid_for(int64_t tiles, int per_block) {
         }
     }
     const int64_t need = (tiles + per_block - 1) / per_block;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * 4));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * per_cu));
 }
 
 // internal launchers used by the renderer's cache frames
 rt_status mlp_infer_launch(const uint16_t* w, const uint16_t* x, int64_t cap, const uint32_t* count, const uint32_t* pix,
                            const float* wt, float* acc, hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_forward<1>, dim3(grid_for((cap + 31) / 32, 4)), dim3(256), 0, st, w, x, cap, nullptr, count,
+    hipLaunchKernelGGL(k_mlp_forward<1>, dim3(grid_for((cap + 31) / 32, kFwdWaves, kFwdBlocksPerCu)),
+                       dim3(64 * kFwdWaves), 0, st, w, x, cap, nullptr, count,
                        pix, wt, acc);
     HIP_TRY_M(hipGetLastError());
     return RT_OK;
@@ -427,7 +509,7 @@ rt_status mlp_infer_launch(const uint16_t* w, const uint16_t* x, int64_t cap, co
 
 rt_status mlp_grad_launch(const uint16_t* w, const uint16_t* x, const float* target, int64_t n, int64_t n_total,
                           const uint32_t* count, int64_t count_base, float* dw, float* loss, hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_grad, dim3(grid_for((n + 31) / 32, kGradWaves)), dim3(64 * kGradWaves), 0, st, w, x,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid_for((n + 31) / 32, kGradWaves, 4)), dim3(64 * kGradWaves), 0, st, w, x,
                        target, n, 1.0f / (3.0f * (float)n_total), count, count_base, dw, loss);
     HIP_TRY_M(hipGetLastError());
     return RT_OK;
@@ -455,18 +537,21 @@ rt_status mlp_adam_launch(float* w, uint16_t* wb, float* m, float* v, float* g, 
 
 using namespace mirt;
 
+static bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
 extern "C" {
 
 int32_t rt_mlp_num_params(void) { return kParams; }
 
 rt_status rt_mlp_forward(const uint16_t* w_bf16, const uint16_t* x_bf16, int64_t n, float* y, void* stream) {
-    if (n < 0 || (n > 0 && (!w_bf16 || !x_bf16 || !y))) {
-        set_error("rt_mlp_forward: invalid argument");
+    if (n < 0 || (n > 0 && (!w_bf16 || !x_bf16 || !y || !aligned16(w_bf16) || !aligned16(x_bf16)))) {
+        set_error("rt_mlp_forward: invalid argument (NULL pointer, n < 0 or w_bf16/x_bf16 not 16-byte aligned)");
         return RT_ERR_INVALID_ARG;
     }
     if (n == 0) return RT_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_mlp_forward<0>, dim3(grid_for((n + 31) / 32, 4)), dim3(256), 0, st, w_bf16, x_bf16, n, y,
+    hipLaunchKernelGGL(k_mlp_forward<0>, dim3(grid_for((n + 31) / 32, kFwdWaves, kFwdBlocksPerCu)),
+                       dim3(64 * kFwdWaves), 0, st, w_bf16, x_bf16, n, y,
                        nullptr, nullptr, nullptr, nullptr);
     HIP_TRY_M(hipGetLastError());
     return RT_OK;
@@ -474,8 +559,10 @@ rt_status rt_mlp_forward(const uint16_t* w_bf16, const uint16_t* x_bf16, int64_t
 
 rt_status rt_mlp_grad(const uint16_t* w_bf16, const uint16_t* x_bf16, const float* target, int64_t n, int64_t n_total,
                       float* dw, float* loss_sum, void* stream) {
-    if (n < 0 || n_total <= 0 || (n > 0 && (!w_bf16 || !x_bf16 || !target || !dw || !loss_sum))) {
-        set_error("rt_mlp_grad: invalid argument");
+    if (n < 0 || n_total <= 0 ||
+        (n > 0 && (!w_bf16 || !x_bf16 || !target || !dw || !loss_sum || !aligned16(w_bf16) || !aligned16(x_bf16)))) {
+        set_error("rt_mlp_grad: invalid argument (NULL pointer, n < 0, n_total <= 0 or w_bf16/x_bf16 not 16-byte "
+                  "aligned)");
         return RT_ERR_INVALID_ARG;
     }
     if (n == 0) return RT_OK;

@@ -245,3 +245,15 @@ def test_global_illumination_room_is_closed():
     t, ids, _ = oracle.closest(w.scene, o, d)
     assert (ids >= 0).all()
     assert w.params.gi == 1 and w.params.max_depth == 6
+
+
+def test_network_entry_points_reject_unaligned_operands_without_a_gpu():
+    """rt_mlp_forward / rt_mlp_grad read weights and features as 16-byte vectors: misaligned pointers are
+    argument errors, caught on the host before any device work."""
+    L = rt.lib()
+    for w, x in ((0x1002, 0x2000), (0x1000, 0x2008)):
+        assert L.rt_mlp_forward(w, x, 5, 0x3000, None) == -1
+        assert b"16-byte aligned" in L.rt_last_error()
+        assert L.rt_mlp_grad(w, x, 0x3000, 5, 5, 0x4000, 0x5000, None) == -1
+        assert b"16-byte aligned" in L.rt_last_error()
+    assert L.rt_mlp_forward(0x1000, 0x2000, 0, 0x3000, None) == 0      # nothing to do
