@@ -36,6 +36,7 @@ namespace mirt {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef short short8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
@@ -146,15 +147,17 @@ __device__ void stage_backward(const uint16_t* __restrict__ w, uint16_t* wb, uin
 // b[ks] (ks = 0..3) is the B operand (this lane's sample, k-slots 16ks+8h..+7).
 // Layer output D (two 32-row tiles) is rounded to BF16 after ReLU and packed
 // back into b as bop[ks][j] = D[ks / 2][8 (ks % 2) + j].
-// ReLU and round to BF16 (nearest even, the hardware's packed conversion) of
-// d[base .. base + 7], packed as one B operand.
+// ReLU and round to BF16 of d[base .. base + 7], packed as one B operand:
+// rounding (nearest even, the hardware's packed conversion) keeps the sign, so
+// the ReLU is applied after it as a signed 16-bit max with 0, which maps every
+// negative value and -0 to +0 and leaves the rest unchanged.
 __device__ __forceinline__ short8 relu_bf16x8(const f32x16& d, int base) {
     uint32_t u[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const float x0 = d[base + 2 * q], x1 = d[base + 2 * q + 1];
-        const bf16x2 v = {(__bf16)(x0 > 0.0f ? x0 : 0.0f), (__bf16)(x1 > 0.0f ? x1 : 0.0f)};
-        u[q] = __builtin_bit_cast(uint32_t, v);
+        const bf16x2 v = {(__bf16)d[base + 2 * q], (__bf16)d[base + 2 * q + 1]};
+        const s16x2 m = __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), (s16x2){0, 0});
+        u[q] = __builtin_bit_cast(uint32_t, m);
     }
     return __builtin_bit_cast(short8, make_uint4(u[0], u[1], u[2], u[3]));
 }
