@@ -65,7 +65,8 @@ def _problem(seed, n):
     return ws, feats, target
 
 
-@pytest.mark.parametrize("n", [1, 31, 100, 4099])
+# 200,003: more tiles than one round of the persistent grid (2,048 waves x 32 samples), ragged tail
+@pytest.mark.parametrize("n", [1, 31, 100, 4099, 200003])
 def test_forward_matches_oracle(rt, n):
     ws, feats, _ = _problem(1, n)
     w = rt.bf16_bits(torch.from_numpy(_flat(ws)).cuda())
@@ -76,7 +77,8 @@ def test_forward_matches_oracle(rt, n):
     assert np.abs(y - yo).max() < 2e-2 * (np.abs(yo).max() + 1e-3)
 
 
-@pytest.mark.parametrize("n", [32, 1000])
+# 70,001: more two-wave groups than training blocks (each block loops), ragged tail
+@pytest.mark.parametrize("n", [32, 1000, 70001])
 def test_gradients_match_oracle(rt, n):
     ws, feats, target = _problem(2, n)
     w = rt.bf16_bits(torch.from_numpy(_flat(ws)).cuda())
