@@ -207,7 +207,9 @@ constexpr int kFwdBlocksPerCu = 1;   // ~240 registers per lane (the weights bel
 // 32-sample tile it is 44 matrix-core instructions, the ReLU/BF16 conversions
 // between them and the input read, whose next tile is fetched before the
 // current one is computed.  The second wave on each SIMD overlaps its
-// conversions and loads with this wave's matrix work.
+// conversions and loads with this wave's matrix work.  In mode 1 the three
+// float atomic adds per query (many queries share a pixel) take about as long
+// as the network itself.
 template <int MODE>
 __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const uint16_t* __restrict__ w,
                                                                 const uint16_t* __restrict__ x, int64_t n,
