@@ -252,6 +252,30 @@ MLP_FWD_FLOP = 2 * (42 * 64 + 4 * 64 * 64 + 64 * 3)                    # 38,528 
 MLP_TRAIN_FLOP = MLP_FWD_FLOP + MLP_FWD_FLOP + 2 * (4 * 64 * 64 + 64 * 3)  # forward, dW, input grads: 110,208
 
 
+def mlp_store_only_tflops(cache, nq, reps=10):
+    """Rate of the network alone: rt_mlp_forward (outputs stored, no per-pixel atomic adds) with the cache's
+    weights on nq seeded random feature rows in [-1, 1); HIP events around reps launches on the current stream.
+    Set beside the cache form's rate it shows what the scatter into the pixels costs."""
+    import torch
+    from paper_1504_03151_amd import rt
+    if nq <= 0:
+        return None
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x = rt.bf16_bits(torch.rand(nq, 64, generator=g, device="cuda") * 2 - 1)
+    wb = cache.bf16_weights()
+    rt.mlp_forward(wb, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        rt.mlp_forward(wb, x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return nq * MLP_FWD_FLOP / (ms / 1e3) / 1e12
+
+
 def bench_cache(w, sc, plain, args):
     """Learned form vs the plain full-depth frame on the same scene, camera, samples and frame numbers.
 
@@ -344,6 +368,7 @@ def bench_cache(w, sc, plain, args):
     tr_ms = kt_c["cache_train"][0] / n
     inf_tflops = q * MLP_FWD_FLOP / (inf_ms / 1e3) / 1e12 if inf_ms > 0 else None
     tr_tflops = 65536 * MLP_TRAIN_FLOP / (tr_ms / 1e3) / 1e12 if tr_ms > 0 else None
+    so_tflops = mlp_store_only_tflops(cache, int(q))
     out = {
         "ms_per_frame": round(ms_c, 3), "plain_ms_per_frame": round(ms_p, 3),
         "speedup_vs_plain": round(ms_p / ms_c, 3),
@@ -364,13 +389,18 @@ def bench_cache(w, sc, plain, args):
                          "achieved": round(inf_tflops, 2) if inf_tflops else None,
                          "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(inf_tflops / MFMA_BF16_PEAK_TFLOPS, 4) if inf_tflops else None,
-                         "flop_per_query": MLP_FWD_FLOP, "traffic": None},
+                         "flop_per_query": MLP_FWD_FLOP, "traffic": None,
+                         "store_only": {"achieved": round(so_tflops, 2) if so_tflops else None,
+                                        "frac": round(so_tflops / MFMA_BF16_PEAK_TFLOPS, 4) if so_tflops else None,
+                                        "what": "rt_mlp_forward on as many random feature rows: outputs stored, "
+                                                "no per-pixel atomic adds"}},
         "mlp_train": {"achieved": round(tr_tflops, 2) if tr_tflops else None, "unit": "TFLOP/s",
                       "flop_per_sample": MLP_TRAIN_FLOP, "ms_per_frame": round(tr_ms, 3)},
     }
     log(f"cache {ms_c:.2f} ms vs plain {ms_p:.2f} ms ({ms_p / ms_c:.2f}x); rel-MSE {out['rel_mse']:.2e} "
         f"(affected {out['rel_mse_affected']:.2e}); truncation {out['truncation_rel_mse']:.2e} "
-        f"(affected {out['truncation_rel_mse_affected']:.2e}); infer {inf_tflops} TFLOP/s, train {tr_tflops} TFLOP/s")
+        f"(affected {out['truncation_rel_mse_affected']:.2e}); infer {inf_tflops} TFLOP/s (store-only {so_tflops}), "
+        f"train {tr_tflops} TFLOP/s")
     return out
 
 
