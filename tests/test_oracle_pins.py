@@ -295,6 +295,83 @@ def test_schlick_normal_incidence_r0():
     _close(rgb, 0.04 * np.array([0.25, 0.5, 0.75]), atol=1e-15)
 
 
+# Dielectric interface between two planes: the glass plane y = 0 (Schlick-weighted
+# reflection and refraction, ior 1.5, no local terms) and a plane y = -1 whose only
+# term is k_a * albedo = C (no lights).  A single camera ray along the optical axis
+# of a 65 x 65 image meets y = 0 at a chosen angle; max depth 1, so each secondary
+# ray returns either the background or C.
+BG = np.array([0.25, 0.5, 0.75])
+C_LOW = np.array([1.0, 0.125, 0.5])
+
+
+def _interface(eye, look_at):
+    glass = S.material((1, 1, 1), k_a=0.0, k_d=0.0, k_s=0.0, ior=1.5, mtype=S.DIELECTRIC)
+    low = S.material(tuple(C_LOW), k_a=1.0, k_d=0.0, k_s=0.0, k_r=0.0)
+    sc = S.make_scene(planes=[[0.0, 1.0, 0.0, 0.0], [0.0, 1.0, 0.0, -1.0]], plane_mat=[0, 1],
+                      materials=np.stack([glass, low]))
+    cam = S.Camera(eye, look_at, (0.0, 1.0, 0.0), 60.0, 65, 65)
+    p = S.Params(max_depth=1, bg=tuple(BG))
+    rec, rgb = oracle.ray_tree(sc, cam, p, 32 * 65 + 32)
+    return rec, rgb
+
+
+def test_schlick_entering_at_sixty_degrees():
+    # ray from above at 60 degrees to the normal: cos = 1/2 on the air side,
+    # F = 0.04 + 0.96 (1 - 1/2)^5 = 0.04 + 0.03 = 0.07 on the reflected ray (background)
+    # and 1 - F = 0.93 on the transmitted ray, which reaches the lower plane (C)
+    th = math.radians(60)
+    rec, rgb = _interface((-10 * math.sin(th), 10 * math.cos(th), 0.0), (0.0, 0.0, 0.0))
+    _close(rgb, 0.07 * BG + 0.93 * C_LOW, atol=1e-12)
+    # Snell: the transmitted ray leaves the normal at asin(sin 60 / 1.5)
+    tr = rec[(rec[:, 0] == 2) & (rec[:, 1] == 1)]
+    assert len(tr) == 1
+    st = math.sin(th) / 1.5
+    _close(tr[0, 5:8], [st, -math.sqrt(1 - st * st), 0.0], atol=1e-12)
+
+
+def test_schlick_leaving_glass_uses_the_air_side_cosine():
+    # ray inside the glass (below y = 0, going up) at sin(theta_i) = 1/sqrt(3):
+    # k^2 = 1 - 1.5^2 (1 - 2/3) = 1/4, so the air-side cosine is 1/2 (60 degrees out)
+    # and F = 0.07 again; with the glass-side cosine sqrt(2/3) F would be
+    # 0.04 + 0.96 (1 - 0.8165)^5 = 0.0402.  The reflected ray goes down to C,
+    # the transmitted one up to the background.
+    si = 1 / math.sqrt(3)
+    ci = math.sqrt(2.0 / 3.0)
+    eye = (-0.5 * si / ci, -0.5, 0.0)
+    rec, rgb = _interface(eye, (0.0, 0.0, 0.0))
+    _close(rgb, 0.07 * C_LOW + 0.93 * BG, atol=1e-12)
+    tr = rec[(rec[:, 0] == 2) & (rec[:, 1] == 1)]
+    assert len(tr) == 1
+    _close(tr[0, 5:8], [math.sqrt(3) / 2, 0.5, 0.0], atol=1e-12)      # 60 degrees from the normal in air
+
+
+def test_total_internal_reflection_reflects_everything():
+    # inside the glass at 60 degrees: sin = 0.866 > 1/1.5, k^2 = 1 - 2.25 * 0.75 < 0:
+    # F = 1, no transmitted ray, all of the radiance comes from the reflected ray (C)
+    th = math.radians(60)
+    eye = (-0.5 * math.tan(th), -0.5, 0.0)
+    rec, rgb = _interface(eye, (0.0, 0.0, 0.0))
+    _close(rgb, C_LOW, atol=1e-12)
+    assert ((rec[:, 0] == 2)).sum() == 0
+    assert ((rec[:, 0] == 1) & (rec[:, 1] == 1)).sum() == 1
+    # the critical angle asin(2/3) separates the two cases
+    for s, transmits in [(0.66, True), (0.67, False)]:
+        c = math.sqrt(1 - s * s)
+        rec, _ = _interface((-0.5 * s / c, -0.5, 0.0), (0.0, 0.0, 0.0))
+        assert ((rec[:, 0] == 2).sum() == 1) == transmits
+
+
+def test_phong_reflection_weight_k_r():
+    # head-on light, k_r = 0.3: local (as in the head-on pin) + 0.3 x the reflected ray,
+    # which leaves (0,0,-1) along -z and returns the background
+    mat = S.material(tuple(ALB), k_a=0.125, k_d=1.0, k_s=0.5, k_r=0.3)
+    w = S.one_sphere(center=(0.0, 0.0, 0.0), radius=1.0, light=(0.0, 0.0, -10.0), size=65, mat=mat)
+    w.params.max_depth = 1
+    w.params.bg = tuple(BG)
+    got = oracle.render(w.scene, w.camera, w.params, [32 * 65 + 32])["rgb"][0]
+    _close(got, 0.125 * ALB + ALB + 0.5 + float(np.float32(0.3)) * BG)    # k_r is stored in FP32
+
+
 def test_ball_lens_on_axis_and_snell_deviation():
     glass = S.material((1, 1, 1), k_a=0.0, k_d=0.0, k_s=0.0, ior=1.5, mtype=S.DIELECTRIC)
     w = S.one_sphere(center=(0.0, 0.0, 0.0), radius=1.0, size=65, mat=glass)
