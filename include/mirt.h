@@ -171,9 +171,19 @@ typedef struct {
 } rt_params;
 
 #define RT_STATS_MAX_DEPTH 16
+/* Bits of rt_stats.status.  The first three are faults (rays were dropped; a
+ * frame with RT_FLAG_SYNC returns RT_ERR_CAPACITY); RT_STATUS_CACHE_FALLBACK
+ * is a report: a learned-form frame found its cache state unhealthy and was
+ * rendered by the plain tracer instead (see rt_render_cached). */
+enum {
+    RT_STATUS_RAY_OVERFLOW = 1,      /* a closest-hit ray queue overflowed */
+    RT_STATUS_SHADOW_OVERFLOW = 2,   /* a shadow queue overflowed */
+    RT_STATUS_CACHE_RECORDS = 4,     /* the learned form's query records overflowed */
+    RT_STATUS_CACHE_FALLBACK = 8     /* the learned form fell back to the plain tracer */
+};
 /* Device-side counters, accumulated by rt_render (caller zeroes them). */
 typedef struct {
-    uint32_t status;          /* bit 0: ray queue overflow; bit 1: shadow queue overflow; bit 2: cache records */
+    uint32_t status;          /* RT_STATUS_* bits */
     uint32_t passes;
     uint64_t rays[RT_STATS_MAX_DEPTH];    /* closest-hit queries issued per depth */
     uint64_t shadow[RT_STATS_MAX_DEPTH];  /* shadow (any-hit) queries issued per depth */
@@ -262,13 +272,22 @@ size_t rt_render_batch_workspace_bytes(const rt_scene* const* scenes, const rt_c
 rt_status rt_render_batch(const rt_scene* const* scenes, const rt_camera* cams, const rt_params* params,
                           int32_t n, float* const* out_rgb, int32_t* const* out_hit_ids);
 
-/* Closest hit of n arbitrary rays.  rays: device float [n][8] = ox, oy, oz,
- * dx, dy, dz (unit length), tmin (ignored, the range is (0, tmax)), tmax
- * (<= 0 or inf: unbounded).  Outputs (device): t [n] (inf on a miss), id [n]
- * original ids (-1 miss).  workspace: device, >= 64 bytes (counters). */
-rt_status rt_intersect(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id,
+/* Closest hit of n arbitrary rays: Algorithm 1's object loop (the nearest
+ * object along the ray), through the BVH; spheres by Eq. 9-12.  rays: device
+ * float [n][8] = ox, oy, oz, dx, dy, dz (unit length), tmin (ignored, the
+ * range is (0, tmax)), tmax (<= 0 or inf: unbounded).  Outputs (device): t [n]
+ * (inf on a miss), id [n] original ids (-1 miss), and uv [n][2] (NULL: not
+ * written; 8-byte aligned) the hit's surface coordinates: for a triangle the
+ * barycentric weights (u, v) of its second and third vertex (hit point =
+ * (1-u-v) v0 + u v1 + v v2); for a sphere the outward normal n at the hit in
+ * spherical coordinates, u = (atan2(n_z, n_x) + pi) / (2 pi), v = acos(n_y) / pi;
+ * (0, 0) for planes and misses.  workspace: device, >= 64 bytes (counters).
+ * Errors: RT_ERR_INVALID_ARG (NULL buffers with n > 0, misaligned uv),
+ * RT_ERR_NOT_UPLOADED, RT_ERR_UNSUPPORTED (traversal stack beyond LDS). */
+rt_status rt_intersect(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id, float* uv,
                        void* workspace, void* stream);
-/* Any hit in (0, tmax) of n rays (same layout; tmax must be finite and > 0);
+/* Any hit in (0, tmax) of n rays: Algorithm 1's blocker loop for shadow rays,
+ * which stops at the first blocker (same layout; tmax must be finite and > 0);
  * occluded [n] device uint8 (1 = blocked). */
 rt_status rt_occluded(const rt_scene* scene, const float* rays, int64_t n, uint8_t* occluded, void* workspace,
                       void* stream);
@@ -320,8 +339,24 @@ rt_status rt_mlp_mfma_probe(const uint16_t* a, const uint16_t* b, float* d, void
  * train_samples of these queries (stratified, random per-frame offset), traces
  * their rays on to full_depth with the plain tracer (the training targets)
  * and takes train_steps Adam steps on the relative-L2 loss.  The image uses
- * the weights from before the frame's training. */
+ * the weights from before the frame's training.
+ *
+ * Health and fallback (the plain tracer is the learned form's fallback): after
+ * a frame's training steps the library checks the loss sums, the FP32 master
+ * weights and the Adam moments, and at the start of every learned-form frame
+ * the BF16 weights it is about to use; any non-finite value sets a health bit
+ * in the state.  A frame that starts with a health bit set answers no query:
+ * its hits at `depth` are shaded and traced on to params->max_depth by the
+ * plain tracer on the device (no host round trip), so the image is the plain
+ * frame's, and rt_stats.status reports RT_STATUS_CACHE_FALLBACK.  The bits
+ * stay set until rt_cache_init initialises the state again.  A healthy frame
+ * pays for the fallback chain's empty launches only (tens of microseconds). */
 enum { RT_CACHE_INFER = 1, RT_CACHE_TRAIN = 2 };
+enum {
+    RT_CACHE_HEALTH_LOSS = 1,        /* a training step's loss sum was not finite */
+    RT_CACHE_HEALTH_WEIGHTS = 2,     /* a master weight or Adam moment was not finite after training */
+    RT_CACHE_HEALTH_BF16 = 4         /* a BF16 weight was not finite at the start of a frame */
+};
 typedef struct {
     int32_t mode;              /* RT_CACHE_INFER or RT_CACHE_TRAIN */
     int32_t depth;             /* [2] depth whose hits query the network (>= 1) */
@@ -335,7 +370,8 @@ typedef struct {
 
 /* Byte offsets inside the cache state.  counters (uint32): [0] Adam steps
  * taken, [1] training samples of the last frame, [2..17] the last frame's
- * per-step loss sums (float bits; divide by 3 x slice size).  The last
+ * per-step loss sums (float bits; divide by 3 x slice size), [18] health bits
+ * (RT_CACHE_HEALTH_*; 0 = healthy).  The last
  * frame's training batch: train_rays [cap][6] (o, d at the cache depth),
  * train_feats [cap][64] BF16, train_targets [cap][3], train_pix [cap]
  * (accumulation slot of each sample's pixel). */

@@ -71,7 +71,7 @@ def lib():
                                     C.c_void_p, C.c_void_p]
             L.or_closest.restype = C.c_int
             L.or_closest.argtypes = [C.POINTER(_Scene), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
-                                     C.c_void_p, C.c_void_p]
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
             L.or_occluded.restype = C.c_int
             L.or_occluded.argtypes = [C.POINTER(_Scene), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
                                       C.c_void_p]
@@ -188,17 +188,21 @@ def _rays9(o, d, tmax=None, so=0.0, sd=0.0):
     return R
 
 
-def closest(scene, o, d, tmax=None, so=0.0, sd=0.0, nthreads: int = 0):
-    """Brute-force closest hit. tmax None/<=0 = infinite. Returns (t, id, margin)."""
+def closest(scene, o, d, tmax=None, so=0.0, sd=0.0, nthreads: int = 0, uv: bool = False):
+    """Brute-force closest hit. tmax None/<=0 = infinite. Returns (t, id, margin), and with uv=True
+    also the hit's surface coordinates [n, 2] (triangle barycentrics of v1 and v2; sphere longitude
+    and polar angle of the outward normal over 2 pi and pi; 0 for planes and misses)."""
     L = lib()
     R = _rays9(o, d, tmax, so, sd)
     n = len(R)
     t = np.zeros(n, np.float64)
     ids = np.zeros(n, np.int64)
     m = np.zeros(n, np.float64)
+    huv = np.zeros((n, 2), np.float64) if uv else None
     sc = OScene(scene)
-    L.or_closest(C.byref(sc.c), R.ctypes.data, n, nthreads, t.ctypes.data, ids.ctypes.data, m.ctypes.data)
-    return t, ids, m
+    L.or_closest(C.byref(sc.c), R.ctypes.data, n, nthreads, t.ctypes.data, ids.ctypes.data, m.ctypes.data,
+                 huv.ctypes.data if uv else None)
+    return (t, ids, m, huv) if uv else (t, ids, m)
 
 
 def occluded(scene, o, d, tmax, so=0.0, sd=0.0, nthreads: int = 0):

@@ -1061,7 +1061,50 @@ typedef struct {
     int64_t* id;
     uint8_t* occ;
     double* margin;
+    double* uv;
 } ray_job;
+
+/* Surface coordinates of a hit at ray parameter t on primitive id:
+ *   triangle: the barycentric weights (u, v) of its second and third vertex,
+ *     so that the hit point is (1-u-v) v0 + u v1 + v v2, from the edge
+ *     functions at the plane point (the same construction as eval_tri);
+ *   sphere: the unit outward normal n = (x - c)/r in spherical coordinates,
+ *     u = (atan2(n_z, n_x) + pi) / (2 pi) (longitude), v = acos(n_y) / pi
+ *     (polar angle from +y), both in [0, 1];
+ *   plane: (0, 0) (a plane carries no parameterisation). */
+static void hit_uv(const or_scene* sc, const oray* ray, int64_t id, double t, double* uv) {
+    uv[0] = uv[1] = 0.0;
+    if (id < 0) return;
+    double p[3];
+    for (int k = 0; k < 3; ++k) p[k] = ray->o[k] + t * ray->d[k];
+    if (id < sc->n_spheres) {
+        const float* s = sc->spheres + 4 * id;
+        double n[3];
+        for (int k = 0; k < 3; ++k) n[k] = (p[k] - (double)s[k]) / (double)s[3];
+        const double ny = fmax(-1.0, fmin(1.0, n[1]));
+        uv[0] = (atan2(n[2], n[0]) + M_PI) / (2.0 * M_PI);
+        uv[1] = acos(ny) / M_PI;
+    } else if (id < sc->n_spheres + sc->n_tris) {
+        const float* tv = sc->tris + 9 * (id - sc->n_spheres);
+        double v0[3], v1[3], v2[3], e1[3], e2[3], n[3], a[3], b[3], q[3];
+        load3f(v0, tv);
+        load3f(v1, tv + 3);
+        load3f(v2, tv + 6);
+        sub3(e1, v1, v0);
+        sub3(e2, v2, v0);
+        cross3(n, e1, e2);
+        const double nn = dot3(n, n);
+        /* weight of v1: the edge v2 -> v0 seen from p; weight of v2: the edge v0 -> v1 */
+        sub3(a, v2, p);
+        sub3(b, v0, p);
+        cross3(q, a, b);
+        uv[0] = dot3(n, q) / nn;
+        sub3(a, v0, p);
+        sub3(b, v1, p);
+        cross3(q, a, b);
+        uv[1] = dot3(n, q) / nn;
+    }
+}
 
 static void load_ray(const double* R, oray* r) {
     for (int i = 0; i < 3; ++i) { r->o[i] = R[i]; r->d[i] = R[3 + i]; }
@@ -1079,6 +1122,7 @@ static void closest_one(void* vctx, int64_t i) {
     J->t[i] = h.t;
     J->id[i] = h.id;
     J->margin[i] = h.margin;
+    if (J->uv) hit_uv(J->S->in, &r, h.id, h.t, J->uv + 2 * i);
 }
 
 static void occluded_one(void* vctx, int64_t i) {
@@ -1090,12 +1134,13 @@ static void occluded_one(void* vctx, int64_t i) {
     J->margin[i] = m;
 }
 
-/* rays [n][9]: o(3), d(3), tmax (<= 0 means infinite), so, sd */
+/* rays [n][9]: o(3), d(3), tmax (<= 0 means infinite), so, sd; uv [n][2]
+ * (or NULL) receives the hit's surface coordinates (see hit_uv) */
 int or_closest(const or_scene* sc, const double* rays, int64_t n, int32_t nthreads, double* t, int64_t* id,
-               double* margin) {
+               double* margin, double* uv) {
     oscene S;
     if (oscene_init(&S, sc) != 0) return -2;
-    ray_job J = {&S, rays, t, id, NULL, margin};
+    ray_job J = {&S, rays, t, id, NULL, margin, uv};
     run_parallel(n, nthreads, closest_one, &J);
     oscene_free(&S);
     return 0;
@@ -1105,7 +1150,7 @@ int or_occluded(const or_scene* sc, const double* rays, int64_t n, int32_t nthre
                 double* margin) {
     oscene S;
     if (oscene_init(&S, sc) != 0) return -2;
-    ray_job J = {&S, rays, NULL, NULL, occ, margin};
+    ray_job J = {&S, rays, NULL, NULL, occ, margin, NULL};
     run_parallel(n, nthreads, occluded_one, &J);
     oscene_free(&S);
     return 0;

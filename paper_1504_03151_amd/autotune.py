@@ -111,11 +111,10 @@ def tune(scenes: Sequence["rt.Scene"], cameras, params, batch: bool = True, warm
     import numpy as np
     space = space or SPACE
     key = f"{_device_name()}|{'batch' if batch else 'seq'}|{signature(scenes, cameras, params)}"
-    if cache_path and os.path.exists(cache_path):
-        with open(cache_path) as f:
-            db = json.load(f)
-        if key in db:
-            res = dict(db[key], cached=True)
+    if cache_path:
+        hit = read_cache(cache_path, key, log)
+        if hit is not None:
+            res = dict(hit, cached=True)
             _Workload(scenes, cameras, params, batch)._set_layout(res["config"]["layout"])
             return res
     W = _Workload(scenes, cameras, params, batch)
@@ -151,12 +150,55 @@ def tune(scenes: Sequence["rt.Scene"], cameras, params, batch: bool = True, warm
     res = {"config": best, "ms": round(best_ms, 4), "default_ms": round(default_ms, 4), "trials": trials,
            "key": key, "cached": False}
     if cache_path:
-        db = {}
-        if os.path.exists(cache_path):
-            with open(cache_path) as f:
-                db = json.load(f)
-        db[key] = {k: v for k, v in res.items() if k != "cached"}
-        os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
-        with open(cache_path, "w") as f:
-            json.dump(db, f, indent=1)
+        write_cache(cache_path, key, {k: v for k, v in res.items() if k != "cached"})
     return res
+
+
+def _load_db(path: str, log: Optional[Callable[[str], None]] = None) -> dict:
+    """The cache file as a dict; an unreadable or malformed file counts as empty (and is reported)."""
+    if not os.path.exists(path):
+        return {}
+    try:
+        with open(path) as f:
+            db = json.load(f)
+    except (OSError, ValueError) as e:
+        if log:
+            log(f"autotune cache {path} unreadable ({e.__class__.__name__}): using defaults and tuning afresh")
+        return {}
+    if not isinstance(db, dict):
+        if log:
+            log(f"autotune cache {path} is not a JSON object: ignored")
+        return {}
+    return db
+
+
+def _valid_entry(e) -> bool:
+    if not isinstance(e, dict) or not isinstance(e.get("config"), dict):
+        return False
+    cfg = e["config"]
+    return (set(cfg) == set(SPACE) and all(isinstance(cfg[k], int) and cfg[k] in SPACE[k] for k in SPACE)
+            and isinstance(e.get("ms"), (int, float)))
+
+
+def read_cache(path: str, key: str, log: Optional[Callable[[str], None]] = None) -> Optional[dict]:
+    """The cached result for key, or None when the file is missing, corrupt, or its entry is malformed
+    (a setting outside the search space is never applied: the caller tunes afresh)."""
+    e = _load_db(path, log).get(key)
+    if e is None:
+        return None
+    if not _valid_entry(e):
+        if log:
+            log(f"autotune cache entry {key} malformed: ignored")
+        return None
+    return e
+
+
+def write_cache(path: str, key: str, entry: dict) -> None:
+    """Add or replace one entry; the file is replaced atomically, so a crash never leaves half a file."""
+    db = _load_db(path)
+    db[key] = entry
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = f"{path}.tmp{os.getpid()}"
+    with open(tmp, "w") as f:
+        json.dump(db, f, indent=1)
+    os.replace(tmp, path)

@@ -486,6 +486,26 @@ __global__ void k_mlp_adam(float* __restrict__ w, uint16_t* __restrict__ wb, flo
     g[i] = 0.0f;
 }
 
+// Health of the learned form after a frame's training steps: bit 0 of *health
+// when one of the steps' loss sums (float bits in loss_bits[0 .. steps)) is
+// not finite, bit 1 when a master weight or an Adam moment is not.  Bits are
+// only ever added; rt_cache_init clears them.  One block.
+__global__ __launch_bounds__(256) void k_mlp_health(const float* __restrict__ w, const float* __restrict__ m,
+                                                    const float* __restrict__ v, int n,
+                                                    const uint32_t* __restrict__ loss_bits, int steps,
+                                                    uint32_t* health) {
+    __shared__ uint32_t bad;
+    if (threadIdx.x == 0) bad = 0u;
+    __syncthreads();
+    uint32_t mine = 0u;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if (!isfinite(w[i]) || !isfinite(m[i]) || !isfinite(v[i])) mine = 2u;
+    if ((int)threadIdx.x < steps && !isfinite(__uint_as_float(loss_bits[threadIdx.x]))) mine |= 1u;
+    if (mine) atomicOr(&bad, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && bad) *health |= bad;
+}
+
 // blocks for `tiles` 32-sample tiles at per_block tiles per round, at most per_cu resident blocks per CU
 static int grid_for(int64_t tiles, int per_block, int per_cu) {
     static std::atomic<int> cu_count[64];   // per device, 0 = not queried yet
@@ -516,6 +536,13 @@ rt_status mlp_grad_launch(const uint16_t* w, const uint16_t* x, const float* tar
                           const uint32_t* count, int64_t count_base, float* dw, float* loss, hipStream_t st) {
     hipLaunchKernelGGL(k_mlp_grad, dim3(grid_for((n + 31) / 32, kGradWaves, 4)), dim3(64 * kGradWaves), 0, st, w, x,
                        target, n, 1.0f / (3.0f * (float)n_total), count, count_base, dw, loss);
+    HIP_TRY_M(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status mlp_health_launch(const float* w, const float* m, const float* v, const uint32_t* loss_bits, int steps,
+                           uint32_t* health, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_health, dim3(1), dim3(256), 0, st, w, m, v, kParams, loss_bits, steps, health);
     HIP_TRY_M(hipGetLastError());
     return RT_OK;
 }

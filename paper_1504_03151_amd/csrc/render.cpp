@@ -1237,6 +1237,41 @@ __global__ void k_cache_select(const uint32_t* ctr, CacheRec rec, RayQ qsrc, uin
     t_pix[j] = rec.pix[src];
 }
 
+// Cache-state counter words: [0] Adam steps, [1] training samples of the last
+// frame, [2 .. 18) the last frame's per-step loss sums, [kCacheHealth] health
+// bits (bit 0 a non-finite loss sum, bit 1 a non-finite master weight or Adam
+// moment after training, bit 2 a non-finite BF16 weight at the start of a
+// frame).  Bits stay set until the state is initialised again.
+constexpr int kCacheHealth = 18;
+
+// The learned form's gate, between the closest hits at the cache depth and
+// their shading.  A healthy cache leaves the frame as it is.  An unhealthy one
+// (any health bit, or a non-finite BF16 weight now) hands the depth's hits to
+// the fallback chain: their count moves from the frame's counters to the
+// chain's, so the network sees no query and the plain tracer shades them and
+// carries their paths on to the full depth.  One block.
+__global__ __launch_bounds__(256) void k_cache_gate(const uint16_t* wb, int n, uint32_t* health, uint32_t* ctr,
+                                                    uint32_t* ctr_fb, int depth, rt_stats* st) {
+    __shared__ uint32_t bad;
+    if (threadIdx.x == 0) bad = 0u;
+    __syncthreads();
+    uint32_t mine = 0u;
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        if ((wb[i] & 0x7F80u) == 0x7F80u) mine = 4u;   // BF16 exponent all ones: Inf or NaN
+    if (mine) atomicOr(&bad, mine);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    uint32_t h = *health;
+    if (bad) {
+        h |= bad;
+        *health = h;
+    }
+    if (h == 0u) return;
+    ctr_fb[kCtrRays + depth] = ctr[kCtrRays + depth];
+    ctr[kCtrRays + depth] = 0u;
+    if (st) atomicOr(&st->status, (uint32_t)RT_STATUS_CACHE_FALLBACK);
+}
+
 __global__ void k_resolve(const float* acc, float* out, int64_t n3, float inv_spp, const uint32_t* accum) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n3) out[i] = acc[i] * (inv_spp / (float)(*accum + 1u));
@@ -1250,7 +1285,8 @@ __global__ void k_clear_acc(float* acc, int64_t n, const uint32_t* accum) {
 
 // fold a pass's queue counters into the caller's statistics
 // part 0: a frame's pass; 1: a learned-form frame (also its network queries);
-// 2: the rays traced for training targets (kept apart from the image's rays)
+// 2: the rays traced for training targets (kept apart from the image's rays);
+// 3: the learned form's fallback chain (rays of the frame's own pass)
 __global__ void k_stats(const uint32_t* ctr, rt_stats* st, int max_depth, int part) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (!st) return;
@@ -1265,7 +1301,7 @@ __global__ void k_stats(const uint32_t* ctr, rt_stats* st, int max_depth, int pa
         st->target_shadow += s;
         return;
     }
-    st->passes += 1;
+    if (part != 3) st->passes += 1;   // part 3: the learned form's fallback chain (depths of the same pass)
     for (int k = 0; k <= max_depth && k < RT_STATS_MAX_DEPTH; ++k) {
         st->rays[k] += (uint64_t)ctr[kCtrRays + k] - (k == 0 ? (uint64_t)ctr[kCtrDead] : 0ull);
         st->shadow[k] += (uint64_t)ctr[kCtrShadow + k];
@@ -1290,10 +1326,40 @@ __global__ void k_load_rays(const float* rays, int64_t n, RayQ q, ShadowQ s, int
     }
 }
 
+// Surface coordinates of a closest hit (rt_intersect's uv output).  Triangle:
+// the barycentric weights of its second and third vertex, V/det and W/det of
+// the watertight test's edge functions (U goes with the first vertex), so
+// that the hit point is (1-u-v) v0 + u v1 + v v2.  Sphere: the outward
+// normal n = (x - c)/r at x = o + t d in spherical coordinates, u =
+// (atan2(n_z, n_x) + pi) / (2 pi), v = acos(n_y) / pi.  Planes and misses: 0.
+__device__ float2 hit_uv(const DevScene& sc, const TRay& r, const Hit& h) {
+#pragma clang fp contract(off)
+    if (h.prim < 0 || h.prim >= sc.n_bvh) return make_float2(0.0f, 0.0f);
+    const float4 p0 = sc.prims[3 * h.prim], p1 = sc.prims[3 * h.prim + 1];
+    if (h.id < sc.n_spheres) {
+        const V3 x = r.o + h.t * r.d;
+        const V3 n = (x - xyz(p0)) * p1.z;
+        const float ny = fminf(1.0f, fmaxf(-1.0f, n.y));
+        const float kPi = 3.14159265358979f;
+        return make_float2((atan2f(n.z, n.x) + kPi) / (2.0f * kPi), acosf(ny) / kPi);
+    }
+    const float4 p2 = sc.prims[3 * h.prim + 2];
+    const V3 A = xyz(p0) - r.o, B = xyz(p1) - r.o, C = xyz(p2) - r.o;
+    const float Az = sel(A, r.kz), Bz = sel(B, r.kz), Cz = sel(C, r.kz);
+    const float Ax = sel(A, r.kx) - r.sx * Az, Ay = sel(A, r.ky) - r.sy * Az;
+    const float Bx = sel(B, r.kx) - r.sx * Bz, By = sel(B, r.ky) - r.sy * Bz;
+    const float Cx = sel(C, r.kx) - r.sx * Cz, Cy = sel(C, r.ky) - r.sy * Cz;
+    const float U = Cx * By - Cy * Bx, V = Ax * Cy - Ay * Cx, W = Bx * Ay - By * Ax;
+    const float det = U + V + W;
+    if (det == 0.0f) return make_float2(0.0f, 0.0f);
+    return make_float2(V / det, W / det);
+}
+
 // Persistent kernels over caller rays (rt_intersect / rt_occluded): same traversal.
 template <bool ANY>
 __global__ __launch_bounds__(256) void k_trace_rays(DevScene sc, const float* rays, int64_t n, float* t_out,
-                                                    int32_t* id_out, uint8_t* occ_out, uint32_t* cursor) {
+                                                    int32_t* id_out, float2* uv_out, uint8_t* occ_out,
+                                                    uint32_t* cursor) {
     extern __shared__ int32_t smem[];
     LdsStack stk = lds_stack(smem, sc.stack_size);
     Work w{0, 0, 0};
@@ -1314,6 +1380,7 @@ __global__ __launch_bounds__(256) void k_trace_rays(DevScene sc, const float* ra
             } else {
                 t_out[i] = h.prim >= 0 ? h.t : INFINITY;
                 id_out[i] = h.prim >= 0 ? h.id : -1;
+                if (uv_out) uv_out[i] = hit_uv(sc, r, h);
             }
         }
     }
@@ -2106,6 +2173,8 @@ rt_status mlp_grad_launch(const uint16_t* w, const uint16_t* x, const float* tar
                           const uint32_t* count, int64_t count_base, float* dw, float* loss, hipStream_t st);
 rt_status mlp_adam_dev_launch(float* w, uint16_t* wb, float* m, float* v, float* g, const uint32_t* step_p, float lr,
                               float b1, float b2, float eps, hipStream_t st);
+rt_status mlp_health_launch(const float* w, const float* m, const float* v, const uint32_t* loss_bits, int steps,
+                            uint32_t* health, hipStream_t st);
 
 constexpr int kMlpParams = 5 * 64 * 64 + 3 * 64;
 constexpr int kTargetGrowth = 4;    // target-wavefront queue capacity per training sample
@@ -2145,7 +2214,7 @@ struct CachePlan {
     rt_cache_layout L;
     uint32_t rec_cap = 0, tcap = 0, tscap = 0;
     size_t off_rec = 0, off_tq[2] = {0, 0}, off_thit = 0, off_ts = 0, off_tbin = 0, off_tbins = 0, off_tctr = 0,
-           total = 0;
+           off_fbctr = 0, total = 0;
 };
 
 static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_params& p, const rt_cache* cache,
@@ -2184,8 +2253,10 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
         if (!(c.bounds_hi[k] > c.bounds_lo[k])) c.bounds_hi[k] = c.bounds_lo[k] + 1.0f;
     rt_params q = p;
     q.samples_per_pass = p.spp;   // cache frames trace every sample in one pass
-    // path tracing: the image's paths are shaded only above the cache depth, which bounds their shadow rays
-    if (p.flags & RT_FLAG_GI) q.max_depth = std::max(0, std::min(p.max_depth, c.depth - 1));
+    // path tracing: the image's paths are shaded above the cache depth, and by the fallback chain (an
+    // unhealthy cache) from it to max_depth; the larger of the two bounds the deferred shadow queue
+    if (p.flags & RT_FLAG_GI)
+        q.max_depth = std::max(0, std::min(p.max_depth, std::max(c.depth - 1, p.max_depth - c.depth)));
     if (!make_plan(h, cam, q, cp.base, why)) return false;
     cp.c = c;
     if (!cache_layout(c.train_samples, cp.L)) {
@@ -2217,6 +2288,8 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
     cp.off_tbins = off;   // its per-bin counts and first slots
     off = a256(off + 2 * 4 * (size_t)kBinMax);
     cp.off_tctr = off;
+    off = a256(off + 4 * kCtrTotal);
+    cp.off_fbctr = off;   // counters of the fallback chain
     off = a256(off + 4 * kCtrTotal);
     cp.total = off;
     return true;
@@ -2304,8 +2377,11 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     sq.key = reinterpret_cast<uint32_t*>(A.ws + pl.off_s2);
 
     const int64_t n3 = 3 * pl.nacc;
+    uint32_t* ctr_fb = reinterpret_cast<uint32_t*>(A.ws + cp.off_fbctr);
+    uint32_t* health = counters + kCacheHealth;
     hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, n3, 0.0f);
     clear_counters(ctr, st);
+    clear_counters(ctr_fb, st);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, ctr + kCtrRec, 1);
     if (A.shc.light_pts) {
         const int n = A.spp * A.sc.n_lights;
@@ -2326,6 +2402,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
                            ctr + kCtrRays + cd, xcd_cursor(ctr, kCtrRayCur + cd), pl.qcap, A.chunk, overflow,
                            nullptr);
     }
+    hipLaunchKernelGGL(k_cache_gate, dim3(1), dim3(256), 0, st, w_bf16, kMlpParams, health, ctr, ctr_fb, cd,
+                       A.stats);
     const float ie[3] = {1.0f / (cc.bounds_hi[0] - cc.bounds_lo[0]), 1.0f / (cc.bounds_hi[1] - cc.bounds_lo[1]),
                          1.0f / (cc.bounds_hi[2] - cc.bounds_lo[2])};
     hipLaunchKernelGGL(k_cache_shade, dim3(A.shade_blocks), dim3(256), 0, st, A.sc, A.shc, q[cd & 1], hq, ctr, cd, rec,
@@ -2336,6 +2414,22 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         if (rs != RT_OK) return rs;
     }
     hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr, A.stats, cd, 1);
+    // Fallback chain: the plain tracer from the cache depth to max_depth.  Its counters hold the depth's hits
+    // only when the gate found the cache unhealthy; otherwise every launch finds empty queues and returns.
+    // It reuses the image's ray, hit and shadow queues, whose earlier contents are consumed by now.
+    {
+        KernelTimer kt(A.time_kernels, st, 1);
+        if (A.shc.gi)
+            hipLaunchKernelGGL((k_shade<false, true>), dim3(A.shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr,
+                               q[cd & 1], hq, ctr_fb, cd, q[(cd + 1) & 1], sq, acc);
+        else
+            hipLaunchKernelGGL((k_shade<false, false>), dim3(A.shade_blocks), dim3(256), 0, st, A.sc, A.shc, nullptr,
+                               q[cd & 1], hq, ctr_fb, cd, q[(cd + 1) & 1], sq, acc);
+    }
+    for (int k = cd + 1; k <= A.shc.max_depth; ++k) bounce(q[k & 1], q[(k + 1) & 1], hq, sq, ctr_fb, A.shc, acc, k);
+    shadows(sq, ctr_fb, pl.scap, reinterpret_cast<uint32_t*>(A.ws + pl.off_s2 + sstride),
+            reinterpret_cast<uint32_t*>(A.ws + pl.off_bins), acc);
+    hipLaunchKernelGGL(k_stats, dim3(1), dim3(64), 0, st, ctr_fb, A.stats, A.shc.max_depth, 3);
 
     if (cc.mode == RT_CACHE_TRAIN) {
         uint32_t* tctr = reinterpret_cast<uint32_t*>(A.ws + cp.off_tctr);
@@ -2380,6 +2474,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
             rs = mlp_adam_dev_launch(wm, wb, m, v, g, counters + 0, cc.lr, cc.b1, cc.b2, cc.eps, st);
             if (rs != RT_OK) return rs;
         }
+        rt_status rs = mlp_health_launch(wm, m, v, counters + 2, cc.train_steps, health, st);
+        if (rs != RT_OK) return rs;
     }
     hipLaunchKernelGGL(k_resolve, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, st, acc, A.out_rgb, n3,
                        A.shc.per_sample ? 1.0f : 1.0f / (float)A.spp, ctr + kCtrAccum);
@@ -2552,8 +2648,8 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     return RT_OK;
 }
 
-static rt_status trace_rays(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id, uint8_t* occ,
-                            void* workspace, void* stream, bool any) {
+static rt_status trace_rays(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id, float* uv,
+                            uint8_t* occ, void* workspace, void* stream, bool any) {
     if (!scene || (n > 0 && (!rays || (any ? !occ : (!t || !id)))) || n < 0 || !workspace) {
         set_error("rt_intersect/rt_occluded: invalid argument");
         return RT_ERR_INVALID_ARG;
@@ -2583,22 +2679,27 @@ static rt_status trace_rays(const rt_scene* scene, const float* rays, int64_t n,
     rt_status rs = any ? persistent_grid(k_trace_rays<true>, lds, g) : persistent_grid(k_trace_rays<false>, lds, g);
     if (rs != RT_OK) return rs;
     g = (int)std::min<int64_t>(g, (n + 255) / 256);
+    float2* uv2 = reinterpret_cast<float2*>(uv);
     if (any)
-        hipLaunchKernelGGL(k_trace_rays<true>, dim3(g), dim3(256), lds, st, sc, rays, n, t, id, occ, cursor);
+        hipLaunchKernelGGL(k_trace_rays<true>, dim3(g), dim3(256), lds, st, sc, rays, n, t, id, uv2, occ, cursor);
     else
-        hipLaunchKernelGGL(k_trace_rays<false>, dim3(g), dim3(256), lds, st, sc, rays, n, t, id, occ, cursor);
+        hipLaunchKernelGGL(k_trace_rays<false>, dim3(g), dim3(256), lds, st, sc, rays, n, t, id, uv2, occ, cursor);
     HIP_TRY(hipGetLastError());
     return RT_OK;
 }
 
-rt_status rt_intersect(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id, void* workspace,
-                       void* stream) {
-    return trace_rays(scene, rays, n, t, id, nullptr, workspace, stream, false);
+rt_status rt_intersect(const rt_scene* scene, const float* rays, int64_t n, float* t, int32_t* id, float* uv,
+                       void* workspace, void* stream) {
+    if (uv && (reinterpret_cast<uintptr_t>(uv) & 7u)) {
+        set_error("rt_intersect: uv must be 8-byte aligned");
+        return RT_ERR_INVALID_ARG;
+    }
+    return trace_rays(scene, rays, n, t, id, uv, nullptr, workspace, stream, false);
 }
 
 rt_status rt_occluded(const rt_scene* scene, const float* rays, int64_t n, uint8_t* occluded, void* workspace,
                       void* stream) {
-    return trace_rays(scene, rays, n, nullptr, nullptr, occluded, workspace, stream, true);
+    return trace_rays(scene, rays, n, nullptr, nullptr, nullptr, occluded, workspace, stream, true);
 }
 
 
@@ -2745,7 +2846,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
         if (A.stats) {
             uint32_t status = 0;
             HIP_TRY(hipMemcpy(&status, &A.stats->status, 4, hipMemcpyDeviceToHost));
-            if (status) {
+            if (status & ~(uint32_t)RT_STATUS_CACHE_FALLBACK) {
                 set_error("rt_render_cached: queue overflow (status " + std::to_string(status) + ")");
                 return RT_ERR_CAPACITY;
             }

@@ -99,6 +99,8 @@ class CacheLayout(C.Structure):
 
 
 CACHE_INFER, CACHE_TRAIN = 1, 2
+CACHE_HEALTH_LOSS, CACHE_HEALTH_WEIGHTS, CACHE_HEALTH_BF16 = 1, 2, 4
+STATUS_RAY_OVERFLOW, STATUS_SHADOW_OVERFLOW, STATUS_CACHE_RECORDS, STATUS_CACHE_FALLBACK = 1, 2, 4, 8
 LAYOUT_DFS, LAYOUT_BFS, LAYOUT_TREELET, LAYOUT_BVH4, LAYOUT_BVH4Q = 0, 1, 2, 3, 4
 NODE_BYTES = {0: 64, 1: 64, 2: 64, 3: 128, 4: 64}   # bytes fetched per node visit, by layout
 TILE_8X8, TILE_16X4, TILE_32X2, TILE_4X16 = 0, 1, 2, 3
@@ -119,7 +121,7 @@ SIGNATURES = {
     "rt_render": (C.c_int32, [_P, C.POINTER(CameraC), C.POINTER(ParamsC), _P, _P]),
     "rt_render_batch_workspace_bytes": (C.c_size_t, [_P, _P, _P, C.c_int32]),
     "rt_render_batch": (C.c_int32, [_P, _P, _P, C.c_int32, _P, _P]),
-    "rt_intersect": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P]),
+    "rt_intersect": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P, _P, _P]),
     "rt_occluded": (C.c_int32, [_P, _P, C.c_int64, _P, _P, _P]),
     "rt_host_trace": (C.c_int32, [_P, _P, C.c_int64, C.c_int32, _P, _P, _P, C.c_int32]),
     "rt_kernel_times": (C.c_int32, [_P, _P, C.c_int32]),
@@ -440,7 +442,7 @@ def render(scene: Scene, camera, params, flags=FLAG_SYNC, **kw):
     return rgb, ids, st
 
 
-def _trace(scene: Scene, rays, any_hit: bool, stream=None):
+def _trace(scene: Scene, rays, any_hit: bool, stream=None, want_uv: bool = False):
     import torch
     if scene.blob is None:
         scene.upload()
@@ -455,14 +457,17 @@ def _trace(scene: Scene, rays, any_hit: bool, stream=None):
         return occ
     t = torch.empty(n, dtype=torch.float32, device=rays.device)
     ids = torch.empty(n, dtype=torch.int32, device=rays.device)
-    _check(L.rt_intersect(scene.handle, rays.data_ptr(), n, t.data_ptr(), ids.data_ptr(), ws.data_ptr(),
-                          _stream_ptr(stream)), "rt_intersect")
-    return t, ids
+    uv = torch.empty((n, 2), dtype=torch.float32, device=rays.device) if want_uv else None
+    _check(L.rt_intersect(scene.handle, rays.data_ptr(), n, t.data_ptr(), ids.data_ptr(),
+                          uv.data_ptr() if want_uv else None, ws.data_ptr(), _stream_ptr(stream)), "rt_intersect")
+    return (t, ids, uv) if want_uv else (t, ids)
 
 
-def intersect(scene: Scene, rays, stream=None):
-    """Closest hit of device rays [n,8] (o, d, tmin, tmax) -> (t [n], id [n]) device tensors."""
-    return _trace(scene, rays, False, stream)
+def intersect(scene: Scene, rays, stream=None, uv: bool = False):
+    """Closest hit of device rays [n,8] (o, d, tmin, tmax) -> (t [n], id [n]) device tensors, and with
+    uv=True also the hit's surface coordinates [n,2] (triangle barycentrics of v1 and v2, sphere
+    longitude and polar angle of the normal over 2 pi and pi, 0 for planes and misses)."""
+    return _trace(scene, rays, False, stream, uv)
 
 
 def occluded(scene: Scene, rays, stream=None):
@@ -570,7 +575,55 @@ class RadianceCache:
     def counters(self) -> dict:
         import torch
         c = self._view("counters", 256, torch.int32).cpu().numpy()
-        return {"steps": int(c[0]), "n_train": int(c[1]), "loss_sums": c[2:18].view(np.float32).copy()}
+        return {"steps": int(c[0]), "n_train": int(c[1]), "loss_sums": c[2:18].view(np.float32).copy(),
+                "health": int(c[18])}
+
+    def health(self) -> int:
+        """CACHE_HEALTH_* bits of the state (0: healthy; set bits make learned-form frames fall back to the
+        plain tracer until the state is initialised again)."""
+        return self.counters()["health"]
+
+    def save(self, path: str) -> None:
+        """Checkpoint of the network: FP32 master weights, Adam moments and the step count (an .npz file)."""
+        import torch
+        n = mlp_num_params()
+        torch.cuda.synchronize()
+        np.savez(path, format=np.array("mirt-radiance-cache-1"), capacity=np.array(self.capacity),
+                 w_master=self._view("w_master", 4 * n, torch.float32).cpu().numpy(),
+                 m=self._view("m", 4 * n, torch.float32).cpu().numpy(),
+                 v=self._view("v", 4 * n, torch.float32).cpu().numpy(),
+                 steps=np.array(self.counters()["steps"], np.int64))
+
+    @staticmethod
+    def read_checkpoint(path: str) -> dict:
+        """Validated arrays of a checkpoint written by save() (no device work)."""
+        n = mlp_num_params()
+        with np.load(path, allow_pickle=False) as z:
+            if "format" not in z.files or str(z["format"]) != "mirt-radiance-cache-1":
+                raise ValueError(f"{path}: not a radiance-cache checkpoint")
+            ck = {k: z[k] for k in ("w_master", "m", "v", "steps", "capacity")}
+        for k in ("w_master", "m", "v"):
+            a = ck[k]
+            if a.dtype != np.float32 or a.shape != (n,):
+                raise ValueError(f"{path}: {k} must be float32 [{n}], got {a.dtype} {a.shape}")
+            if not np.isfinite(a).all():
+                raise ValueError(f"{path}: {k} holds non-finite values")
+        if (ck["v"] < 0).any() or int(ck["steps"]) < 0:
+            raise ValueError(f"{path}: negative second moment or step count")
+        return ck
+
+    @classmethod
+    def load(cls, path: str, capacity: int = None, device="cuda") -> "RadianceCache":
+        """A state restored from save(): master weights (and their BF16 copy), Adam moments, step count."""
+        import torch
+        ck = cls.read_checkpoint(path)
+        cache = cls(ck["w_master"], capacity=int(capacity or ck["capacity"]), device=device)
+        n = mlp_num_params()
+        cache._view("m", 4 * n, torch.float32).copy_(torch.from_numpy(ck["m"]))
+        cache._view("v", 4 * n, torch.float32).copy_(torch.from_numpy(ck["v"]))
+        cache._view("counters", 4, torch.int32).fill_(int(ck["steps"]))
+        torch.cuda.synchronize()
+        return cache
 
     def training_batch(self):
         """(rays [n,6], features [n,64] f32, targets [n,3], pixel [n]) of the last trained frame (device tensors)."""

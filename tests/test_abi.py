@@ -257,3 +257,51 @@ def test_network_entry_points_reject_unaligned_operands_without_a_gpu():
         assert L.rt_mlp_grad(w, x, 0x3000, 5, 5, 0x4000, 0x5000, None) == -1
         assert b"16-byte aligned" in L.rt_last_error()
     assert L.rt_mlp_forward(0x1000, 0x2000, 0, 0x3000, None) == 0      # nothing to do
+
+
+def test_autotune_cache_survives_corrupt_files(tmp_path):
+    """A corrupt or malformed autotune cache is never applied: the tuner falls back to tuning from the
+    defaults, and writing replaces the file whole."""
+    from paper_1504_03151_amd import autotune
+    path = str(tmp_path / "tune.json")
+    key = "dev|seq|abc"
+    good = {"config": {"layout": 4, "chunk": 128, "tile": 0}, "ms": 19.3, "default_ms": 22.8, "trials": []}
+    assert autotune.read_cache(path, key) is None                       # missing file
+    for junk in ("{not json", "[1, 2, 3]", '{"dev|seq|abc": 5}', "\x00\xff",
+                 '{"dev|seq|abc": {"config": {"layout": 9, "chunk": 128, "tile": 0}, "ms": 1.0}}',
+                 '{"dev|seq|abc": {"config": {"layout": 4, "chunk": 100, "tile": 0}, "ms": 1.0}}',
+                 '{"dev|seq|abc": {"config": {"layout": 4, "chunk": 128}, "ms": 1.0}}'):
+        with open(path, "w", errors="surrogateescape") as f:
+            f.write(junk)
+        msgs = []
+        assert autotune.read_cache(path, key, msgs.append) is None, junk
+        assert msgs, junk
+    autotune.write_cache(path, key, good)                               # replaces the corrupt file
+    assert autotune.read_cache(path, key) == good
+    autotune.write_cache(path, "other", good)
+    assert autotune.read_cache(path, key) == good and autotune.read_cache(path, "other") == good
+    assert [p.name for p in tmp_path.iterdir()] == ["tune.json"]       # no temporary left behind
+
+
+def test_cache_init_and_checkpoint_reject_non_finite_weights_without_a_gpu(tmp_path):
+    """rt_cache_init validates the host weights before any device work; a checkpoint with NaN weights,
+    a wrong shape or another format is refused before anything is loaded."""
+    L = rt.lib()
+    n = rt.mlp_num_params()
+    w = np.zeros(n, np.float32)
+    w[77] = np.nan
+    assert L.rt_cache_init(0x100000, 64, w.ctypes.data, None) == -1
+    assert b"non-finite" in L.rt_last_error()
+    good = dict(format=np.array("mirt-radiance-cache-1"), capacity=np.array(64),
+                w_master=np.zeros(n, np.float32), m=np.zeros(n, np.float32), v=np.zeros(n, np.float32),
+                steps=np.array(3, np.int64))
+    p = str(tmp_path / "ok.npz")
+    np.savez(p, **good)
+    ck = rt.RadianceCache.read_checkpoint(p)
+    assert int(ck["steps"]) == 3
+    for k, bad in (("w_master", np.full(n, np.nan, np.float32)), ("m", np.zeros(n - 1, np.float32)),
+                   ("v", -np.ones(n, np.float32)), ("format", np.array("something-else"))):
+        p = str(tmp_path / f"bad_{k}.npz")
+        np.savez(p, **dict(good, **{k: bad}))
+        with pytest.raises(ValueError):
+            rt.RadianceCache.read_checkpoint(p)

@@ -192,3 +192,98 @@ def test_learned_form_full_frame_sampled(rt):
     tol = 1e-3 + 3e-2 * cache_mag.max(axis=1)
     assert (err[rob] <= tol[rob]).all(), (err - tol)[rob].max()
     assert (cache_mag[rob & hit].max(axis=1) > 1e-3).sum() >= 4   # the compared pixels carry cache terms
+
+
+def _poison(cache, key, index, nbytes, dtype, bits):
+    view = cache._view(key, nbytes, dtype)
+    view[index] = bits
+    torch.cuda.synchronize()
+
+
+def test_unhealthy_cache_falls_back_to_the_plain_tracer(rt):
+    """The plain full-depth tracer is the learned form's fallback: a NaN in the BF16 weights a frame is about
+    to use makes that frame answer no query and trace on to max_depth instead (the plain frame, reported by
+    the status bit); a NaN that enters the FP32 master weights shows in the next frame, after training has
+    turned the loss and the weights non-finite.  Initialising the state again restores the learned form."""
+    w = _scene()
+    sc = rt.Scene(w.scene).upload()
+    plain_rgb, plain_ids, _ = rt.render(sc, w.camera, w.params)
+    torch.cuda.synchronize()
+    cache = rt.RadianceCache(S.mlp_init_weights(5), capacity=2048)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, mode=rt.CACHE_TRAIN, depth=2, full_depth=w.params.max_depth,
+                          train_samples=2048, train_steps=2)
+    healthy, _ = r.render(rt.FLAG_SYNC)
+    healthy = healthy.clone()
+    torch.cuda.synchronize()
+    assert r.read_stats()["status"] == 0 and cache.health() == 0
+    assert r.read_stats()["cache_queries"] > 50
+    assert (healthy - plain_rgb).abs().max() > 1e-3           # the learned frame differs from the plain one
+
+    # (1) a NaN BF16 weight: this very frame falls back (graph replay and eager launches alike)
+    n = rt.mlp_num_params()
+    _poison(cache, "w_bf16", 4097, 2 * n, torch.int16, 0x7FC0)
+    for flags in (rt.FLAG_SYNC, rt.FLAG_SYNC | rt.FLAG_NO_GRAPH):
+        rgb, ids = r.render(flags)
+        torch.cuda.synchronize()
+        st = r.read_stats()
+        assert st["status"] == rt.STATUS_CACHE_FALLBACK, st["status"]
+        assert st["cache_queries"] == 0
+        assert torch.equal(ids, plain_ids)
+        assert torch.allclose(rgb, plain_rgb, rtol=1e-5, atol=1e-5), (rgb - plain_rgb).abs().max()
+        assert cache.health() & rt.CACHE_HEALTH_BF16
+    # the same rays as the plain frame, depth by depth
+    r_plain = rt.Renderer(sc, w.camera, w.params)
+    r_plain.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert r.read_stats()["rays"] == r_plain.read_stats()["rays"]
+    assert r.read_stats()["shadow"] == r_plain.read_stats()["shadow"]
+
+    # (2) re-initialised: the learned form is back
+    cache2 = rt.RadianceCache(S.mlp_init_weights(5), capacity=2048)
+    r2 = rt.CachedRenderer(sc, w.camera, w.params, cache2, mode=rt.CACHE_TRAIN, depth=2,
+                           full_depth=w.params.max_depth, train_samples=2048, train_steps=2)
+    again, _ = r2.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert r2.read_stats()["status"] == 0 and cache2.health() == 0
+    assert torch.allclose(again, healthy, rtol=1e-5, atol=1e-5)
+
+    # (3) a NaN master weight: the frame still uses the finite BF16 copy, its training turns the loss and the
+    # weights non-finite, and the next frame falls back
+    _poison(cache2, "w_master", 123, 4 * n, torch.float32, float("nan"))
+    r2.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert r2.read_stats()["status"] == 0
+    assert cache2.health() & rt.CACHE_HEALTH_WEIGHTS
+    rgb, ids = r2.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert r2.read_stats()["status"] == rt.STATUS_CACHE_FALLBACK
+    assert torch.allclose(rgb, plain_rgb, rtol=1e-5, atol=1e-5)
+
+
+def test_cache_checkpoint_round_trip(rt, tmp_path):
+    """Saving and loading the network's state (master weights, Adam moments, step count) resumes training
+    exactly: the next frame of the loaded state equals that of the original, image and weights."""
+    w = _scene()
+    sc = rt.Scene(w.scene).upload()
+    kw = dict(mode=rt.CACHE_TRAIN, depth=2, full_depth=6, train_samples=2048, train_steps=2)
+    cache = rt.RadianceCache(S.mlp_init_weights(9), capacity=2048)
+    r = rt.CachedRenderer(sc, w.camera, w.params, cache, **kw)
+    for f in range(3):
+        w.params.frame = f
+        r.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    path = str(tmp_path / "cache.npz")
+    cache.save(path)
+    loaded = rt.RadianceCache.load(path)
+    assert loaded.counters()["steps"] == cache.counters()["steps"] == 6
+    assert torch.equal(loaded.master_weights(), cache.master_weights())
+    assert torch.equal(loaded.bf16_weights(), cache.bf16_weights())
+    r_loaded = rt.CachedRenderer(sc, w.camera, w.params, loaded, **kw)
+    w.params.frame = 3
+    a, _ = r.render(rt.FLAG_SYNC)
+    b, _ = r_loaded.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    # training is deterministic up to the order of the gradient's atomic additions
+    assert torch.allclose(loaded.master_weights(), cache.master_weights(), rtol=0, atol=1e-6)
+    assert loaded.counters()["steps"] == 8

@@ -5,6 +5,9 @@ exceeds 1e-4 the primary hit ids match exactly; on pixels whose whole ray tree
 is robust, RGB agrees within 1e-3 absolute; at least 98% of the compared
 pixels are robust.  Non-robust pixels must still carry a valid id.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -12,6 +15,8 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from paper_1504_03151_amd import scenes as S
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 pytestmark = pytest.mark.gpu
 
@@ -154,17 +159,53 @@ def test_edge_cases(rt):
 
 # ------------------------------------------------------------------ single rays through rt_intersect / rt_occluded
 
-def _oracle_rays(w, pixels):
-    recs = [oracle.ray_tree(w.scene, w.camera, w.params, int(p))[0] for p in pixels]
+def _workers():
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _oracle_rays(w, jobs):
+    """Every ray the oracle traces for the given (pixel, sample) pairs (its ray log, in recursion order)."""
+    with ThreadPoolExecutor(_workers()) as ex:
+        recs = list(ex.map(lambda a: oracle.ray_tree(w.scene, w.camera, w.params, int(a[0]), int(a[1]))[0], jobs))
     return np.concatenate(recs, axis=0)
 
 
-@pytest.mark.parametrize("cfg", ["tiny", "c0"])
+def _uv_normal(uv):
+    """Unit normal of a sphere hit from its (longitude / 2 pi, polar angle / pi) surface coordinates."""
+    ph, th = 2 * np.pi * uv[:, 0] - np.pi, np.pi * uv[:, 1]
+    return np.stack([np.sin(th) * np.cos(ph), np.cos(th), np.sin(th) * np.sin(ph)], axis=1)
+
+
+def _ray_jobs(cfg):
+    """(workload, node layout, (pixel, sample) pairs) of the per-ray comparisons.  c2's rays come from
+    pixels whose first camera ray hits an object: 16 jittered samples, up to 8 bounces through mirror
+    and glass icospheres, 8 lights per hit."""
+    if cfg == "tiny":
+        w = S.random_tiny(7, size=40, depth=4)
+        return w, 0, [(p, 0) for p in S.pixel_subset(w.camera, 600, 11)]
+    if cfg == "c0":
+        w = S.config0()
+        return w, 0, [(p, 0) for p in S.pixel_subset(w.camera, 600, 11)]
+    if cfg == "c1":
+        w = S.config1()
+        return w, 4, [(p, 0) for p in S.pixel_subset(w.camera, 1024, 12)]
+    w = S.config2()
+    fx = np.load(os.path.join(GOLDEN, "c2_frame_oracle.npz"))
+    hit_px = fx["pixels"][fx["ids"][:, 0] >= 0][:32]
+    return w, 4, [(p, s) for p in hit_px for s in range(w.params.spp)]
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "c0", "c1", "c2"])
 def test_intersect_and_occluded_on_oracle_rays(rt, cfg):
-    w = S.random_tiny(7, size=40, depth=4) if cfg == "tiny" else S.config0()
-    pixels = S.pixel_subset(w.camera, 600, 11)
-    rec = _oracle_rays(w, pixels)
-    sc = rt.Scene(w.scene).upload()
+    """rt_intersect / rt_occluded (Algorithm 1's object loop and blocker loop) on the oracle's own camera,
+    secondary and shadow rays, cast to FP32; c1 and c2 through the quantized four-wide nodes the benchmark
+    uses.  Robust rays: equal ids, t within 2e-5, equal blocked flags, surface coordinates as the oracle's.
+    At least 98% of the rays must be robust (the oracle measures 99.85% or more on every set here)."""
+    w, layout, jobs = _ray_jobs(cfg)
+    floor = 0.98
+    rec = _oracle_rays(w, jobs)
+    sc = rt.Scene(w.scene, node_layout=layout).upload()
+    ns, nt = len(w.scene.spheres), len(w.scene.tris)
     for shadow in (False, True):
         sel = rec[rec[:, 0] == 3] if shadow else rec[rec[:, 0] != 3]
         R = rt.make_rays(sel[:, 2:5], sel[:, 5:8], sel[:, 8] if shadow else None)
@@ -172,18 +213,42 @@ def test_intersect_and_occluded_on_oracle_rays(rt, cfg):
         Rd = torch.from_numpy(R).cuda()
         if shadow:
             occ = rt.occluded(sc, Rd).cpu().numpy().astype(bool)
-            ref, m = oracle.occluded(w.scene, o32, d32, R[:, 7].astype(np.float64))
+            ref, m = oracle.occluded(w.scene, o32, d32, R[:, 7].astype(np.float64), nthreads=_workers())
             rob = m > ROBUST
-            assert rob.mean() > 0.97 and (occ[rob] == ref[rob]).all()
+            assert rob.mean() >= floor, f"shadow rays: robust fraction {rob.mean():.4f}"
+            bad = np.where(rob & (occ != ref))[0]
+            assert len(bad) == 0, f"{len(bad)} robust shadow rays differ of {rob.sum()}"
         else:
-            t, ids = rt.intersect(sc, Rd)
-            t, ids = t.cpu().numpy(), ids.cpu().numpy()
-            tr, ir, m = oracle.closest(w.scene, o32, d32)
+            t, ids, uv = rt.intersect(sc, Rd, uv=True)
+            t, ids, uv = t.cpu().numpy(), ids.cpu().numpy(), uv.cpu().numpy().astype(np.float64)
+            tr, ir, m, uvr = oracle.closest(w.scene, o32, d32, nthreads=_workers(), uv=True)
             rob = m > ROBUST
-            assert rob.mean() > 0.97
-            assert (ids[rob] == ir[rob]).all()
+            assert rob.mean() >= floor, f"closest-hit rays: robust fraction {rob.mean():.4f}"
+            bad = np.where(rob & (ids != ir))[0]
+            assert len(bad) == 0, (f"{len(bad)} robust rays with different ids of {rob.sum()}, e.g. gpu "
+                                   f"{ids[bad[0]]} oracle {ir[bad[0]]}")
             hit = rob & (ir >= 0)
             np.testing.assert_allclose(t[hit], tr[hit], rtol=2e-5)
+            # triangle barycentrics: FP32 edge functions of coordinates relative to the ray origin, so the
+            # error grows with the distance and shrinks with the triangle's projected size (tolerance below)
+            tri = hit & (ir >= ns) & (ir < ns + nt)
+            if tri.any():
+                v = w.scene.tris[ir[tri] - ns].astype(np.float64)
+                area2 = np.linalg.norm(np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]), axis=1)
+                cosang = np.abs(np.einsum("ij,ij->i", np.cross(v[:, 1] - v[:, 0], v[:, 2] - v[:, 0]) /
+                                          area2[:, None], d32[tri]))
+                span = np.abs(o32[tri]).max(axis=1) + tr[tri]
+                edge = np.linalg.norm(v - np.roll(v, 1, axis=1), axis=2).max(axis=1)
+                tol = 1e-5 + 64 * 2.0 ** -24 * span * edge / (area2 * np.maximum(cosang, 1e-3))
+                err = np.abs(uv[tri] - uvr[tri]).max(axis=1)
+                worst = int(np.argmax(err / tol))
+                assert (err <= tol).all(), f"barycentrics off by {err[worst]:.2e} (tolerance {tol[worst]:.2e})"
+            sph = hit & (ir < ns)
+            if sph.any():
+                dn = np.linalg.norm(_uv_normal(uv[sph]) - _uv_normal(uvr[sph]), axis=1)
+                assert dn.max() <= 1e-3, f"sphere normal from uv off by {dn.max():.2e}"
+            miss_or_plane = rob & ((ir < 0) | (ir >= ns + nt))
+            assert (uv[miss_or_plane] == 0).all()
 
 
 @pytest.mark.parametrize("layout", [0, 3, 4])      # binary depth-first, four-wide, quantized four-wide
@@ -217,12 +282,16 @@ def test_random_rays_bvh_equals_brute_force(rt, layout):
 
 # ------------------------------------------------------------------ full-size configurations, sampled pixels
 
-def test_config1_full_frame_sampled(rt):
+@pytest.mark.parametrize("layout", [0, 4])       # binary depth-first; quantized four-wide (the tuned layout)
+def test_config1_full_frame_sampled(rt, layout):
+    """1080p terrain (522,242 triangles) with 64 mirror spheres, depth 5: 4,096 seeded pixels."""
     w = S.config1()
-    _, rgb, ids, st = render(rt, w)
+    sc = rt.Scene(w.scene, node_layout=layout).upload()
+    rgb, ids, st = rt.render(sc, w.camera, w.params)
+    torch.cuda.synchronize()
     assert st["status"] == 0
-    pixels = S.pixel_subset(w.camera, 384, 21)
-    compare(w, rgb, ids, pixels)
+    pixels = S.pixel_subset(w.camera, 4096, 21)
+    compare(w, rgb, ids, pixels, nthreads=_workers())
 
 
 def test_config2_full_frame_sampled(rt):
@@ -264,6 +333,53 @@ def test_config2_full_frame_sampled(rt):
     g_avg = rgb.reshape(-1, 3).double().cpu().numpy()[pixels]
     assert full.sum() >= 8
     assert np.abs(g_avg - ref["rgb"]).max(axis=1)[full].max() <= RGB_TOL
+
+
+def test_config2_benchmarked_setting_against_stored_oracle(rt):
+    """The benchmarked frame exactly as bench.py times it after autotuning (quantized four-wide nodes, 8x8
+    tiles, queue chunk 128; 1080p x 16 jittered spp, depth 8), against the oracle's brute-force render of
+    1,024 seeded pixels (512 with an object under the first sample, 512 others) stored by
+    tests/golden/make_oracle_fixtures.py.
+
+    Per sample (each sample's whole ray tree): robust samples have the oracle's primary id and radiance
+    within 1e-3.  The oracle certifies 95.0% of these samples robust: all of the background pixels' and
+    90.1% of the object pixels' (a sample's tree of up to ~200 rays crosses many small facets of mirror
+    and glass icospheres, and one decision within the 1e-4 margin anywhere in it excludes the sample).
+    That fraction is a property of the scene and the oracle alone; the floor only guards against a
+    shrunken comparison set.  The averaged frame is compared on the 718 pixels (70%) all of whose 16
+    samples are robust."""
+    import sys
+    sys.path.insert(0, GOLDEN)
+    from make_oracle_fixtures import scene_digest
+    fx = np.load(os.path.join(GOLDEN, "c2_frame_oracle.npz"))
+    w = S.config2()
+    assert str(fx["digest"]) == scene_digest(w), "stored oracle results are for another scene"
+    pixels = fx["pixels"]
+    sc = rt.Scene(w.scene, node_layout=rt.LAYOUT_BVH4Q).upload()
+    rs = rt.Renderer(sc, w.camera, w.params, per_sample=True, tile=0, queue_chunk=128)
+    rgb_s, ids = rs.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    st = rs.read_stats()
+    assert st["status"] == 0 and st["rays"][8] > 0
+    g_s = rgb_s.reshape(-1, w.params.spp, 3).double().cpu().numpy()[pixels]
+    g_ids = ids.reshape(-1, w.params.spp).cpu().numpy()[pixels]
+    assert ((g_ids >= -1) & (g_ids < w.scene.n_prims)).all()
+    rob = fx["margin_s"] > ROBUST
+    assert rob.mean() >= 0.94, f"per-sample robust fraction {rob.mean():.4f}"
+    bad = np.where(rob & (g_ids != fx["ids"]))
+    assert len(bad[0]) == 0, f"{len(bad[0])} robust samples with different primary ids"
+    err = np.abs(g_s - fx["rgb_s"]).max(axis=2)
+    assert err[rob].max() <= RGB_TOL, f"per-sample rgb error {err[rob].max():.3e}"
+    # the averaged frame: the benchmarked output
+    ra = rt.Renderer(sc, w.camera, w.params, tile=0, queue_chunk=128)
+    rgb, ids_a = ra.render(rt.FLAG_SYNC)
+    torch.cuda.synchronize()
+    assert torch.equal(ids_a, ids)
+    assert torch.allclose(rgb, rgb_s.mean(dim=2), atol=2e-5)
+    full = fx["margin"] > ROBUST
+    assert full.sum() >= 700, full.sum()
+    g_avg = rgb.reshape(-1, 3).double().cpu().numpy()[pixels]
+    assert np.abs(g_avg - fx["rgb"]).max(axis=1)[full].max() <= RGB_TOL
 
 
 def test_deferred_shadow_queue_capacity(rt):

@@ -62,6 +62,44 @@ def test_plane_closed_form():
 TRI = [[-1.0, -1.0, 5.0], [1.0, -1.0, 5.0], [0.0, 1.0, 5.0]]
 
 
+def test_hit_surface_coordinates():
+    # triangle: aiming at (1-u-v) v0 + u v1 + v v2 returns (u, v); the centroid returns (1/3, 1/3);
+    # a vertex returns its own unit weight
+    v0, v1, v2 = (np.array(v, np.float64) for v in TRI)
+    targets = [(0.2, 0.3), (1 / 3, 1 / 3), (0.0, 1.0), (0.7, 0.05)]
+    o, d = [], []
+    for u, v in targets:
+        x = (1 - u - v) * v0 + u * v1 + v * v2
+        src = np.array([0.3, -0.2, -4.0])
+        dd = x - src
+        o.append(src)
+        d.append(dd / np.linalg.norm(dd))
+    sc = _scene(tris=[TRI], tri_mat=[0])
+    t, ids, m, uv = oracle.closest(sc, o, d, uv=True)
+    assert (ids == 0).all()
+    np.testing.assert_allclose(uv, np.array(targets), rtol=0, atol=1e-12)
+    # sphere: unit sphere at the origin; u = (atan2(n_z, n_x) + pi) / (2 pi), v = acos(n_y) / pi
+    sc = _scene(spheres=[[0.0, 0.0, 0.0, 1.0]], sphere_mat=[0])
+    th, ph = 1.1, 0.4                                        # hit normal n = (sin th cos ph, cos th, sin th sin ph)
+    n = np.array([math.sin(th) * math.cos(ph), math.cos(th), math.sin(th) * math.sin(ph)])
+    o = [[0, 0, -10], [10, 0, 0], [0, 10, 0], list(5 * n)]
+    d = [[0, 0, 1], [-1, 0, 0], [0, -1, 0], list(-n)]
+    t, ids, m, uv = oracle.closest(sc, o, d, uv=True)
+    assert (ids == 0).all()
+    expect = [(0.25, 0.5),                                   # n = (0, 0, -1): atan2(-1, 0) = -pi/2
+              (0.5, 0.5),                                    # n = (1, 0, 0): atan2(0, 1) = 0
+              (None, 0.0),                                   # the pole n = +y: polar angle 0
+              ((ph + math.pi) / (2 * math.pi), th / math.pi)]
+    for (eu, ev), (gu, gv) in zip(expect, uv):
+        if eu is not None:
+            assert abs(gu - eu) < 1e-12
+        assert abs(gv - ev) < 1e-7
+    # planes and misses carry (0, 0)
+    sc = _scene(planes=[[0.0, 1.0, 0.0, -5.0]], plane_mat=[0])
+    _, ids, _, uv = oracle.closest(sc, [[0, 0, 0], [0, 0, 0]], [[0, -1, 0], [0, 1, 0]], uv=True)
+    assert ids[0] == 0 and ids[1] == -1 and (uv == 0).all()
+
+
 def test_triangle_hit_edges_inclusive_and_degenerate():
     sc = _scene(tris=[TRI], tri_mat=[0])
     o = [[0, 0, 0], [-1, -1, 0], [-1.001, -1, 0], [0, 1, 0], [0, 1.0001, 0], [0, 0, 6]]
