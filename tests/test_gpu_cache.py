@@ -283,7 +283,8 @@ def test_cache_checkpoint_round_trip(rt, tmp_path):
     a, _ = r.render(rt.FLAG_SYNC)
     b, _ = r_loaded.render(rt.FLAG_SYNC)
     torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    # the same weights give the same image up to the order of the per-pixel atomic additions
+    assert torch.allclose(a, b, rtol=1e-5, atol=1e-6)
     # training is deterministic up to the order of the gradient's atomic additions
     assert torch.allclose(loaded.master_weights(), cache.master_weights(), rtol=0, atol=1e-6)
     assert loaded.counters()["steps"] == 8
