@@ -254,6 +254,21 @@ size_t rt_scene_refit_workspace_bytes(const rt_scene* scene);
 rt_status rt_scene_refit(rt_scene* scene, const float* spheres, const float* tris, void* workspace,
                          size_t workspace_bytes, int32_t flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight per-frame loops of dynamic scenes, harnesses that forbid
+ * hipMalloc): rt_scene_refit with its scratch (the refit header and a box per
+ * node, rt_scene_refit_workspace_bytes) taken from a buffer the library holds
+ * in static device memory, at most rt_scene_refit_noalloc_max_bytes() (32 MiB:
+ * up to 1,398,090 nodes) per GPU, kept until the process ends.  Same kernels,
+ * same results, same flags and errors as rt_scene_refit, plus RT_ERR_CAPACITY
+ * for a scene whose scratch exceeds the maximum.  Allocates nothing: no
+ * hipMalloc, hipFree or allocating library call.  All calls on one GPU share
+ * the buffer: calls that overlap on one GPU (two streams, two threads) race
+ * and must be ordered by the caller. */
+size_t rt_scene_refit_noalloc_max_bytes(void);
+rt_status rt_scene_refit_noalloc(rt_scene* scene, const float* spheres, const float* tris, int32_t flags,
+                                 void* stream);
+
 /* Workspace bytes rt_render needs for this camera and parameters (queues,
  * accumulator, counters).  Returns 0 and sets the last error for invalid input. */
 size_t rt_render_workspace_bytes(const rt_scene* scene, const rt_camera* cam, const rt_params* params);

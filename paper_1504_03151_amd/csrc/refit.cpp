@@ -13,6 +13,7 @@
 // own positions therefore reproduces the uploaded blob bit for bit.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <string>
 
 #include "bvh_quant.h"
@@ -215,45 +216,73 @@ __global__ void k_refit_level(uint8_t* nodes, const float4* prims, int32_t ns, c
 
 size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-}  // namespace
-}  // namespace mirt
-
-using namespace mirt;
-
-extern "C" {
-
-size_t rt_scene_refit_workspace_bytes(const rt_scene* scene) {
-    if (!scene) return 0;
-    return kRefitHeader + a256(24 * (size_t)std::max<int64_t>(scene->h.n_nodes, 1));
+size_t refit_scratch_bytes(const SceneHost& h) {
+    return kRefitHeader + a256(24 * (size_t)std::max<int64_t>(h.n_nodes, 1));
 }
 
-rt_status rt_scene_refit(rt_scene* scene, const float* spheres, const float* tris, void* workspace,
-                         size_t workspace_bytes, int32_t flags, void* stream) {
+// Scratch of rt_scene_refit_noalloc: the refit header and a box per node in
+// one file-scope device array.  Every GPU the library runs on holds its own
+// copy until the process ends; calls on one GPU share it.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current.  In host code `scratch` names a host-side stand-in,
+// never a device address: only this pointer is passed to kernels.
+rt_status scratch_ptr(const char* who, uint8_t** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* per_dev[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error(std::string(who) + ": hipGetDevice: " + hipGetErrorString(e));
+        return RT_ERR_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error(std::string(who) + ": device index beyond 63");
+        return RT_ERR_UNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    if (!per_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string(who) + ": hipGetSymbolAddress(scratch): " + hipGetErrorString(e));
+            return RT_ERR_HIP;
+        }
+        per_dev[dev] = p;
+    }
+    *out = static_cast<uint8_t*>(per_dev[dev]);
+    return RT_OK;
+}
+
+// Argument checks shared by both entry points (everything but the scratch).
+rt_status refit_check(const char* who, const rt_scene* scene, const float* spheres, const float* tris) {
     if (!scene) {
-        set_error("rt_scene_refit: NULL scene");
+        set_error(std::string(who) + ": NULL scene");
         return RT_ERR_INVALID_ARG;
     }
-    SceneHost& h = scene->h;
+    const SceneHost& h = scene->h;
     if (!h.dev) {
-        set_error("rt_scene_refit: scene not uploaded (call rt_scene_upload)");
+        set_error(std::string(who) + ": scene not uploaded (call rt_scene_upload)");
         return RT_ERR_NOT_UPLOADED;
     }
     if ((h.n_spheres && !spheres) || (h.n_tris && !tris)) {
-        set_error("rt_scene_refit: NULL position array with a non-zero count");
-        return RT_ERR_INVALID_ARG;
-    }
-    if (!workspace || workspace_bytes < rt_scene_refit_workspace_bytes(scene)) {
-        set_error("rt_scene_refit: workspace missing or smaller than rt_scene_refit_workspace_bytes");
-        return RT_ERR_CAPACITY;
-    }
-    if (reinterpret_cast<uintptr_t>(workspace) & 255) {
-        set_error("rt_scene_refit: workspace must be 256-byte aligned");
+        set_error(std::string(who) + ": NULL position array with a non-zero count");
         return RT_ERR_INVALID_ARG;
     }
     if (h.refit_levels.size() < 2 || h.refit_levels.back() != h.n_nodes) {
-        set_error("rt_scene_refit: scene has no refit order");
+        set_error(std::string(who) + ": scene has no refit order");
         return RT_ERR_INVALID_ARG;
     }
+    return RT_OK;
+}
+
+// The refit itself on a checked scene and a scratch of refit_scratch_bytes (256-byte aligned).
+rt_status refit_enqueue(rt_scene* scene, const float* spheres, const float* tris, void* workspace, int32_t flags,
+                        void* stream) {
+    SceneHost& h = scene->h;
     hipStream_t st = static_cast<hipStream_t>(stream);
     uint8_t* base = static_cast<uint8_t*>(h.dev);
     uint32_t* ws = static_cast<uint32_t*>(workspace);
@@ -299,6 +328,52 @@ rt_status rt_scene_refit(rt_scene* scene, const float* spheres, const float* tri
         }
     }
     return RT_OK;
+}
+
+}  // namespace
+}  // namespace mirt
+
+using namespace mirt;
+
+extern "C" {
+
+size_t rt_scene_refit_workspace_bytes(const rt_scene* scene) {
+    if (!scene) return 0;
+    return refit_scratch_bytes(scene->h);
+}
+
+rt_status rt_scene_refit(rt_scene* scene, const float* spheres, const float* tris, void* workspace,
+                         size_t workspace_bytes, int32_t flags, void* stream) {
+    rt_status rs = refit_check("rt_scene_refit", scene, spheres, tris);
+    if (rs != RT_OK) return rs;
+    if (!workspace || workspace_bytes < refit_scratch_bytes(scene->h)) {
+        set_error("rt_scene_refit: workspace missing or smaller than rt_scene_refit_workspace_bytes");
+        return RT_ERR_CAPACITY;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) & 255) {
+        set_error("rt_scene_refit: workspace must be 256-byte aligned");
+        return RT_ERR_INVALID_ARG;
+    }
+    return refit_enqueue(scene, spheres, tris, workspace, flags, stream);
+}
+
+size_t rt_scene_refit_noalloc_max_bytes(void) { return kNoAllocScratchBytes; }
+
+rt_status rt_scene_refit_noalloc(rt_scene* scene, const float* spheres, const float* tris, int32_t flags,
+                                 void* stream) {
+    if (scene && refit_scratch_bytes(scene->h) > kNoAllocScratchBytes) {
+        set_error("rt_scene_refit_noalloc: the scene's " + std::to_string(scene->h.n_nodes) +
+                  " nodes need " + std::to_string(refit_scratch_bytes(scene->h)) +
+                  " bytes of scratch, more than the " + std::to_string(kNoAllocScratchBytes) +
+                  " bytes the library holds per GPU (use rt_scene_refit with a workspace)");
+        return RT_ERR_CAPACITY;
+    }
+    rt_status rs = refit_check("rt_scene_refit_noalloc", scene, spheres, tris);
+    if (rs != RT_OK) return rs;
+    uint8_t* ptr = nullptr;
+    rs = scratch_ptr("rt_scene_refit_noalloc", &ptr);
+    if (rs != RT_OK) return rs;
+    return refit_enqueue(scene, spheres, tris, ptr, flags, stream);
 }
 
 }  // extern "C"

@@ -117,6 +117,8 @@ SIGNATURES = {
     "rt_scene_upload": (C.c_int32, [_P, _P, C.c_size_t, _P]),
     "rt_scene_refit_workspace_bytes": (C.c_size_t, [_P]),
     "rt_scene_refit": (C.c_int32, [_P, _P, _P, _P, C.c_size_t, C.c_int32, _P]),
+    "rt_scene_refit_noalloc_max_bytes": (C.c_size_t, []),
+    "rt_scene_refit_noalloc": (C.c_int32, [_P, _P, _P, C.c_int32, _P]),
     "rt_render_workspace_bytes": (C.c_size_t, [_P, C.POINTER(CameraC), C.POINTER(ParamsC)]),
     "rt_render": (C.c_int32, [_P, C.POINTER(CameraC), C.POINTER(ParamsC), _P, _P]),
     "rt_render_batch_workspace_bytes": (C.c_size_t, [_P, _P, _P, C.c_int32]),
@@ -258,25 +260,31 @@ class Scene:
         off = self.device_base - self.blob.data_ptr()
         return self.blob[off:off + self.device_bytes]
 
-    def refit(self, spheres=None, tris=None, sync: bool = False, stream=None):
+    def refit(self, spheres=None, tris=None, sync: bool = False, stream=None, noalloc: bool = False):
         """Refit the uploaded BVH on the GPU to new positions: spheres float32 [ns,4], tris float32 [nt,3,3]
-        (contiguous CUDA tensors in the build order).  The tree is kept; only the device copy changes."""
+        (contiguous CUDA tensors in the build order).  The tree is kept; only the device copy changes.
+        noalloc=True: rt_scene_refit_noalloc (scratch in the library's static device buffer, no workspace)."""
         import torch
         if self.blob is None:
             raise RTError(-7, "rt_scene_refit", "scene not uploaded")
-        need = int(lib().rt_scene_refit_workspace_bytes(self.handle))
-        ws = getattr(self, "_refit_ws", None)
-        if ws is None or ws.numel() < need + 256:
-            ws = self._refit_ws = torch.empty(need + 256, dtype=torch.uint8, device=self.blob.device)
-        base = (ws.data_ptr() + 255) // 256 * 256
         ns, nt = len(self.src.spheres), len(self.src.tris)
         for t, n, what in ((spheres, 4 * ns, "spheres"), (tris, 9 * nt, "tris")):
             if n and (t is None or t.numel() != n):
                 raise ValueError(f"refit: {what} must hold {n} floats")
             if t is not None:
                 assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
-        _check(lib().rt_scene_refit(self.handle, _ptr(spheres), _ptr(tris), base, need, FLAG_SYNC if sync else 0,
-                                    _stream_ptr(stream)), "rt_scene_refit")
+        flags = FLAG_SYNC if sync else 0
+        if noalloc:
+            _check(lib().rt_scene_refit_noalloc(self.handle, _ptr(spheres), _ptr(tris), flags, _stream_ptr(stream)),
+                   "rt_scene_refit_noalloc")
+            return self
+        need = int(lib().rt_scene_refit_workspace_bytes(self.handle))
+        ws = getattr(self, "_refit_ws", None)
+        if ws is None or ws.numel() < need + 256:
+            ws = self._refit_ws = torch.empty(need + 256, dtype=torch.uint8, device=self.blob.device)
+        base = (ws.data_ptr() + 255) // 256 * 256
+        _check(lib().rt_scene_refit(self.handle, _ptr(spheres), _ptr(tris), base, need, flags, _stream_ptr(stream)),
+               "rt_scene_refit")
         return self
 
     def host_trace(self, rays: np.ndarray, any_hit: bool = False, nthreads: int = 0, with_work: bool = False):
