@@ -489,21 +489,16 @@ __global__ void k_mlp_adam(float* __restrict__ w, uint16_t* __restrict__ wb, flo
 // Health of the learned form after a frame's training steps: bit 0 of *health
 // when one of the steps' loss sums (float bits in loss_bits[0 .. steps)) is
 // not finite, bit 1 when a master weight or an Adam moment is not.  Bits are
-// only ever added; rt_cache_init clears them.  One block.
+// only ever added; rt_cache_init clears them.  One thread per parameter.
 __global__ __launch_bounds__(256) void k_mlp_health(const float* __restrict__ w, const float* __restrict__ m,
                                                     const float* __restrict__ v, int n,
                                                     const uint32_t* __restrict__ loss_bits, int steps,
                                                     uint32_t* health) {
-    __shared__ uint32_t bad;
-    if (threadIdx.x == 0) bad = 0u;
-    __syncthreads();
-    uint32_t mine = 0u;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        if (!isfinite(w[i]) || !isfinite(m[i]) || !isfinite(v[i])) mine = 2u;
-    if ((int)threadIdx.x < steps && !isfinite(__uint_as_float(loss_bits[threadIdx.x]))) mine |= 1u;
-    if (mine) atomicOr(&bad, mine);
-    __syncthreads();
-    if (threadIdx.x == 0 && bad) *health |= bad;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t bad = 0u;
+    if (i < n && (!isfinite(w[i]) || !isfinite(m[i]) || !isfinite(v[i]))) bad = 2u;
+    if (i < steps && !isfinite(__uint_as_float(loss_bits[i]))) bad |= 1u;
+    if (bad) atomicOr(health, bad);
 }
 
 // blocks for `tiles` 32-sample tiles at per_block tiles per round, at most per_cu resident blocks per CU
@@ -542,7 +537,8 @@ rt_status mlp_grad_launch(const uint16_t* w, const uint16_t* x, const float* tar
 
 rt_status mlp_health_launch(const float* w, const float* m, const float* v, const uint32_t* loss_bits, int steps,
                            uint32_t* health, hipStream_t st) {
-    hipLaunchKernelGGL(k_mlp_health, dim3(1), dim3(256), 0, st, w, m, v, kParams, loss_bits, steps, health);
+    hipLaunchKernelGGL(k_mlp_health, dim3((kParams + 255) / 256), dim3(256), 0, st, w, m, v, kParams, loss_bits,
+                       steps, health);
     HIP_TRY_M(hipGetLastError());
     return RT_OK;
 }

@@ -1249,21 +1249,29 @@ constexpr int kCacheHealth = 18;
 // (any health bit, or a non-finite BF16 weight now) hands the depth's hits to
 // the fallback chain: their count moves from the frame's counters to the
 // chain's, so the network sees no query and the plain tracer shades them and
-// carries their paths on to the full depth.  One block.
+// carries their paths on to the full depth.  One thread per weight; the last
+// block to finish (the chain's counters, cleared each frame, collect the
+// blocks' findings and count the finished blocks) takes the decision.
+constexpr int kCtrGateBad = 100;    // fallback chain's counters: non-finite BF16 weights seen by the gate
+constexpr int kCtrGateDone = 101;   // ... and the gate's finished blocks
 __global__ __launch_bounds__(256) void k_cache_gate(const uint16_t* wb, int n, uint32_t* health, uint32_t* ctr,
                                                     uint32_t* ctr_fb, int depth, rt_stats* st) {
-    __shared__ uint32_t bad;
-    if (threadIdx.x == 0) bad = 0u;
+    __shared__ uint32_t last;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = i < n && (wb[i] & 0x7F80u) == 0x7F80u;   // BF16 exponent all ones: Inf or NaN
+    if (__any(bad) && lane_id() == 0) atomicOr(ctr_fb + kCtrGateBad, 4u);
     __syncthreads();
-    uint32_t mine = 0u;
-    for (int i = threadIdx.x; i < n; i += blockDim.x)
-        if ((wb[i] & 0x7F80u) == 0x7F80u) mine = 4u;   // BF16 exponent all ones: Inf or NaN
-    if (mine) atomicOr(&bad, mine);
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(ctr_fb + kCtrGateDone, 1u) == gridDim.x - 1 ? 1u : 0u;
+    }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    const uint32_t seen = atomicOr(ctr_fb + kCtrGateBad, 0u);
     uint32_t h = *health;
-    if (bad) {
-        h |= bad;
+    if (seen) {
+        h |= seen;
         *health = h;
     }
     if (h == 0u) return;
@@ -2402,8 +2410,8 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
                            ctr + kCtrRays + cd, xcd_cursor(ctr, kCtrRayCur + cd), pl.qcap, A.chunk, overflow,
                            nullptr);
     }
-    hipLaunchKernelGGL(k_cache_gate, dim3(1), dim3(256), 0, st, w_bf16, kMlpParams, health, ctr, ctr_fb, cd,
-                       A.stats);
+    hipLaunchKernelGGL(k_cache_gate, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, w_bf16, kMlpParams, health, ctr,
+                       ctr_fb, cd, A.stats);
     const float ie[3] = {1.0f / (cc.bounds_hi[0] - cc.bounds_lo[0]), 1.0f / (cc.bounds_hi[1] - cc.bounds_lo[1]),
                          1.0f / (cc.bounds_hi[2] - cc.bounds_lo[2])};
     hipLaunchKernelGGL(k_cache_shade, dim3(A.shade_blocks), dim3(256), 0, st, A.sc, A.shc, q[cd & 1], hq, ctr, cd, rec,

@@ -47,7 +47,7 @@ def test_area_lit_tiny_scene_every_pixel(rt, seed):
     torch.cuda.synchronize()
     ref = oracle.render(w.scene, w.camera, w.params)
     rob = ref["margin"] > ROBUST
-    assert rob.mean() > 0.9
+    assert rob.mean() > 0.965                              # oracle: 0.9762 (seed 0), 0.9725 (seed 3)
     g_ids = ids.reshape(-1, w.params.spp).cpu().numpy()
     assert (g_ids[rob] == ref["ids"][rob]).all()
     err = np.abs(rgb.reshape(-1, 3).double().cpu().numpy() - ref["rgb"]).max(axis=1)
@@ -123,7 +123,7 @@ def test_progressive_passes_average_the_frames(rt):
         w.params.frame = f
         refs.append(oracle.render(w.scene, w.camera, w.params))
     rob = np.all([r["margin"] > ROBUST for r in refs], axis=0)
-    assert rob.mean() > 0.85
+    assert rob.mean() > 0.965                              # oracle: 0.9717 (robust in all six frames)
     ref_mean = np.mean([r["rgb"] for r in refs], axis=0)
     err = np.abs(acc.reshape(-1, 3).double().cpu().numpy() - ref_mean).max(axis=1)
     assert err[rob].max() <= RGB_TOL

@@ -51,7 +51,7 @@ def test_every_tile_and_layout_gives_the_default_frame(rt):
     # and the default frame is the oracle's on robust pixels
     ref = oracle.render(w.scene, w.camera, w.params)
     rob = ref["margin"] > 1e-4
-    assert rob.mean() > 0.9
+    assert rob.mean() > 0.955                              # oracle: 0.9609 (4 jittered samples per pixel)
     assert (ids0.reshape(-1, 4).cpu().numpy()[rob] == ref["ids"][rob]).all()
 
 

@@ -55,7 +55,7 @@ def test_batch_matches_oracle(rt):
     for w, rb, ib in zip(ws, rgb_b, ids_b):
         ref = oracle.render(w.scene, w.camera, w.params)
         rob = ref["margin"] > 1e-4
-        assert rob.mean() > 0.93
+        assert rob.mean() > 0.945                          # oracle: 0.9518 to 1.0 over these scenes
         g_ids = ib.reshape(-1, w.params.spp).cpu().numpy()
         assert (g_ids[rob] == ref["ids"][rob]).all()
         err = np.abs(rb.reshape(-1, 3).double().cpu().numpy() - ref["rgb"]).max(axis=1)

@@ -57,7 +57,7 @@ def test_cache_inference_matches_oracle(rt):
     np.add.at(img, rec[:, 0].astype(int), term)
     np.add.at(cache_mag, rec[:, 0].astype(int), np.abs(term))
     rob = ref["margin"] > 1e-4
-    assert rob.mean() > 0.93
+    assert rob.mean() > 0.98                               # oracle: 0.9986
     g = rgb.reshape(-1, 3).double().cpu().numpy()
     err = np.abs(g - img)
     tol = 1e-3 + 3e-2 * cache_mag

@@ -64,7 +64,7 @@ def test_tiny_mixed_scenes_every_sample(rt, seed):
     w = _gi(S.random_tiny(seed, n_spheres=6, n_tris=60, size=33, depth=6))
     w.params.spp, w.params.jitter = 4, 1
     _, g_s, g_ids, st = per_sample(rt, w)
-    ref, rob = compare_samples(w, g_s, g_ids, np.arange(w.camera.n_pixels), 0.8)
+    ref, rob = compare_samples(w, g_s, g_ids, np.arange(w.camera.n_pixels), 0.98)   # oracle: 0.9865 to 0.9977
     # path tracing traces one continuation per path: each depth's ray count is at most the primary count
     assert all(st["rays"][k + 1] <= st["rays"][k] for k in range(6))
     assert st["rays"][6] > 0
@@ -101,7 +101,7 @@ def test_mixed_walls_follow_the_oracle_and_average_to_the_branching_sum(rt):
     sem = vals.std(0) / math.sqrt(len(vals))
     # 5 standard errors, plus FP32 rounding (the red channel, the albedo's largest, has no variance)
     assert (np.abs(vals.mean(0) - expect) < 5 * sem + 1e-5 * expect).all(), (vals.mean(0), expect, sem)
-    compare_samples(w, g_s, g_ids, np.arange(0, 256, 7), 0.85)
+    compare_samples(w, g_s, g_ids, np.arange(0, 256, 7), 0.91)   # oracle: 0.919
 
 
 def test_frame_is_the_mean_of_its_samples_and_frames_differ(rt):
@@ -138,7 +138,7 @@ def test_batch_with_some_scenes_in_gi_equals_single_frames(rt):
     for w, x in zip(ws[1::2], rb[1::2]):
         ref = oracle.render(w.scene, w.camera, w.params)
         rob = ref["margin"] > ROBUST
-        assert rob.mean() > 0.8
+        assert rob.mean() > 0.98                           # oracle: 0.9862, 0.9968
         err = np.abs(x.reshape(-1, 3).double().cpu().numpy() - ref["rgb"]).max(1)
         assert err[rob].max() <= RGB_TOL
 
@@ -184,7 +184,7 @@ def test_learned_form_with_gi_matches_the_oracle(rt):
     np.add.at(img, rec[:, 0].astype(int), term)
     np.add.at(mag, rec[:, 0].astype(int), np.abs(term))
     rob = ref["margin"] > ROBUST
-    assert rob.mean() > 0.9
+    assert rob.mean() > 0.98                               # oracle: 0.9973
     err = np.abs(rgb.reshape(-1, 3).double().cpu().numpy() - img)
     tol = 1e-3 + 3e-2 * mag
     assert (err[rob] <= tol[rob]).all(), (err - tol)[rob].max()
@@ -211,7 +211,7 @@ def test_learned_form_targets_with_gi_are_keyed_paths(rt):
     L, m = oracle.radiance(w.scene, w.params, o, d, 2, so=float(np.abs(o).max()) * 4e-7, sd=4e-7, pixels=idx,
                            sample=0)
     rob = m > ROBUST
-    assert rob.mean() > 0.8, rob.mean()
+    assert rob.mean() > 0.8, rob.mean()      # rays chosen by the GPU's training selection: no oracle-only figure
     np.testing.assert_allclose(targets[idx][rob], L[rob], atol=1e-3, rtol=0)
     assert np.abs(L[rob]).max() > 0.05
 
@@ -226,4 +226,4 @@ def test_gi_room_full_frame_sampled(rt):
     assert st["rays"][0] == n
     assert all(n - 64 <= r <= n for r in st["rays"][1:7]), st["rays"]
     pixels = S.pixel_subset(w.camera, 3, 23)
-    compare_samples(w, g_s, g_ids, pixels, 0.5)
+    compare_samples(w, g_s, g_ids, pixels, 0.7)          # oracle: 0.708 (48 depth-6 path samples)

@@ -82,7 +82,7 @@ def test_tiny_mixed_scenes_every_pixel(rt, seed):
     w = S.random_tiny(seed, size=37, depth=4)
     w.camera.height = 29
     _, rgb, ids, _ = render(rt, w)
-    compare(w, rgb, ids, min_robust=0.95)
+    compare(w, rgb, ids, min_robust=0.97)          # oracle: 0.9795 (seed 3) to 1.0
 
 
 def test_one_sphere_silhouette_and_shadow(rt):
@@ -103,7 +103,7 @@ def test_jittered_spp_and_graph_replay(rt):
         torch.cuda.synchronize()
         assert torch.equal(again[1], first[1])
         assert torch.allclose(again[0], first[0], atol=1e-5)
-    compare(w, first[0], first[1], min_robust=0.95)
+    compare(w, first[0], first[1], min_robust=0.98)       # oracle: 0.9983
 
 
 def test_pass_splits_give_the_same_frame(rt):
@@ -128,7 +128,7 @@ def test_pass_splits_give_the_same_frame(rt):
         assert torch.allclose(rgb, out[0][0], rtol=1e-5, atol=1e-6)
     assert torch.equal(ids_s, out[0][1])
     assert torch.allclose(rgb_s.mean(dim=2), out[0][0], rtol=1e-5, atol=2e-6)
-    compare(w, out[1][0], out[1][1], min_robust=0.95)
+    compare(w, out[1][0], out[1][1], min_robust=0.965)    # oracle: 0.973 (10 samples per pixel)
 
 
 def test_edge_cases(rt):
@@ -146,7 +146,7 @@ def test_edge_cases(rt):
     w = S.Workload(planes, S.Camera((0.0, 0.0, -5.0), (0.0, -0.2, 0.0), (0.0, 1.0, 0.0), 70.0, 17, 11),
                    S.Params(max_depth=3), "planes")
     _, rgb, ids, _ = render(rt, w)
-    compare(w, rgb, ids, min_robust=0.9)
+    compare(w, rgb, ids, min_robust=0.9)           # oracle: 0.909 (two planes near grazing incidence)
     w = S.config0()
     w.camera.width = w.camera.height = 1
     _, rgb, ids, _ = render(rt, w)
@@ -400,6 +400,6 @@ def test_deferred_shadow_queue_capacity(rt):
     assert st["rays"][:5] == [1024] * 5 and st["shadow"][:5] == [1024] * 5
     ref = oracle.render(scene, cam, p)
     rob = ref["margin"] > ROBUST
-    assert rob.mean() > 0.9
+    assert rob.mean() > 0.94                               # oracle: 0.949 (the box's edges and corners)
     np.testing.assert_allclose(rgb.reshape(-1, 3).cpu().numpy()[rob], ref["rgb"][rob], rtol=0, atol=1e-3)
     assert (ids.reshape(-1).cpu().numpy()[rob] == ref["ids"][rob, 0]).all()

@@ -72,7 +72,7 @@ def test_moved_scene_frames_match_the_oracle_and_refit_back_restores(rt, layout)
     assert st["status"] == 0
     out = oracle.render(m, w.camera, w.params)
     rob = out["margin"] > ROBUST
-    assert rob.mean() > 0.95
+    assert rob.mean() > 0.98                               # oracle: 0.9875 (layout-independent)
     g_ids = ids.reshape(-1, w.params.spp).cpu().numpy()
     assert (g_ids[rob] == out["ids"][rob]).all()
     err = np.abs(rgb.reshape(-1, 3).double().cpu().numpy() - out["rgb"]).max(1)
@@ -154,10 +154,15 @@ def test_config2_refit_is_exact_and_moved_frame_follows_the_oracle(rt):
     rgb_s, ids = r.render(rt.FLAG_SYNC)
     torch.cuda.synchronize()
     assert r.read_stats()["status"] == 0
-    pixels = S.pixel_subset(w.camera, 8, 31)
+    # pixels whose first camera ray hits a moved icosphere (found by the oracle on the moved scene), and others
+    cand = S.pixel_subset(w.camera, 3000, 31)
+    o, d = oracle.camera_rays(w.camera, w.params, cand, sample=0)
+    _, ih, _ = oracle.closest(m, o, d)
+    pixels = np.sort(np.concatenate([cand[ih >= 0][:16], cand[ih < 0][:4]]))
     out = oracle.render(m, w.camera, w.params, pixels)
+    assert (out["ids"][:, 0] >= 0).sum() >= 16
     rob = out["margin_s"] > ROBUST
-    assert rob.mean() > 0.8
+    assert rob.mean() > 0.87                               # oracle: 0.878 (90% of the object pixels' samples, all of the others')
     g = rgb_s.reshape(-1, w.params.spp, 3).double().cpu().numpy()[pixels]
     gi = ids.reshape(-1, w.params.spp).cpu().numpy()[pixels]
     assert (gi[rob] == out["ids"][rob]).all()
@@ -178,7 +183,7 @@ def test_spheres_only_and_empty_scenes(rt):
         torch.cuda.synchronize()
         out = oracle.render(m, w.camera, w.params)
         rob = out["margin"] > ROBUST
-        assert rob.mean() > 0.97
+        assert rob.mean() > 0.98                           # oracle: 0.9992
         assert (ids.reshape(-1).cpu().numpy()[rob] == out["ids"][rob, 0]).all()
         assert np.abs(rgb.reshape(-1, 3).double().cpu().numpy() - out["rgb"]).max(1)[rob].max() <= 1e-3
     planes = S.make_scene(planes=[[0.0, 1.0, 0.0, -1.0]], plane_mat=[0], materials=w.scene.materials[:1],
@@ -207,5 +212,5 @@ def test_batched_frame_after_refit_equals_single_frames(rt):
         assert torch.allclose(rgb, x, rtol=1e-5, atol=1e-6)
         out = oracle.render(m, w.camera, w.params)
         rob = out["margin"] > ROBUST
-        assert rob.mean() > 0.95
+        assert rob.mean() > 0.97                           # oracle: 0.9754 to 0.9900
         assert (u.reshape(-1).cpu().numpy()[rob] == out["ids"][rob, 0]).all()
