@@ -343,9 +343,6 @@ rt_status rt_mlp_grad(const uint16_t* w_bf16, const uint16_t* x_bf16, const floa
  * w_bf16 and clears grad. */
 rt_status rt_mlp_adam(float* w, uint16_t* w_bf16, float* m, float* v, float* grad, int32_t step, float lr,
                       float b1, float b2, float eps, void* stream);
-/* Diagnostic: d [32][32] = a [32][16] x b [16][32] (BF16 in, FP32 out) on one
- * matrix-core instruction, for checking the operand layout the kernels use. */
-rt_status rt_mlp_mfma_probe(const uint16_t* a, const uint16_t* b, float* d, void* stream);
 
 /* ---- learned form: frames whose recursion below `depth` is answered by the network ----
  * At depth `depth`, a ray that misses returns the background and a ray that

@@ -70,22 +70,6 @@ __device__ __forceinline__ f32x16 zero16() {
 }
 
 // ----------------------------------------------------------------------------
-// layout probe: D = A B for one 32x32x16 tile (A [32][16], B [16][32] bf16)
-// ----------------------------------------------------------------------------
-__global__ void k_mfma_probe(const uint16_t* A, const uint16_t* B, float* D) {
-    const int l = threadIdx.x & 63, h = l >> 5, r = l & 31;
-    short8 a, b;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        a[j] = (short)A[r * 16 + 8 * h + j];
-        b[j] = (short)B[(8 * h + j) * 32 + r];
-    }
-    const f32x16 d = mfma(a, b, zero16());
-#pragma unroll
-    for (int i = 0; i < 16; ++i) D[(8 * (i >> 2) + 4 * h + (i & 3)) * 32 + r] = d[i];
-}
-
-// ----------------------------------------------------------------------------
 // weight staging into LDS
 // ----------------------------------------------------------------------------
 // Forward weights: Wf[layer][out m][k-slot kappa], layers 0..4 (64 rows) and
@@ -118,26 +102,6 @@ __device__ void stage_forward(const uint16_t* __restrict__ w, uint16_t* wf) {
             b = ld4(src + swap23(8 * g + 4));
         }
         *reinterpret_cast<uint4*>(wf + row * kWp + 8 * g) = make_uint4(a.x, a.y, b.x, b.y);
-    }
-}
-
-// Backward weights: Wb[l][in m][k-slot kappa] = W_{l+1}[sigma(kappa)][m] for
-// layers 1..4 (the products g_h_{l} = W_{l+1}^T g_z_{l+1}), rows kWp apart like
-// the forward copy, and the output layer's transpose Wb6[m][k] = W6[k][m] (k < 3,
-// 16 columns).  One unit reads 8 consecutive columns m of a row j of W_{l+1}
-// (16 bytes; sigma is its own inverse, so that row lands in k-slot sigma(j)).
-__device__ void stage_backward(const uint16_t* __restrict__ w, uint16_t* wb, uint16_t* wb6) {
-    for (int u = threadIdx.x; u < 4 * kW * 8; u += blockDim.x) {
-        const int li = u >> 9, j = (u >> 3) & 63, mg = u & 7;   // li 0..3 -> weight layer 2..5 (index 1..4)
-        const uint4 v = *reinterpret_cast<const uint4*>(w + (li + 1) * kLayerElems + j * kW + 8 * mg);
-        const uint32_t q[4] = {v.x, v.y, v.z, v.w};
-        uint16_t* dst = wb + (li * kW + 8 * mg) * kWp + swap23(j);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) dst[i * kWp] = (uint16_t)(q[i >> 1] >> (16 * (i & 1)));
-    }
-    for (int e = threadIdx.x; e < kW * 16; e += blockDim.x) {
-        const int m = e / 16, k = e % 16;
-        wb6[e] = k < 3 ? w[5 * kLayerElems + k * kW + m] : (uint16_t)0;
     }
 }
 
@@ -284,6 +248,18 @@ __global__ __launch_bounds__(64 * kFwdWaves) void k_mlp_forward(const uint16_t* 
 // ----------------------------------------------------------------------------
 // forward + backward: accumulates dW (FP32, natural layout) and the loss sum
 // ----------------------------------------------------------------------------
+// A training step (16,384 samples) is too small to fill the matrix cores: the
+// kernel is bound by the latency of its dependent chain (weight staging, six
+// forward and five backward layers, each a few matrix instructions with LDS
+// round trips) and by the device atomics of dW.  What shortens the chain: the
+// staging issues all of a thread's global reads before its LDS writes, the
+// first group's features are read while the weights are staged, and the ReLU
+// mask of g_z is a packed integer test on the BF16 activations with the
+// hardware's packed conversion (38.9 -> 32.2 us per step).  A variant with
+// every wave independent (no block barriers; each product also issued with its
+// operands' roles swapped, so that the transposes dW needs come out of the
+// matrix cores instead of LDS) ran its chain in 29.5 us but, adding every
+// wave's dW separately, doubled the atomics to 57 us.
 constexpr int kGradWaves = 2;   // waves per block of the training kernel (LDS budget); one 32-column dW tile each
 
 static_assert(kGradWaves == 2, "each wave of the training kernel reduces one of the two 32-column dW tiles");
@@ -298,10 +274,93 @@ struct GradLds {
     uint16_t ht[kGradWaves][kW * 32];      // per wave: [feature][sample]
 };
 
-// D-layout value (tile mt, index i) of a packed operand b[2 mt + i / 8][i % 8]
-__device__ __forceinline__ float unpack_d(const short8 (&b)[4], int mt, int i) {
-    return bf2f((uint16_t)b[2 * mt + (i >> 3)][i & 7]);
+// g_z = bf16(g_h) where the layer's activation is positive, else +0, for the
+// accumulator values g[base .. base + 7] against the packed activation chunk a
+// (the same samples and features in the same register order).  A BF16 value is
+// positive exactly when its bits, read as a signed 16-bit integer, are; the
+// conversion is the hardware's packed one (nearest even).
+__device__ __forceinline__ short8 masked_grad(const f32x16& g, int base, const short8& a) {
+    uint32_t u[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bf16x2 v = {(__bf16)g[base + 2 * q], (__bf16)g[base + 2 * q + 1]};
+        const s16x2 act = {a[2 * q], a[2 * q + 1]};
+        const s16x2 keep = act > (s16x2){0, 0};   // all ones where positive
+        u[q] = __builtin_bit_cast(uint32_t, v) & __builtin_bit_cast(uint32_t, keep);
+    }
+    return __builtin_bit_cast(short8, make_uint4(u[0], u[1], u[2], u[3]));
 }
+
+// Forward weights as in stage_forward, and backward weights Wb[l][in m][k-slot
+// kappa] = W_{l+1}[sigma(kappa)][m] for layers 1..4 (the products g_h_{l} =
+// W_{l+1}^T g_z_{l+1}), rows kWp apart like the forward copy, plus the output
+// layer's transpose Wb6[m][k] = W6[k][m] (k < 3, 16 columns).  One backward
+// unit reads 8 consecutive columns m of a row j of W_{l+1} (16 bytes; sigma is
+// its own inverse, so that row lands in k-slot sigma(j)).  Every global read
+// of a thread is issued before its LDS writes (kStride threads; the trip
+// counts are exact multiples), so the reads overlap.
+template <int kStride>
+__device__ void stage_grad_weights(const uint16_t* __restrict__ w, GradLds& S) {
+    constexpr int kFwdUnits = kFwdRows * 8, kBwdUnits = 4 * kW * 8;
+    static_assert(kFwdUnits % kStride == 0 && kBwdUnits % kStride == 0 && (kW * 16) % kStride == 0, "stride");
+    {
+        constexpr int kIt = kFwdUnits / kStride;
+        uint2 a[kIt], b[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int u = threadIdx.x + it * kStride;
+            const int row = u >> 3, g = u & 7;
+            const int layer = row >> 6, m = row & 63;
+            const uint16_t* src = w + layer * kLayerElems + m * kW;
+            a[it] = make_uint2(0u, 0u);
+            b[it] = make_uint2(0u, 0u);
+            if (layer == 0) {
+                a[it] = ld4(src + 8 * g);
+                b[it] = ld4(src + 8 * g + 4);
+            } else if (layer < 5 || m < 3) {
+                a[it] = ld4(src + swap23(8 * g));
+                b[it] = ld4(src + swap23(8 * g + 4));
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int u = threadIdx.x + it * kStride;
+            *reinterpret_cast<uint4*>(S.wf + (u >> 3) * kWp + 8 * (u & 7)) =
+                make_uint4(a[it].x, a[it].y, b[it].x, b[it].y);
+        }
+    }
+    {
+        constexpr int kIt = kBwdUnits / kStride;
+        uint4 v[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int u = threadIdx.x + it * kStride;
+            const int li = u >> 9, j = (u >> 3) & 63, mg = u & 7;
+            v[it] = *reinterpret_cast<const uint4*>(w + (li + 1) * kLayerElems + j * kW + 8 * mg);
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int u = threadIdx.x + it * kStride;
+            const int li = u >> 9, j = (u >> 3) & 63, mg = u & 7;
+            const uint32_t q[4] = {v[it].x, v[it].y, v[it].z, v[it].w};
+            uint16_t* dst = S.wb + (li * kW + 8 * mg) * kWp + swap23(j);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dst[i * kWp] = (uint16_t)(q[i >> 1] >> (16 * (i & 1)));
+        }
+    }
+    {
+        constexpr int kIt = kW * 16 / kStride;
+        uint16_t v[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int e = threadIdx.x + it * kStride, m = e / 16, k = e % 16;
+            v[it] = k < 3 ? w[5 * kLayerElems + k * kW + m] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) S.wb6[threadIdx.x + it * kStride] = v[it];
+    }
+}
+
 
 // write a packed D-layout activation block to LDS as [feature][sample]
 __device__ __forceinline__ void store_dlayout(uint16_t* dst, const short8 (&b)[4], int l) {
@@ -360,23 +419,27 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __
                                                               int64_t count_base, float* __restrict__ dw,
                                                               float* __restrict__ loss_sum) {
     __shared__ __attribute__((aligned(16))) GradLds S;
-    stage_forward(w, S.wf);
-    stage_backward(w, S.wb, S.wb6);
-    const int wave = threadIdx.x >> 6;
-    for (int e = threadIdx.x & 63; e < 32 * 32; e += 64) S.gy[wave][e] = 0;
-    __syncthreads();
     // samples [count_base, count_base + n) of a batch whose valid size is *count_p
     if (count_p) n = min(n, max((int64_t)0, (int64_t)*count_p - count_base));
+    const int wave = threadIdx.x >> 6;
     const int l = threadIdx.x & 63, h = l >> 5, r = l & 31;
     const int64_t tiles = (n + 31) / 32;
     const int64_t groups = (tiles + kGradWaves - 1) / kGradWaves;
+    // the first group's features are read while the weights are staged
+    short8 b[4];
+    {
+        const int64_t s0 = ((int64_t)blockIdx.x * kGradWaves + wave) * 32 + r;
+        load_input(x, s0, (int64_t)blockIdx.x < groups && s0 < n, l, b);
+    }
+    stage_grad_weights<64 * kGradWaves>(w, S);
+    for (int e = threadIdx.x & 63; e < 32 * 32; e += 64) S.gy[wave][e] = 0;
+    __syncthreads();
     for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {   // block-uniform loop
         const int64_t t = g * kGradWaves + wave;
         const int64_t s = t * 32 + r;
         const bool valid = s < n;
         // forward, keeping every layer's operand in this lane's LDS slots
-        short8 b[4];
-        load_input(x, s, valid, l, b);
+        if (g != blockIdx.x) load_input(x, s, valid, l, b);
 #pragma unroll
         for (int q = 0; q < 4; ++q) S.act[wave][0][q][l] = b[q];
         for (int k = 1; k < 6; ++k) {
@@ -416,11 +479,10 @@ __global__ __launch_bounds__(64 * kGradWaves) void k_mlp_grad(const uint16_t* __
             // g_z_L = bf16(g_h_L * [h_L > 0]), packed like the forward activations
             short8 hl[4], gz[4];
             load_act(S, wave, L, l, hl);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                gz[i >> 3][i & 7] = (short)(unpack_d(hl, 0, i) > 0.0f ? f2bf(gh0[i]) : 0);
-                gz[2 + (i >> 3)][i & 7] = (short)(unpack_d(hl, 1, i) > 0.0f ? f2bf(gh1[i]) : 0);
-            }
+            gz[0] = masked_grad(gh0, 0, hl[0]);
+            gz[1] = masked_grad(gh0, 8, hl[1]);
+            gz[2] = masked_grad(gh1, 0, hl[2]);
+            gz[3] = masked_grad(gh1, 8, hl[3]);
             __syncthreads();
             store_dlayout(S.gz[wave], gz, l);
             short8 hp[4];
@@ -605,16 +667,6 @@ rt_status rt_mlp_adam(float* w, uint16_t* w_bf16, float* m, float* v, float* gra
         return RT_ERR_INVALID_ARG;
     }
     return mlp_adam_launch(w, w_bf16, m, v, grad, step, lr, b1, b2, eps, static_cast<hipStream_t>(stream));
-}
-
-rt_status rt_mlp_mfma_probe(const uint16_t* a, const uint16_t* b, float* d, void* stream) {
-    if (!a || !b || !d) {
-        set_error("rt_mlp_mfma_probe: NULL argument");
-        return RT_ERR_INVALID_ARG;
-    }
-    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream), a, b, d);
-    HIP_TRY_M(hipGetLastError());
-    return RT_OK;
 }
 
 }  // extern "C"

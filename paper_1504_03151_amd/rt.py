@@ -131,7 +131,6 @@ SIGNATURES = {
     "rt_mlp_forward": (C.c_int32, [_P, _P, C.c_int64, _P, _P]),
     "rt_mlp_grad": (C.c_int32, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, _P]),
     "rt_mlp_adam": (C.c_int32, [_P, _P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float, _P]),
-    "rt_mlp_mfma_probe": (C.c_int32, [_P, _P, _P, _P]),
     "rt_cache_state_layout": (C.c_int32, [C.c_int32, C.POINTER(CacheLayout)]),
     "rt_cache_state_bytes": (C.c_size_t, [C.c_int32]),
     "rt_cache_init": (C.c_int32, [_P, C.c_int32, _P, _P]),
@@ -539,15 +538,6 @@ def mlp_grad(w_bf16, x_bf16, target, dw, loss_sum, n_total=None, stream=None):
 def mlp_adam(w, w_bf16, m, v, grad, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, stream=None):
     _check(lib().rt_mlp_adam(w.data_ptr(), w_bf16.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(), int(step),
                              lr, b1, b2, eps, _stream_ptr(stream)), "rt_mlp_adam")
-
-
-def mfma_probe(a_bits, b_bits, stream=None):
-    import torch
-    d = torch.empty((32, 32), dtype=torch.float32, device=a_bits.device)
-    _check(lib().rt_mlp_mfma_probe(a_bits.data_ptr(), b_bits.data_ptr(), d.data_ptr(), _stream_ptr(stream)),
-           "rt_mlp_mfma_probe")
-    return d
-
 
 
 class RadianceCache:

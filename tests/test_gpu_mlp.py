@@ -44,14 +44,6 @@ def _close(a, b, what):
     assert cos > 0.999 and rel < 2e-2, (what, cos, rel)
 
 
-def test_mfma_operand_layout(rt):
-    rng = np.random.default_rng(0)
-    A = rng.integers(-4, 5, size=(32, 16)).astype(np.float32)
-    B = rng.integers(-4, 5, size=(16, 32)).astype(np.float32)
-    d = rt.mfma_probe(rt.bf16_bits(torch.from_numpy(A).cuda()), rt.bf16_bits(torch.from_numpy(B).cuda()))
-    np.testing.assert_array_equal(d.cpu().numpy(), A @ B)
-
-
 def _problem(seed, n):
     rng = np.random.default_rng(seed)
     ws = S.mlp_init_weights(seed)
