@@ -376,12 +376,26 @@ HD void cswap(float& ka, int32_t& ca, float& kb, int32_t& cb) {
 // Four-wide traversal: the hit children of a node are ordered by entry
 // distance (five-comparator network, misses sorted last), the far ones pushed,
 // the nearest taken next; leaves are postponed as in the binary traversal.
-// Byte i of a quantized plane word, decoded: fma(q, scale, origin).
-HD float qplane(uint32_t w, int i, float scale, float origin) {
-    return fmaf((float)((w >> (8 * i)) & 0xFFu), scale, origin);
+// Slab test of one child from its six plane distances (x0, x1, y0, y1, z0, z1
+// along the ray), as in box1.
+HD bool slab_t(float x0, float x1, float y0, float y1, float z0, float z1, float tbest, float& tn) {
+    const float tmin = max3f(fminf(x0, x1), fminf(y0, y1), fmaxf(fminf(z0, z1), 0.0f));
+    const float tmax = min3f(fmaxf(x0, x1), fmaxf(y0, y1), fminf(fmaxf(z0, z1), tbest));
+    tn = tmin;
+    return tmin <= tmax;
 }
 
-// Children of a quantized four-wide node: decoded boxes, then the float slab test.
+// Distance along the ray to the plane of byte i of a quantized plane word:
+// (q scale + corner - o) / d folded into one fma, q a + b with a = scale / d
+// and b = (corner - o) / d per axis.  The folded form differs from decoding
+// the plane first by a few FP32 roundings of quantities bounded by the
+// coordinate magnitude, far inside the builder's outward padding of 2^-19 of
+// the scene scale, so the test stays conservative.
+HD float qdist(uint32_t w, int i, float a, float b) {
+    return fmaf((float)((w >> (8 * i)) & 0xFFu), a, b);
+}
+
+// Children of a quantized four-wide node: folded plane distances, then the slab test.
 HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, bool& b2, bool& b3, float& k0,
                float& k1, float& k2, float& k3, int4& ch) {
     const float4 o = n->origin;
@@ -392,14 +406,17 @@ HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, 
     const float sy = as_float_i((int)(((eb >> 8) & 0xFFu) << 23));
     const float sz = as_float_i((int)(((eb >> 16) & 0xFFu) << 23));
     const uint32_t valid = eb >> 24;
-    b0 = ((valid & 1u) != 0u) & box1(r, qplane(qa.x, 0, sx, o.x), qplane(qa.y, 0, sx, o.x), qplane(qa.z, 0, sy, o.y),
-                              qplane(qa.w, 0, sy, o.y), qplane(qb.x, 0, sz, o.z), qplane(qb.y, 0, sz, o.z), tbest, k0);
-    b1 = ((valid & 2u) != 0u) & box1(r, qplane(qa.x, 1, sx, o.x), qplane(qa.y, 1, sx, o.x), qplane(qa.z, 1, sy, o.y),
-                              qplane(qa.w, 1, sy, o.y), qplane(qb.x, 1, sz, o.z), qplane(qb.y, 1, sz, o.z), tbest, k1);
-    b2 = ((valid & 4u) != 0u) & box1(r, qplane(qa.x, 2, sx, o.x), qplane(qa.y, 2, sx, o.x), qplane(qa.z, 2, sy, o.y),
-                              qplane(qa.w, 2, sy, o.y), qplane(qb.x, 2, sz, o.z), qplane(qb.y, 2, sz, o.z), tbest, k2);
-    b3 = ((valid & 8u) != 0u) & box1(r, qplane(qa.x, 3, sx, o.x), qplane(qa.y, 3, sx, o.x), qplane(qa.z, 3, sy, o.y),
-                              qplane(qa.w, 3, sy, o.y), qplane(qb.x, 3, sz, o.z), qplane(qb.y, 3, sz, o.z), tbest, k3);
+    const float ax = sx * r.inv.x, ay = sy * r.inv.y, az = sz * r.inv.z;
+    const float bx = fmaf(o.x, r.inv.x, -r.oinv.x), by = fmaf(o.y, r.inv.y, -r.oinv.y),
+                bz = fmaf(o.z, r.inv.z, -r.oinv.z);
+    b0 = ((valid & 1u) != 0u) & slab_t(qdist(qa.x, 0, ax, bx), qdist(qa.y, 0, ax, bx), qdist(qa.z, 0, ay, by),
+                                       qdist(qa.w, 0, ay, by), qdist(qb.x, 0, az, bz), qdist(qb.y, 0, az, bz), tbest, k0);
+    b1 = ((valid & 2u) != 0u) & slab_t(qdist(qa.x, 1, ax, bx), qdist(qa.y, 1, ax, bx), qdist(qa.z, 1, ay, by),
+                                       qdist(qa.w, 1, ay, by), qdist(qb.x, 1, az, bz), qdist(qb.y, 1, az, bz), tbest, k1);
+    b2 = ((valid & 4u) != 0u) & slab_t(qdist(qa.x, 2, ax, bx), qdist(qa.y, 2, ax, bx), qdist(qa.z, 2, ay, by),
+                                       qdist(qa.w, 2, ay, by), qdist(qb.x, 2, az, bz), qdist(qb.y, 2, az, bz), tbest, k2);
+    b3 = ((valid & 8u) != 0u) & slab_t(qdist(qa.x, 3, ax, bx), qdist(qa.y, 3, ax, bx), qdist(qa.z, 3, ay, by),
+                                       qdist(qa.w, 3, ay, by), qdist(qb.x, 3, az, bz), qdist(qb.y, 3, az, bz), tbest, k3);
     ch = make_int4((int)qb.z, (int)qb.w, qc.x, qc.y);
 }
 
