@@ -376,15 +376,6 @@ HD void cswap(float& ka, int32_t& ca, float& kb, int32_t& cb) {
 // Four-wide traversal: the hit children of a node are ordered by entry
 // distance (five-comparator network, misses sorted last), the far ones pushed,
 // the nearest taken next; leaves are postponed as in the binary traversal.
-// Slab test of one child from its six plane distances (x0, x1, y0, y1, z0, z1
-// along the ray), as in box1.
-HD bool slab_t(float x0, float x1, float y0, float y1, float z0, float z1, float tbest, float& tn) {
-    const float tmin = max3f(fminf(x0, x1), fminf(y0, y1), fmaxf(fminf(z0, z1), 0.0f));
-    const float tmax = min3f(fmaxf(x0, x1), fmaxf(y0, y1), fminf(fmaxf(z0, z1), tbest));
-    tn = tmin;
-    return tmin <= tmax;
-}
-
 // Distance along the ray to the plane of byte i of a quantized plane word:
 // (q scale + corner - o) / d folded into one fma, q a + b with a = scale / d
 // and b = (corner - o) / d per axis.  The folded form differs from decoding
@@ -395,7 +386,12 @@ HD float qdist(uint32_t w, int i, float a, float b) {
     return fmaf((float)((w >> (8 * i)) & 0xFFu), a, b);
 }
 
-// Children of a quantized four-wide node: folded plane distances, then the slab test.
+// Children of a quantized four-wide node: folded plane distances, then the
+// slab test.  Per axis the plane word nearer along the ray (the low planes
+// when the direction component is non-negative, else the high ones) is picked
+// once per node, so each child's entry is a max and its exit a min of three
+// distances with no per-axis min/max (the same result: for a valid child the
+// low plane is not above the high one, and no distance is NaN).
 HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, bool& b2, bool& b3, float& k0,
                float& k1, float& k2, float& k3, int4& ch) {
     const float4 o = n->origin;
@@ -409,14 +405,22 @@ HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, 
     const float ax = sx * r.inv.x, ay = sy * r.inv.y, az = sz * r.inv.z;
     const float bx = fmaf(o.x, r.inv.x, -r.oinv.x), by = fmaf(o.y, r.inv.y, -r.oinv.y),
                 bz = fmaf(o.z, r.inv.z, -r.oinv.z);
-    b0 = ((valid & 1u) != 0u) & slab_t(qdist(qa.x, 0, ax, bx), qdist(qa.y, 0, ax, bx), qdist(qa.z, 0, ay, by),
-                                       qdist(qa.w, 0, ay, by), qdist(qb.x, 0, az, bz), qdist(qb.y, 0, az, bz), tbest, k0);
-    b1 = ((valid & 2u) != 0u) & slab_t(qdist(qa.x, 1, ax, bx), qdist(qa.y, 1, ax, bx), qdist(qa.z, 1, ay, by),
-                                       qdist(qa.w, 1, ay, by), qdist(qb.x, 1, az, bz), qdist(qb.y, 1, az, bz), tbest, k1);
-    b2 = ((valid & 4u) != 0u) & slab_t(qdist(qa.x, 2, ax, bx), qdist(qa.y, 2, ax, bx), qdist(qa.z, 2, ay, by),
-                                       qdist(qa.w, 2, ay, by), qdist(qb.x, 2, az, bz), qdist(qb.y, 2, az, bz), tbest, k2);
-    b3 = ((valid & 8u) != 0u) & slab_t(qdist(qa.x, 3, ax, bx), qdist(qa.y, 3, ax, bx), qdist(qa.z, 3, ay, by),
-                                       qdist(qa.w, 3, ay, by), qdist(qb.x, 3, az, bz), qdist(qb.y, 3, az, bz), tbest, k3);
+    const bool px = r.inv.x >= 0.0f, py = r.inv.y >= 0.0f, pz = r.inv.z >= 0.0f;
+    const uint32_t nx = px ? qa.x : qa.y, fx = px ? qa.y : qa.x;
+    const uint32_t ny = py ? qa.z : qa.w, fy = py ? qa.w : qa.z;
+    const uint32_t nz = pz ? qb.x : qb.y, fz = pz ? qb.y : qb.x;
+#define MIRT_QCHILD(i, b, k)                                                                              \
+    {                                                                                                     \
+        const float tn = max3f(qdist(nx, i, ax, bx), qdist(ny, i, ay, by), fmaxf(qdist(nz, i, az, bz), 0.0f)); \
+        const float tf = min3f(qdist(fx, i, ax, bx), qdist(fy, i, ay, by), fminf(qdist(fz, i, az, bz), tbest)); \
+        k = tn;                                                                                           \
+        b = ((valid >> i) & 1u) != 0u && tn <= tf;                                                        \
+    }
+    MIRT_QCHILD(0, b0, k0)
+    MIRT_QCHILD(1, b1, k1)
+    MIRT_QCHILD(2, b2, k2)
+    MIRT_QCHILD(3, b3, k3)
+#undef MIRT_QCHILD
     ch = make_int4((int)qb.z, (int)qb.w, qc.x, qc.y);
 }
 
