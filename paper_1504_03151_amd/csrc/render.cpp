@@ -14,6 +14,7 @@
 // Queue tails live in device counters, so no step reads anything back to the
 // host and the whole frame can be captured in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 #include <algorithm>
 #include <cmath>
@@ -399,7 +400,7 @@ struct QueueFetch {
     }
 };
 
-template <bool COUNT, bool BATCH>
+template <bool COUNT, bool BATCH, int L = -1>
 __device__ __forceinline__ void extend_queue(const DevScene& sc, const BatchScene* tab, const RayQ& q, const HitQ& hit,
                                              const uint32_t* count_p, uint32_t* cursor, uint32_t cap, uint32_t chunk,
                                              int32_t* overflow, unsigned long long* work_out) {
@@ -419,7 +420,7 @@ __device__ __forceinline__ void extend_queue(const DevScene& sc, const BatchScen
                 }
                 const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? (q.meta[i] >> 20) : 0u);
                 const TRay r = make_tray(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
-                const Hit h = traverse<false, COUNT>(S, r, INFINITY, stk, w);
+                const Hit h = traverse<false, COUNT, L>(S, r, INFINITY, stk, w);
                 hit.t[i] = h.t;
                 hit.prim[i] = h.prim;
             }
@@ -429,28 +430,31 @@ __device__ __forceinline__ void extend_queue(const DevScene& sc, const BatchScen
 }
 
 // Seven waves per SIMD: 71 registers instead of 80 (six waves), no spills in
-// the single-scene form.
-template <bool COUNT, bool BATCH>
+// the single-scene form.  L: the node layout compiled in (-1: read from the
+// scene, as batched frames, whose scenes may differ, and counting frames do);
+// a kernel built for one layout spends no registers on the others' code.
+template <bool COUNT, bool BATCH, int L = -1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) void k_extend(DevScene sc, const BatchScene* tab, RayQ q, HitQ hit,
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
                                                 uint32_t chunk, int32_t* overflow, unsigned long long* work_out) {
-    extend_queue<COUNT, BATCH>(sc, tab, q, hit, count_p, cursor, cap, chunk, overflow, work_out);
+    extend_queue<COUNT, BATCH, L>(sc, tab, q, hit, count_p, cursor, cap, chunk, overflow, work_out);
 }
 
 // The same for the bounces after the first: their queues are small and incoherent, so a launch is bound by
 // the latency of each ray's chain of node fetches; eight waves per SIMD (a few spilled registers) hide more
 // of it than the six the register count otherwise allows.
+template <int L>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_extend_deep(
     DevScene sc, RayQ q, HitQ hit, const uint32_t* count_p, uint32_t* cursor, uint32_t cap, uint32_t chunk,
     int32_t* overflow) {
-    extend_queue<false, false>(sc, nullptr, q, hit, count_p, cursor, cap, chunk, overflow, nullptr);
+    extend_queue<false, false, L>(sc, nullptr, q, hit, count_p, cursor, cap, chunk, overflow, nullptr);
 }
 
 // Any-hit over the shadow queue; adds the contribution of each unblocked light
 // to its pixel.  Eight waves per SIMD (a few spilled registers): more rays in
 // flight hide more of the node-fetch latency than the six the register count
 // otherwise allows.
-template <bool COUNT, bool BATCH>
+template <bool COUNT, bool BATCH, int L = -1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_shadow(DevScene sc, const BatchScene* tab, ShadowQ s,
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
                                                 uint32_t chunk, float* acc, int32_t* overflow,
@@ -472,7 +476,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                 const uint32_t i = perm ? perm[j] : begin + j;   // binned order of deferred shadow rays
                 const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? s.sid[i] : 0u);
                 const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
-                const Hit h = traverse<true, COUNT>(S, r, s.tmax[i], stk, w);
+                const Hit h = traverse<true, COUNT, L>(S, r, s.tmax[i], stk, w);
                 if (h.prim < 0) {
                     if (vis) {   // binned order visits pixels at random: mark the entry, add in queue order later
                         atomicOr(vis + (i >> 5), 1u << (i & 31u));
@@ -1660,16 +1664,29 @@ struct FrameArgs {
     bool bin_shadows;           // deferred shadow rays are binned before their traversal
 };
 
+// Calls f with the scene's node layout as a compile-time constant (the
+// single-scene traversal kernels are built for each layout).
+template <class F>
+static void by_layout(int wide, F&& f) {
+    if (wide == 2) f(std::integral_constant<int, 2>());
+    else if (wide == 1) f(std::integral_constant<int, 1>());
+    else f(std::integral_constant<int, 0>());
+}
+
 static rt_status frame_grids(FrameArgs& A) {
     A.lds = 0;   // the split stack's LDS part is static
-    rt_status s1 = A.count_work ? persistent_grid(k_extend<true, false>, 0, A.gx)
-                                : persistent_grid(k_extend<false, false>, 0, A.gx);
+    rt_status s1 = RT_OK, s2 = RT_OK, s3 = RT_OK;
+    by_layout(A.sc.wide, [&](auto L) {
+        constexpr int kL = decltype(L)::value;
+        s1 = A.count_work ? persistent_grid(k_extend<true, false>, 0, A.gx)
+                          : persistent_grid(k_extend<false, false, kL>, 0, A.gx);
+        s2 = A.count_work ? persistent_grid(k_shadow<true, false>, 0, A.gs)
+                          : persistent_grid(k_shadow<false, false, kL>, 0, A.gs);
+        s3 = persistent_grid(k_extend_deep<kL>, 0, A.gxd);
+    });
     if (s1 != RT_OK) return s1;
-    s1 = A.count_work ? persistent_grid(k_shadow<true, false>, 0, A.gs)
-                      : persistent_grid(k_shadow<false, false>, 0, A.gs);
-    if (s1 != RT_OK) return s1;
-    s1 = persistent_grid(k_extend_deep, 0, A.gxd);
-    if (s1 != RT_OK) return s1;
+    if (s2 != RT_OK) return s2;
+    if (s3 != RT_OK) return s3;
     A.gxd = std::min<int>(A.gxd, (int)(kMaxPersistentThreads / 256));
     A.gxd = (int)std::min<int64_t>(A.gxd, std::max<int64_t>(kXcd, ((int64_t)A.pl.qcap + 255) / 256));
     A.gx = std::min<int>(A.gx, (int)(kMaxPersistentThreads / 256));
@@ -1731,8 +1748,11 @@ static void enqueue_shadow_segment(const FrameArgs& A, const ShadowQ& sq, const 
             hipLaunchKernelGGL((k_shadow<true, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq,
                                g.end_p, g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p, vis);
         else
-            hipLaunchKernelGGL((k_shadow<false, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq,
-                               g.end_p, g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p, vis);
+            by_layout(A.sc.wide, [&](auto L) {
+                hipLaunchKernelGGL((k_shadow<false, false, decltype(L)::value>), dim3(g.grid), dim3(256), A.lds, st,
+                                   A.sc, nullptr, sq, g.end_p, g.cursor, g.cap, A.chunk, acc, g.overflow, swork,
+                                   g.perm, g.begin_p, vis);
+            });
     }
     if (vis) hipLaunchKernelGGL(k_vis_resolve, dim3(2048), dim3(256), 0, st, sq, vis, g.begin_p, g.end_p, g.cap, acc);
 }
@@ -1791,12 +1811,17 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
                                        ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk,
                                        overflow, work);
                 else if (k > 0)
-                    hipLaunchKernelGGL(k_extend_deep, dim3(A.gxd), dim3(256), 0, st, A.sc, qi, hq, ctr + kCtrRays + k,
-                                       xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk, overflow);
+                    by_layout(A.sc.wide, [&](auto L) {
+                        hipLaunchKernelGGL(k_extend_deep<decltype(L)::value>, dim3(A.gxd), dim3(256), 0, st, A.sc, qi,
+                                           hq, ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk,
+                                           overflow);
+                    });
                 else
-                    hipLaunchKernelGGL((k_extend<false, false>), dim3(gx), dim3(256), A.lds, st, A.sc, nullptr, qi,
-                                       hq, ctr + kCtrRays + k, xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk,
-                                       overflow, work);
+                    by_layout(A.sc.wide, [&](auto L) {
+                        hipLaunchKernelGGL((k_extend<false, false, decltype(L)::value>), dim3(gx), dim3(256), A.lds,
+                                           st, A.sc, nullptr, qi, hq, ctr + kCtrRays + k,
+                                           xcd_cursor(ctr, kCtrRayCur + k), pl.qcap, A.chunk, overflow, work);
+                    });
             }
             {
                 KernelTimer kt(A.time_kernels, st, 1);
@@ -2353,9 +2378,11 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
                                    c_ + kCtrRays + k, xcd_cursor(c_, kCtrRayCur + k), shc.qcap, A.chunk, overflow,
                                    work);
             else
-                hipLaunchKernelGGL((k_extend<false, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, qi, h,
-                                   c_ + kCtrRays + k, xcd_cursor(c_, kCtrRayCur + k), shc.qcap, A.chunk, overflow,
-                                   work);
+                by_layout(A.sc.wide, [&](auto L) {
+                    hipLaunchKernelGGL((k_extend<false, false, decltype(L)::value>), dim3(A.gx), dim3(256), 0, st,
+                                       A.sc, nullptr, qi, h, c_ + kCtrRays + k, xcd_cursor(c_, kCtrRayCur + k),
+                                       shc.qcap, A.chunk, overflow, work);
+                });
         }
         {
             KernelTimer kt(A.time_kernels, st, 1);
@@ -2406,9 +2433,11 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     // depth cd: closest hits, then cache queries instead of shading
     {
         KernelTimer kt(A.time_kernels, st, 0);
-        hipLaunchKernelGGL((k_extend<false, false>), dim3(A.gx), dim3(256), 0, st, A.sc, nullptr, q[cd & 1], hq,
-                           ctr + kCtrRays + cd, xcd_cursor(ctr, kCtrRayCur + cd), pl.qcap, A.chunk, overflow,
-                           nullptr);
+        by_layout(A.sc.wide, [&](auto L) {
+            hipLaunchKernelGGL((k_extend<false, false, decltype(L)::value>), dim3(A.gx), dim3(256), 0, st, A.sc,
+                               nullptr, q[cd & 1], hq, ctr + kCtrRays + cd, xcd_cursor(ctr, kCtrRayCur + cd),
+                               pl.qcap, A.chunk, overflow, nullptr);
+        });
     }
     hipLaunchKernelGGL(k_cache_gate, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, w_bf16, kMlpParams, health, ctr,
                        ctr_fb, cd, A.stats);

@@ -487,7 +487,9 @@ HD bool trace_bvh4(const DevScene& s, const TRay& r, Hit& h, Stack& stk, Work& w
 // Closest hit (ANY = false) or any hit (ANY = true) in (0, tmax).  Ties in t
 // go to the smaller original id.  Stack is a small push/pop policy object
 // (LDS-resident on the GPU, an array on the host).
-template <bool ANY, bool COUNT, class Stack>
+// L selects the node layout at compile time (0 binary, 1 four-wide float, 2
+// four-wide quantized), or at run time from s.wide when L < 0.
+template <bool ANY, bool COUNT, int L = -1, class Stack>
 HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& work) {
     Hit h;
     h.t = tmax;
@@ -503,8 +505,9 @@ HD Hit traverse(const DevScene& s, const TRay& r, float tmax, Stack& stk, Work& 
             if (ANY) return h;
         }
     }
-    if (s.wide == 2) trace_bvh4<ANY, COUNT, true>(s, r, h, stk, work);
-    else if (s.wide == 1) trace_bvh4<ANY, COUNT, false>(s, r, h, stk, work);
+    const int wide = L >= 0 ? L : s.wide;
+    if (wide == 2) trace_bvh4<ANY, COUNT, true>(s, r, h, stk, work);
+    else if (wide == 1) trace_bvh4<ANY, COUNT, false>(s, r, h, stk, work);
     else trace_bvh2<ANY, COUNT>(s, r, h, stk, work);
     return h;
 }
