@@ -207,8 +207,13 @@ __device__ __forceinline__ LdsStack lds_stack(int32_t* smem, int stack_size) {
 // paths of deep trees) in a per-thread global region ([entry][thread]).
 // Keeping LDS at 4 KB per wave lets register pressure, not LDS, set occupancy.
 constexpr int kSplitLds = 16;
+// The LDS column is typed with the LDS address space: given two generic
+// pointers, the compiler merges the two loads of a pop into one flat load
+// through a selected pointer, which waits on the vector memory counter and
+// occupies the texture address unit even when every lane reads LDS.
+typedef __attribute__((address_space(3))) int32_t lds_i32;
 struct SplitStack {
-    int32_t* p;      // LDS column of this lane
+    lds_i32* p;      // LDS column of this lane
     int32_t* g;      // overflow column of this thread (stride = threads of the grid)
     uint32_t gstride;
     int sp;
@@ -224,13 +229,15 @@ struct SplitStack {
     }
     __device__ int32_t pop() {
         --sp;
-        return sp < kSplitLds ? p[sp * 64] : g[(size_t)(sp - kSplitLds) * gstride];
+        int32_t v = p[min(sp, kSplitLds - 1) * 64];
+        if (sp >= kSplitLds) v = g[(size_t)(sp - kSplitLds) * gstride];
+        return v;
     }
 };
 
 __device__ __forceinline__ SplitStack split_stack(int32_t* smem, int32_t* overflow) {
     SplitStack s;
-    s.p = smem + (threadIdx.x >> 6) * kSplitLds * 64 + (threadIdx.x & 63);
+    s.p = (lds_i32*)(smem + (threadIdx.x >> 6) * kSplitLds * 64 + (threadIdx.x & 63));
     s.gstride = gridDim.x * blockDim.x;
     s.g = overflow + blockIdx.x * blockDim.x + threadIdx.x;
     s.sp = 0;
