@@ -7,13 +7,18 @@
 
 namespace mirt {
 
-// Per axis: origin p = the lowest child plane, scale 2^e the smallest power of
-// two with 255 * 2^e >= the node's extent; a lower plane takes the largest q
-// whose decoded fma(q, 2^e, p) is <= the true plane, an upper plane the
-// smallest q whose decoded value is >= it (checked with the same fma the
-// traversal decodes with), so every decoded box contains its child's padded
-// box.  lo/hi: child boxes; valid: used slots; child: the four references.
-// Returns false if an axis cannot be covered (non-finite extents).
+// Per axis: scale 2^e, the smallest power of two with 255 * 2^e >= the
+// node's extent; the node stores the scale s = 4 * 2^e (exponent byte e + 129)
+// and the origin p = the lowest child plane m minus 1024 * 2^e (rounded, then
+// lowered an ulp at a time until q = 0 decodes to at most m), so that byte q
+// decodes to the plane fma(256 + q / 4, s, p) = p + (1024 + q) 2^e: the value
+// 256 + q / 4 is exact in FP16, which the device traversal widens two bytes at
+// a time.  A lower plane takes the largest q whose decoded value is <= the
+// true plane, an upper plane the smallest q whose decoded value is >= it
+// (checked with that same fma), so every decoded box contains its child's
+// padded box.  lo/hi: child boxes; valid: used slots; child: the four
+// references.  Returns false if an axis cannot be covered (non-finite
+// extents).
 HD bool quantize_children(const float (&lo)[4][3], const float (&hi)[4][3], const bool (&valid)[4], int4 child,
                           Node4q& q) {
 #pragma clang fp contract(off)
@@ -30,7 +35,6 @@ HD bool quantize_children(const float (&lo)[4][3], const float (&hi)[4][3], cons
             mn = 0.0f;
             mx = 0.0f;
         }
-        p[a] = mn;
         const double ext = (double)mx - mn;
         int e = -126;
         if (ext > 0.0) {
@@ -41,24 +45,31 @@ HD bool quantize_children(const float (&lo)[4][3], const float (&hi)[4][3], cons
             e = c > -126 ? c : -126;
         }
         for (;; ++e) {
-            if (e > 127) return false;
-            const float sc = as_float_i((e + 127) << 23);   // 2^e, a normal float
+            if (e > 125) return false;
+            const float sc = as_float_i((e + 127) << 23);       // 2^e, a normal float
+            const float s4 = as_float_i((e + 129) << 23);       // the stored scale 4 * 2^e
+            float org = (float)((double)mn - 1024.0 * (double)sc);
+            while (fmaf(256.0f, s4, org) > mn) org = nextafterf(org, -INFINITY);
+            p[a] = org;
             bool ok = true;
             uint32_t wl = 0, wh = 0;
             for (int i = 0; i < 4 && ok; ++i) {
-                if (!valid[i]) continue;
+                if (!valid[i]) {   // an unused slot decodes to an inverted box (low plane above high)
+                    wl |= 255u << (8 * i);
+                    continue;
+                }
                 double ql = floor(((double)lo[i][a] - mn) / sc);
-                ql = ql > 0.0 ? ql : 0.0;
-                while (ql > 0.0 && fmaf((float)ql, sc, mn) > lo[i][a]) ql -= 1.0;
+                ql = ql > 0.0 ? (ql < 255.0 ? ql : 255.0) : 0.0;
+                while (ql > 0.0 && fmaf(256.0f + 0.25f * (float)ql, s4, org) > lo[i][a]) ql -= 1.0;
                 double qh = ceil(((double)hi[i][a] - mn) / sc);
                 qh = qh > 0.0 ? qh : 0.0;
-                while (qh <= 255.0 && fmaf((float)qh, sc, mn) < hi[i][a]) qh += 1.0;
+                while (qh <= 255.0 && fmaf(256.0f + 0.25f * (float)qh, s4, org) < hi[i][a]) qh += 1.0;
                 if (qh > 255.0 || ql > 255.0) ok = false;
                 wl |= (uint32_t)ql << (8 * i);
                 wh |= (uint32_t)qh << (8 * i);
             }
             if (ok) {
-                ebytes |= (uint32_t)(e + 127) << (8 * a);
+                ebytes |= (uint32_t)(e + 129) << (8 * a);
                 qlo[a] = wl;
                 qhi[a] = wh;
                 break;

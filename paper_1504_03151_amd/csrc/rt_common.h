@@ -45,11 +45,12 @@ struct alignas(128) Node4 {
 static_assert(sizeof(Node4) == 128, "four-wide node must be 128 bytes");
 
 // Quantized four-wide node (RT_LAYOUT_BVH4Q): 64 bytes.  Child box planes are
-// 8-bit offsets from the node's origin p in units of a power of two per axis:
-// plane = fma(q, 2^e_axis, p_axis), which is exact in the product and rounds
-// once; the host chooses each q so that the decoded box contains the child's
+// 8-bit codes q on a grid of step 2^e per axis: plane = fma(256 + q / 4, s, p)
+// with the stored scale s = 4 * 2^e and origin p (the lowest child plane less
+// 1024 * 2^e, so that the code's value 256 + q / 4 is exact in FP16); the
+// builder chooses each q so that the decoded box contains the child's
 // (padded) box, so traversal stays exact and only visits a little more.
-//   origin = (p.x, p.y, p.z, bits: biased e_x | e_y << 8 | e_z << 16 | valid-child mask << 24)
+//   origin = (p.x, p.y, p.z, bits: biased exponents of s_x | s_y << 8 | s_z << 16 | valid-child mask << 24)
 //   qa = (lo.x, hi.x, lo.y, hi.y) with byte i = child i
 //   qb = (lo.z, hi.z, child 0, child 1)
 //   qc = (child 2, child 3, 0, 0)
@@ -376,15 +377,32 @@ HD void cswap(float& ka, int32_t& ca, float& kb, int32_t& cb) {
 // Four-wide traversal: the hit children of a node are ordered by entry
 // distance (five-comparator network, misses sorted last), the far ones pushed,
 // the nearest taken next; leaves are postponed as in the binary traversal.
-// Distance along the ray to the plane of byte i of a quantized plane word:
-// (q scale + corner - o) / d folded into one fma, q a + b with a = scale / d
-// and b = (corner - o) / d per axis.  The folded form differs from decoding
-// the plane first by a few FP32 roundings of quantities bounded by the
-// coordinate magnitude, far inside the builder's outward padding of 2^-19 of
-// the scene scale, so the test stays conservative.
+// Distance along the ray to the plane of byte q of a quantized plane word.
+// The node stores per axis a scale s = 4 * 2^e and an origin p such that the
+// plane is p + (256 + q / 4) s; the distance (p + (256 + q / 4) s - o) / d is
+// one fma, (256 + q / 4) a + b, with a = s / d and b = (p - o) / d per node
+// and axis.  The folded form differs from decoding the plane first by a few
+// FP32 roundings of quantities bounded by the coordinate magnitude (p lies
+// about four node extents below the node), far inside the builder's outward
+// padding of 2^-19 of the scene scale, so the test stays conservative.
+// 256 + q / 4 is exact in FP16 (the spacing in [256, 512) is 1/4): the device
+// widens two bytes at a time into FP16 halves with one byte permute and takes
+// the widening into a mixed-precision fma; the host evaluates the same fma on
+// the same operands in FP32.
 HD float qdist(uint32_t w, int i, float a, float b) {
-    return fmaf((float)((w >> (8 * i)) & 0xFFu), a, b);
+    return fmaf(256.0f + 0.25f * (float)((w >> (8 * i)) & 0xFFu), a, b);
 }
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef _Float16 mirt_half2 __attribute__((ext_vector_type(2)));
+// bytes 0 and 1 (k = 0) or 2 and 3 (k = 1) of w as the FP16 halves 256 + q / 4 (0x5C00 | q is
+// 256 + q / 4: exponent 8, q in the top eight of the ten mantissa bits)
+__device__ __forceinline__ uint32_t qhalves(uint32_t w, int k) {
+    return __builtin_amdgcn_perm(0x5C5C5C5Cu, w, k ? 0x04030402u : 0x04010400u);
+}
+__device__ __forceinline__ float qdist_h(uint32_t pr, int h, float a, float b) {
+    return fmaf((float)__builtin_bit_cast(mirt_half2, pr)[h], a, b);
+}
+#endif
 
 // Children of a quantized four-wide node: folded plane distances, then the
 // slab test.  Per axis the plane word nearer along the ray (the low planes
@@ -401,7 +419,6 @@ HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, 
     const float sx = as_float_i((int)((eb & 0xFFu) << 23));
     const float sy = as_float_i((int)(((eb >> 8) & 0xFFu) << 23));
     const float sz = as_float_i((int)(((eb >> 16) & 0xFFu) << 23));
-    const uint32_t valid = eb >> 24;
     const float ax = sx * r.inv.x, ay = sy * r.inv.y, az = sz * r.inv.z;
     const float bx = fmaf(o.x, r.inv.x, -r.oinv.x), by = fmaf(o.y, r.inv.y, -r.oinv.y),
                 bz = fmaf(o.z, r.inv.z, -r.oinv.z);
@@ -409,18 +426,27 @@ HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, 
     const uint32_t nx = px ? qa.x : qa.y, fx = px ? qa.y : qa.x;
     const uint32_t ny = py ? qa.z : qa.w, fy = py ? qa.w : qa.z;
     const uint32_t nz = pz ? qb.x : qb.y, fz = pz ? qb.y : qb.x;
+#if defined(__HIP_DEVICE_COMPILE__)
+    const uint32_t nx2[2] = {qhalves(nx, 0), qhalves(nx, 1)}, fx2[2] = {qhalves(fx, 0), qhalves(fx, 1)};
+    const uint32_t ny2[2] = {qhalves(ny, 0), qhalves(ny, 1)}, fy2[2] = {qhalves(fy, 0), qhalves(fy, 1)};
+    const uint32_t nz2[2] = {qhalves(nz, 0), qhalves(nz, 1)}, fz2[2] = {qhalves(fz, 0), qhalves(fz, 1)};
+#define MIRT_QD(w, i, a, b) qdist_h(w##2[(i) >> 1], (i) & 1, a, b)
+#else
+#define MIRT_QD(w, i, a, b) qdist(w, i, a, b)
+#endif
 #define MIRT_QCHILD(i, b, k)                                                                              \
     {                                                                                                     \
-        const float tn = max3f(qdist(nx, i, ax, bx), qdist(ny, i, ay, by), fmaxf(qdist(nz, i, az, bz), 0.0f)); \
-        const float tf = min3f(qdist(fx, i, ax, bx), qdist(fy, i, ay, by), fminf(qdist(fz, i, az, bz), tbest)); \
+        const float tn = max3f(MIRT_QD(nx, i, ax, bx), MIRT_QD(ny, i, ay, by), fmaxf(MIRT_QD(nz, i, az, bz), 0.0f)); \
+        const float tf = min3f(MIRT_QD(fx, i, ax, bx), MIRT_QD(fy, i, ay, by), fminf(MIRT_QD(fz, i, az, bz), tbest)); \
         k = tn;                                                                                           \
-        b = ((valid >> i) & 1u) != 0u && tn <= tf;                                                        \
+        b = tn <= tf;                                                                                     \
     }
     MIRT_QCHILD(0, b0, k0)
     MIRT_QCHILD(1, b1, k1)
     MIRT_QCHILD(2, b2, k2)
     MIRT_QCHILD(3, b3, k3)
 #undef MIRT_QCHILD
+#undef MIRT_QD
     ch = make_int4((int)qb.z, (int)qb.w, qc.x, qc.y);
 }
 
