@@ -105,7 +105,7 @@ typedef struct {
                              breadth-first inside) stored contiguously, blocks in depth-first order,
                              RT_LAYOUT_BVH4 the binary tree collapsed into 128-byte four-wide nodes
                              (depth-first), RT_LAYOUT_BVH4Q the same tree in 64-byte nodes whose child
-                             boxes are 8-bit offsets, rounded outward, from the node's corner;
+                             boxes are 8-bit codes on a power-of-two grid per axis, rounded outward;
                              RT_ERR_BVH_DEPTH if a four-wide traversal stack would exceed 96 */
 } rt_build_opts;
 
