@@ -472,10 +472,12 @@ HD bool trace_bvh4(const DevScene& s, const TRay& r, Hit& h, Stack& stk, Work& w
             int4 ch;
             if (QUANT) kids_q(s.nodes4q + node, r, h.t, b0, b1, b2, b3, k0, k1, k2, k3, ch);
             else kids_f(s.nodes4 + node, r, h.t, b0, b1, b2, b3, k0, k1, k2, k3, ch);
-            const int cnt = (int)b0 + (int)b1 + (int)b2 + (int)b3;
-            if (cnt == 0) {
+            if (!(b0 || b1 || b2 || b3)) {
                 node = stk.pop();
             } else {
+                // missed children sort last with key +inf; the entry distance of a box the ray
+                // reaches is finite (+inf means parallel to a slab and outside it), so after the
+                // sort "key < +inf" marks the children to visit
                 int32_t c0 = ch.x, c1 = ch.y, c2 = ch.z, c3 = ch.w;
                 k0 = b0 ? k0 : INFINITY;
                 k1 = b1 ? k1 : INFINITY;
@@ -486,9 +488,9 @@ HD bool trace_bvh4(const DevScene& s, const TRay& r, Hit& h, Stack& stk, Work& w
                 cswap(k0, c0, k2, c2);
                 cswap(k1, c1, k3, c3);
                 cswap(k1, c1, k2, c2);
-                if (cnt > 3) stk.push(c3);
-                if (cnt > 2) stk.push(c2);
-                if (cnt > 1) stk.push(c1);
+                if (k3 < INFINITY) stk.push(c3);
+                if (k2 < INFINITY) stk.push(c2);
+                if (k1 < INFINITY) stk.push(c1);
                 node = c0;
             }
             if (node < 0 && node != kStackDone && leaf == 0) {
