@@ -8,12 +8,12 @@
 namespace mirt {
 
 // Per axis: scale 2^e, the smallest power of two with 255 * 2^e >= the
-// node's extent; the node stores the scale s = 4 * 2^e (exponent byte e + 129)
-// and the origin p = the lowest child plane m minus 1024 * 2^e (rounded, then
-// lowered an ulp at a time until q = 0 decodes to at most m), so that byte q
-// decodes to the plane fma(256 + q / 4, s, p) = p + (1024 + q) 2^e: the value
-// 256 + q / 4 is exact in FP16, which the device traversal widens two bytes at
-// a time.  A lower plane takes the largest q whose decoded value is <= the
+// node's extent; the node stores the scale s = 4 * 2^e (as its exponent e + 2
+// in a signed byte) and the origin p = the lowest child plane m minus
+// 1024 * 2^e (rounded, then lowered an ulp at a time until q = 0 decodes to
+// at most m), so that byte q decodes to the plane fma(256 + q / 4, s, p) =
+// p + (1024 + q) 2^e: the value 256 + q / 4 is exact in FP16, which the
+// device traversal widens two bytes at a time.  A lower plane takes the largest q whose decoded value is <= the
 // true plane, an upper plane the smallest q whose decoded value is >= it
 // (checked with that same fma), so every decoded box contains its child's
 // padded box.  lo/hi: child boxes; valid: used slots; child: the four
@@ -69,7 +69,7 @@ HD bool quantize_children(const float (&lo)[4][3], const float (&hi)[4][3], cons
                 wh |= (uint32_t)qh << (8 * i);
             }
             if (ok) {
-                ebytes |= (uint32_t)(e + 129) << (8 * a);
+                ebytes |= (uint32_t)(uint8_t)(int8_t)(e + 2) << (8 * a);
                 qlo[a] = wl;
                 qhi[a] = wh;
                 break;

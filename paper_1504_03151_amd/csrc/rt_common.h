@@ -50,7 +50,7 @@ static_assert(sizeof(Node4) == 128, "four-wide node must be 128 bytes");
 // 1024 * 2^e, so that the code's value 256 + q / 4 is exact in FP16); the
 // builder chooses each q so that the decoded box contains the child's
 // (padded) box, so traversal stays exact and only visits a little more.
-//   origin = (p.x, p.y, p.z, bits: biased exponents of s_x | s_y << 8 | s_z << 16 | valid-child mask << 24)
+//   origin = (p.x, p.y, p.z, bits: exponents of s_x | s_y << 8 | s_z << 16 (signed bytes) | valid-child mask << 24)
 //   qa = (lo.x, hi.x, lo.y, hi.y) with byte i = child i
 //   qb = (lo.z, hi.z, child 0, child 1)
 //   qc = (child 2, child 3, 0, 0)
@@ -416,10 +416,9 @@ HD void kids_q(const Node4q* n, const TRay& r, float tbest, bool& b0, bool& b1, 
     const uint4 qa = n->qa, qb = n->qb;
     const int4 qc = n->qc;
     const uint32_t eb = (uint32_t)as_int_f(o.w);
-    const float sx = as_float_i((int)((eb & 0xFFu) << 23));
-    const float sy = as_float_i((int)(((eb >> 8) & 0xFFu) << 23));
-    const float sz = as_float_i((int)(((eb >> 16) & 0xFFu) << 23));
-    const float ax = sx * r.inv.x, ay = sy * r.inv.y, az = sz * r.inv.z;
+    // a = s / d = 2^n / d with the signed exponent bytes n (exact, like the product by 2^n)
+    const float ax = ldexpf(r.inv.x, (int)(int8_t)(eb & 0xFFu)), ay = ldexpf(r.inv.y, (int)(int8_t)((eb >> 8) & 0xFFu)),
+                az = ldexpf(r.inv.z, (int)(int8_t)((eb >> 16) & 0xFFu));
     const float bx = fmaf(o.x, r.inv.x, -r.oinv.x), by = fmaf(o.y, r.inv.y, -r.oinv.y),
                 bz = fmaf(o.z, r.inv.z, -r.oinv.z);
     const bool px = r.inv.x >= 0.0f, py = r.inv.y >= 0.0f, pz = r.inv.z >= 0.0f;
