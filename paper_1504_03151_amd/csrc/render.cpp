@@ -45,10 +45,12 @@ struct RayQ {
     float *ox, *oy, *oz, *dx, *dy, *dz, *wr, *wg, *wb;
     uint32_t *pix, *meta;   // meta: depth (bits 0-3) | sample (bits 4-19) | scene (bits 20-31)
 };
+// A shadow entry is three 16-byte records, so that a traversal lane reads its
+// segment with two loads and, if unblocked, its contribution with one.
 struct ShadowQ {
-    float *ox, *oy, *oz, *dx, *dy, *dz, *tmax, *cr, *cg, *cb;
-    uint32_t* pix;
-    uint32_t* sid;   // scene of each entry (batched frames only)
+    float4* a;       // origin (the light point), tmax
+    float4* b;       // unit direction, scene of the entry (bits; batched frames)
+    float4* c;       // contribution rgb, pixel (bits)
     uint32_t* key;   // bin of each entry (deferred shadows: light and origin cell), or NULL
 };
 struct HitQ {
@@ -481,17 +483,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             const uint32_t j = b + lane_id();
             if (j < end) {
                 const uint32_t i = perm ? perm[j] : begin + j;   // binned order of deferred shadow rays
-                const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? s.sid[i] : 0u);
-                const TRay r = make_tray(v3(s.ox[i], s.oy[i], s.oz[i]), v3(s.dx[i], s.dy[i], s.dz[i]));
-                const Hit h = traverse<true, COUNT, L>(S, r, s.tmax[i], stk, w);
+                const float4 ea = s.a[i], eb = s.b[i];
+                const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? (uint32_t)as_int_f(eb.w) : 0u);
+                const TRay r = make_tray(v3(ea.x, ea.y, ea.z), v3(eb.x, eb.y, eb.z));
+                const Hit h = traverse<true, COUNT, L>(S, r, ea.w, stk, w);
                 if (h.prim < 0) {
                     if (vis) {   // binned order visits pixels at random: mark the entry, add in queue order later
                         atomicOr(vis + (i >> 5), 1u << (i & 31u));
                     } else {
-                        const uint32_t p = s.pix[i];
-                        atomicAdd(acc + 3 * p + 0, s.cr[i]);
-                        atomicAdd(acc + 3 * p + 1, s.cg[i]);
-                        atomicAdd(acc + 3 * p + 2, s.cb[i]);
+                        const float4 ec = s.c[i];
+                        const uint32_t p = (uint32_t)as_int_f(ec.w);
+                        atomicAdd(acc + 3 * p + 0, ec.x);
+                        atomicAdd(acc + 3 * p + 1, ec.y);
+                        atomicAdd(acc + 3 * p + 2, ec.z);
                     }
                 }
             }
@@ -529,16 +533,17 @@ __global__ __launch_bounds__(256) void k_vis_resolve(ShadowQ s, const uint32_t* 
         __syncthreads();
         for (uint32_t i = b + threadIdx.x; i < min(b + kVisChunk, end); i += blockDim.x) {
             if (!((vis[i >> 5] >> (i & 31u)) & 1u)) continue;
-            const uint32_t p = s.pix[i];
+            const float4 ec = s.c[i];
+            const uint32_t p = (uint32_t)as_int_f(ec.w);
             uint32_t h = (p * 2654435761u) >> 21;   // 11 bits: a slot of the table
             for (;;) {   // at most 1024 keys in 2048 slots: a free or matching slot is always found
                 const uint32_t old = atomicCAS(&key[h], kDeadRay, p);
                 if (old == kDeadRay || old == p) break;
                 h = (h + 1u) & (kVisSlots - 1u);
             }
-            atomicAdd(&val[0][h], s.cr[i]);
-            atomicAdd(&val[1][h], s.cg[i]);
-            atomicAdd(&val[2][h], s.cb[i]);
+            atomicAdd(&val[0][h], ec.x);
+            atomicAdd(&val[1][h], ec.y);
+            atomicAdd(&val[2][h], ec.z);
         }
         __syncthreads();
         for (int k = threadIdx.x; k < kVisSlots; k += blockDim.x) {
@@ -756,18 +761,9 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
     V3 sd = xs - lp;
     const float dist = sqrtf(dot(sd, sd));
     sd = sd * (1.0f / dist);
-    sq.ox[slot] = lp.x;
-    sq.oy[slot] = lp.y;
-    sq.oz[slot] = lp.z;
-    sq.dx[slot] = sd.x;
-    sq.dy[slot] = sd.y;
-    sq.dz[slot] = sd.z;
-    sq.tmax[slot] = dist;
-    sq.cr[slot] = w.x * lt.cr;
-    sq.cg[slot] = w.y * lt.cg;
-    sq.cb[slot] = w.z * lt.cb;
-    sq.pix[slot] = pix;
-    if (sq.sid) sq.sid[slot] = sid;
+    sq.a[slot] = make_float4(lp.x, lp.y, lp.z, dist);
+    sq.b[slot] = make_float4(sd.x, sd.y, sd.z, as_float_i((int)sid));
+    sq.c[slot] = make_float4(w.x * lt.cr, w.y * lt.cg, w.z * lt.cb, as_float_i((int)pix));
     if (sq.key) {
         const int c = C.bin_c;
         const uint32_t cell = bin_axis(xs.x, C.bin_lo[0], C.bin_inv[0], c) +
@@ -1328,22 +1324,6 @@ __global__ void k_stats(const uint32_t* ctr, rt_stats* st, int max_depth, int pa
     if (part == 1) st->cache_queries += ctr[kCtrRec];
 }
 
-// rays [n][8] -> queue; and hit buffer -> (t, original id)
-__global__ void k_load_rays(const float* rays, int64_t n, RayQ q, ShadowQ s, int to_shadow) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float* R = rays + 8 * i;
-    float tmax = R[7];
-    if (!(tmax > 0.0f)) tmax = INFINITY;
-    if (to_shadow) {
-        s.ox[i] = R[0]; s.oy[i] = R[1]; s.oz[i] = R[2];
-        s.dx[i] = R[3]; s.dy[i] = R[4]; s.dz[i] = R[5];
-        s.tmax[i] = tmax;
-    } else {
-        q.ox[i] = R[0]; q.oy[i] = R[1]; q.oz[i] = R[2];
-        q.dx[i] = R[3]; q.dy[i] = R[4]; q.dz[i] = R[5];
-    }
-}
 
 // Surface coordinates of a closest hit (rt_intersect's uv output).  Triangle:
 // the barycentric weights of its second and third vertex, V/det and W/det of
@@ -1462,6 +1442,8 @@ struct Plan {
 constexpr uint32_t kMaxPersistentThreads = 1u << 20;
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
+// the shadow queue: three arrays of 16-byte records
+static size_t shadow_queue_bytes(uint32_t cap) { return 3 * a256(16 * (size_t)cap); }
 
 static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params& p, Plan& pl, std::string& why,
                       bool bin_space = true) {
@@ -1526,7 +1508,7 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     pl.off_hit = off;
     off = a256(off + 2 * 4 * (size_t)pl.qcap + 2 * 256);
     pl.off_s = off;
-    off = a256(off + 11 * 4 * (size_t)pl.scap + 11 * 256);
+    off = a256(off + shadow_queue_bytes(pl.scap));
     // plain frames bin their deferred shadow queue: a key and an order slot per entry
     pl.off_s2 = pl.off_s;
     if (bin_space) {
@@ -1553,15 +1535,10 @@ static RayQ ray_queue(uint8_t* base, uint32_t cap) {
     return q;
 }
 
-// 11 arrays (12 with the scene ids of a batched frame)
-static ShadowQ shadow_queue(uint8_t* base, uint32_t cap, bool with_sid) {
-    const size_t stride = a256(4 * (size_t)cap);
-    float* f[10];
-    for (int k = 0; k < 10; ++k) f[k] = reinterpret_cast<float*>(base + k * stride);
-    ShadowQ s{f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], f[9],
-              reinterpret_cast<uint32_t*>(base + 10 * stride),
-              with_sid ? reinterpret_cast<uint32_t*>(base + 11 * stride) : nullptr, nullptr};
-    return s;
+static ShadowQ shadow_queue(uint8_t* base, uint32_t cap) {
+    const size_t stride = a256(16 * (size_t)cap);
+    return ShadowQ{reinterpret_cast<float4*>(base), reinterpret_cast<float4*>(base + stride),
+                   reinterpret_cast<float4*>(base + 2 * stride), nullptr};
 }
 
 static HitQ hit_queue(uint8_t* base, uint32_t cap) {
@@ -1775,7 +1752,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
     float* acc = reinterpret_cast<float*>(A.ws + pl.off_acc);
     RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
     HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
-    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap, false);
+    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap);
     int32_t* overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack);
     const int gx = A.gx, shade_blocks = A.shade_blocks;
     unsigned long long* work = A.stats ? reinterpret_cast<unsigned long long*>(&A.stats->node_visits) : nullptr;
@@ -2035,7 +2012,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
     bp.off_hit = off;
     off = a256(off + 2 * a256(4 * (size_t)bp.qcap));
     bp.off_s = off;
-    off = a256(off + 12 * a256(4 * (size_t)bp.scap));
+    off = a256(off + shadow_queue_bytes(bp.scap));
     bp.off_stack = off;
     off = a256(off + 4 * (size_t)kMaxPersistentThreads * std::max(0, bp.stack_max - kSplitLds));
     bp.off_lpts = off;
@@ -2108,7 +2085,7 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
     float* acc = reinterpret_cast<float*>(B.ws + pl.off_acc);
     RayQ q[2] = {ray_queue(B.ws + pl.off_q[0], pl.qcap), ray_queue(B.ws + pl.off_q[1], pl.qcap)};
     HitQ hq = hit_queue(B.ws + pl.off_hit, pl.qcap);
-    ShadowQ sq = shadow_queue(B.ws + pl.off_s, pl.scap, true);
+    ShadowQ sq = shadow_queue(B.ws + pl.off_s, pl.scap);
     int32_t* overflow = reinterpret_cast<int32_t*>(B.ws + pl.off_stack);
     unsigned long long* work = B.stats ? reinterpret_cast<unsigned long long*>(&B.stats->node_visits) : nullptr;
     unsigned long long* swork = B.stats ? reinterpret_cast<unsigned long long*>(&B.stats->shadow_node_visits) : nullptr;
@@ -2322,7 +2299,7 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
     cp.off_thit = off;
     off = a256(off + 2 * a256(4 * (size_t)cp.tcap));
     cp.off_ts = off;
-    off = a256(off + 11 * a256(4 * (size_t)cp.tscap));
+    off = a256(off + shadow_queue_bytes(cp.tscap));
     cp.off_tbin = off;    // keys and order of the targets' deferred shadow queue
     off = a256(off + 2 * a256(4 * (size_t)cp.tscap));
     cp.off_tbins = off;   // its per-bin counts and first slots
@@ -2363,7 +2340,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     float* acc = reinterpret_cast<float*>(A.ws + pl.off_acc);
     RayQ q[2] = {ray_queue(A.ws + pl.off_q[0], pl.qcap), ray_queue(A.ws + pl.off_q[1], pl.qcap)};
     HitQ hq = hit_queue(A.ws + pl.off_hit, pl.qcap);
-    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap, false);
+    ShadowQ sq = shadow_queue(A.ws + pl.off_s, pl.scap);
     int32_t* overflow = reinterpret_cast<int32_t*>(A.ws + pl.off_stack);
     const CacheRec rec = cache_records(A.ws + cp.off_rec, cp.rec_cap);
     uint8_t* S = C.state;
@@ -2479,7 +2456,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
         uint32_t* tctr = reinterpret_cast<uint32_t*>(A.ws + cp.off_tctr);
         RayQ tq[2] = {ray_queue(A.ws + cp.off_tq[0], cp.tcap), ray_queue(A.ws + cp.off_tq[1], cp.tcap)};
         HitQ th = hit_queue(A.ws + cp.off_thit, cp.tcap);
-        ShadowQ ts = shadow_queue(A.ws + cp.off_ts, cp.tscap, false);
+        ShadowQ ts = shadow_queue(A.ws + cp.off_ts, cp.tscap);
         ts.key = reinterpret_cast<uint32_t*>(A.ws + cp.off_tbin);
         float* targets = reinterpret_cast<float*>(S + L.train_targets);
         uint16_t* t_feats = reinterpret_cast<uint16_t*>(S + L.train_feats);
