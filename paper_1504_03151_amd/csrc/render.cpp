@@ -41,9 +41,12 @@ namespace mirt {
 // ---------------------------------------------------------------------------
 // queues
 // ---------------------------------------------------------------------------
+// A queued ray is three 16-byte records: a traversal lane reads its ray with
+// two loads.  meta: depth (bits 0-3) | sample (bits 4-19) | scene (bits 20-31).
 struct RayQ {
-    float *ox, *oy, *oz, *dx, *dy, *dz, *wr, *wg, *wb;
-    uint32_t *pix, *meta;   // meta: depth (bits 0-3) | sample (bits 4-19) | scene (bits 20-31)
+    float4* a;   // origin, pixel (bits; kDeadRay for an empty slot)
+    float4* b;   // unit direction, meta (bits)
+    float4* c;   // path weight rgb, unused
 };
 // A shadow entry is three 16-byte records, so that a traversal lane reads its
 // segment with two loads and, if unblocked, its contribution with one.
@@ -302,7 +305,7 @@ __device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int
     const int px = ((int)(tile - ty * (uint32_t)tiles_x) << lw) + (int)(lane & ((1u << lw) - 1u));
     const int py = ((int)ty << (6 - lw)) + (int)(lane >> lw);
     if (px >= cam.W || py >= cam.H) {
-        q.pix[slot] = kDeadRay;
+        q.a[slot].w = as_float_i((int)kDeadRay);
         return false;
     }
     const uint32_t pixel = (uint32_t)py * cam.W + px;
@@ -323,17 +326,11 @@ __device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int
     double d[3];
     for (int i = 0; i < 3; ++i) d[i] = cam.f[i] + X * cam.r[i] + Y * cam.u[i];
     const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-    q.ox[slot] = (float)cam.eye[0];
-    q.oy[slot] = (float)cam.eye[1];
-    q.oz[slot] = (float)cam.eye[2];
-    q.dx[slot] = (float)(d[0] * inv);
-    q.dy[slot] = (float)(d[1] * inv);
-    q.dz[slot] = (float)(d[2] * inv);
-    q.wr[slot] = 1.0f;
-    q.wg[slot] = 1.0f;
-    q.wb[slot] = 1.0f;
-    q.pix[slot] = acc_off + (per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel);
-    q.meta[slot] = meta_hi | ((uint32_t)s << 4);
+    const uint32_t pix = acc_off + (per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel);
+    q.a[slot] = make_float4((float)cam.eye[0], (float)cam.eye[1], (float)cam.eye[2], as_float_i((int)pix));
+    q.b[slot] = make_float4((float)(d[0] * inv), (float)(d[1] * inv), (float)(d[2] * inv),
+                            as_float_i((int)(meta_hi | ((uint32_t)s << 4))));
+    q.c[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
     return true;
 }
 
@@ -423,12 +420,14 @@ __device__ __forceinline__ void extend_queue(const DevScene& sc, const BatchScen
         for (uint32_t b = base; b < end; b += 64) {
             const uint32_t i = b + lane_id();
             if (i < end) {
-                if (q.pix[i] == kDeadRay) {
+                const float4 ra = q.a[i];
+                if ((uint32_t)as_int_f(ra.w) == kDeadRay) {
                     hit.prim[i] = -1;
                     continue;
                 }
-                const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? (q.meta[i] >> 20) : 0u);
-                const TRay r = make_tray(v3(q.ox[i], q.oy[i], q.oz[i]), v3(q.dx[i], q.dy[i], q.dz[i]));
+                const float4 rb = q.b[i];
+                const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? ((uint32_t)as_int_f(rb.w) >> 20) : 0u);
+                const TRay r = make_tray(v3(ra.x, ra.y, ra.z), v3(rb.x, rb.y, rb.z));
                 const Hit h = traverse<false, COUNT, L>(S, r, INFINITY, stk, w);
                 hit.t[i] = h.t;
                 hit.prim[i] = h.prim;
@@ -798,17 +797,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
         uint32_t pix = 0, meta = 0;
         V3 o = v3(0, 0, 0), d = v3(0, 0, 1), w = v3(0, 0, 0);
         float t = 0.0f;
+        float4 ra = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (active) {
-            pix = qin.pix[i];
+            ra = qin.a[i];
+            pix = (uint32_t)as_int_f(ra.w);
             active = pix != kDeadRay;
         }
         if (active) {
             prim = hit.prim[i];
             t = hit.t[i];
-            meta = qin.meta[i];
-            o = v3(qin.ox[i], qin.oy[i], qin.oz[i]);
-            d = v3(qin.dx[i], qin.dy[i], qin.dz[i]);
-            w = v3(qin.wr[i], qin.wg[i], qin.wb[i]);
+            const float4 rb = qin.b[i], rc = qin.c[i];
+            meta = (uint32_t)as_int_f(rb.w);
+            o = v3(ra.x, ra.y, ra.z);
+            d = v3(rb.x, rb.y, rb.z);
+            w = v3(rc.x, rc.y, rc.z);
         }
         const uint32_t sid = BATCH ? (meta >> 20) : 0u;
         const DevScene& S = scene_of<BATCH>(sc, tab, sid);
@@ -1021,17 +1023,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
         const uint32_t meta_next = (meta & ~15u) | (uint32_t)(depth + 1);
         if (want_r) {
             if (qslot < qcap) {
-                qout.ox[qslot] = xs.x;
-                qout.oy[qslot] = xs.y;
-                qout.oz[qslot] = xs.z;
-                qout.dx[qslot] = dr.x;
-                qout.dy[qslot] = dr.y;
-                qout.dz[qslot] = dr.z;
-                qout.wr[qslot] = w.x * fr.x;
-                qout.wg[qslot] = w.y * fr.y;
-                qout.wb[qslot] = w.z * fr.z;
-                qout.pix[qslot] = pix;
-                qout.meta[qslot] = meta_next;
+                qout.a[qslot] = make_float4(xs.x, xs.y, xs.z, as_float_i((int)pix));
+                qout.b[qslot] = make_float4(dr.x, dr.y, dr.z, as_float_i((int)meta_next));
+                qout.c[qslot] = make_float4(w.x * fr.x, w.y * fr.y, w.z * fr.z, 0.0f);
             } else {
                 atomicOr(ctr + kCtrStatus, 1u);
             }
@@ -1040,17 +1034,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
         if (want_t) {
             if (qslot < qcap) {
                 const V3 xt = x - eps_s * nf;
-                qout.ox[qslot] = xt.x;
-                qout.oy[qslot] = xt.y;
-                qout.oz[qslot] = xt.z;
-                qout.dx[qslot] = dt.x;
-                qout.dy[qslot] = dt.y;
-                qout.dz[qslot] = dt.z;
-                qout.wr[qslot] = w.x * ft.x;
-                qout.wg[qslot] = w.y * ft.y;
-                qout.wb[qslot] = w.z * ft.z;
-                qout.pix[qslot] = pix;
-                qout.meta[qslot] = meta_next;
+                qout.a[qslot] = make_float4(xt.x, xt.y, xt.z, as_float_i((int)pix));
+                qout.b[qslot] = make_float4(dt.x, dt.y, dt.z, as_float_i((int)meta_next));
+                qout.c[qslot] = make_float4(w.x * ft.x, w.y * ft.y, w.z * ft.z, 0.0f);
             } else {
                 atomicOr(ctr + kCtrStatus, 1u);
             }
@@ -1144,15 +1130,19 @@ __global__ __launch_bounds__(256) void k_cache_shade(DevScene sc, ShadeConst c, 
         bool active = i < count;
         uint32_t pix = 0, meta = 0;
         int prim = -1;
+        float4 ra = make_float4(0.0f, 0.0f, 0.0f, 0.0f), rb = ra;
         if (active) {
-            pix = qin.pix[i];
+            ra = qin.a[i];
+            pix = (uint32_t)as_int_f(ra.w);
             active = pix != kDeadRay;
         }
         V3 w = v3(0, 0, 0);
         if (active) {
             prim = hit.prim[i];
-            meta = qin.meta[i];
-            w = v3(qin.wr[i], qin.wg[i], qin.wb[i]);
+            rb = qin.b[i];
+            meta = (uint32_t)as_int_f(rb.w);
+            const float4 rc = qin.c[i];
+            w = v3(rc.x, rc.y, rc.z);
             if (depth == 0 && c.out_ids) {
                 int oid = -1;
                 if (prim >= sc.n_bvh) oid = prim;
@@ -1174,8 +1164,8 @@ __global__ __launch_bounds__(256) void k_cache_shade(DevScene sc, ShadeConst c, 
                 atomicOr(ctr + kCtrStatus, 4u);
                 continue;
             }
-            const V3 o = v3(qin.ox[i], qin.oy[i], qin.oz[i]);
-            const V3 d = v3(qin.dx[i], qin.dy[i], qin.dz[i]);
+            const V3 o = v3(ra.x, ra.y, ra.z);
+            const V3 d = v3(rb.x, rb.y, rb.z);
             const float t = hit.t[i];
             const V3 x = v3(fmaf(t, d.x, o.x), fmaf(t, d.y, o.y), fmaf(t, d.z, o.z));
             V3 ng;
@@ -1221,26 +1211,19 @@ __global__ void k_cache_select(const uint32_t* ctr, CacheRec rec, RayQ qsrc, uin
     uint32_t src = (uint32_t)(((double)j + u) * (double)queries / (double)n_train);
     src = min(src, queries - 1u);
     const uint32_t i = rec.src[src];
-    qt.ox[j] = qsrc.ox[i];
-    qt.oy[j] = qsrc.oy[i];
-    qt.oz[j] = qsrc.oz[i];
-    qt.dx[j] = qsrc.dx[i];
-    qt.dy[j] = qsrc.dy[i];
-    qt.dz[j] = qsrc.dz[i];
-    qt.wr[j] = 1.0f;
-    qt.wg[j] = 1.0f;
-    qt.wb[j] = 1.0f;
-    qt.pix[j] = j;
-    qt.meta[j] = (uint32_t)depth;
+    const float4 sa = qsrc.a[i], sb = qsrc.b[i];
+    qt.a[j] = make_float4(sa.x, sa.y, sa.z, as_float_i((int)j));
+    qt.b[j] = make_float4(sb.x, sb.y, sb.z, as_float_i(depth));
+    qt.c[j] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
     const uint4* fs = reinterpret_cast<const uint4*>(rec.feats + (size_t)src * 64);
     uint4* fd = reinterpret_cast<uint4*>(t_feats + (size_t)j * 64);
     for (int q = 0; q < 8; ++q) fd[q] = fs[q];
-    t_rays[6 * j + 0] = qsrc.ox[i];
-    t_rays[6 * j + 1] = qsrc.oy[i];
-    t_rays[6 * j + 2] = qsrc.oz[i];
-    t_rays[6 * j + 3] = qsrc.dx[i];
-    t_rays[6 * j + 4] = qsrc.dy[i];
-    t_rays[6 * j + 5] = qsrc.dz[i];
+    t_rays[6 * j + 0] = sa.x;
+    t_rays[6 * j + 1] = sa.y;
+    t_rays[6 * j + 2] = sa.z;
+    t_rays[6 * j + 3] = sb.x;
+    t_rays[6 * j + 4] = sb.y;
+    t_rays[6 * j + 5] = sb.z;
     t_pix[j] = rec.pix[src];
 }
 
@@ -1442,8 +1425,9 @@ struct Plan {
 constexpr uint32_t kMaxPersistentThreads = 1u << 20;
 
 static size_t a256(size_t x) { return (x + 255) & ~(size_t)255; }
-// the shadow queue: three arrays of 16-byte records
+// the ray and shadow queues: three arrays of 16-byte records
 static size_t shadow_queue_bytes(uint32_t cap) { return 3 * a256(16 * (size_t)cap); }
+static size_t ray_queue_bytes(uint32_t cap) { return 3 * a256(16 * (size_t)cap); }
 
 static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params& p, Plan& pl, std::string& why,
                       bool bin_space = true) {
@@ -1503,7 +1487,7 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
     off = a256(off + 12 * (size_t)pl.nacc);
     for (int b = 0; b < 2; ++b) {
         pl.off_q[b] = off;
-        off = a256(off + 11 * 4 * (size_t)pl.qcap + 11 * 256);
+        off = a256(off + ray_queue_bytes(pl.qcap));
     }
     pl.off_hit = off;
     off = a256(off + 2 * 4 * (size_t)pl.qcap + 2 * 256);
@@ -1527,12 +1511,9 @@ static bool make_plan(const SceneHost& s, const rt_camera& cam, const rt_params&
 }
 
 static RayQ ray_queue(uint8_t* base, uint32_t cap) {
-    const size_t stride = a256(4 * (size_t)cap);
-    float* f[9];
-    for (int k = 0; k < 9; ++k) f[k] = reinterpret_cast<float*>(base + k * stride);
-    RayQ q{f[0], f[1], f[2], f[3], f[4], f[5], f[6], f[7], f[8], reinterpret_cast<uint32_t*>(base + 9 * stride),
-           reinterpret_cast<uint32_t*>(base + 10 * stride)};
-    return q;
+    const size_t stride = a256(16 * (size_t)cap);
+    return RayQ{reinterpret_cast<float4*>(base), reinterpret_cast<float4*>(base + stride),
+                reinterpret_cast<float4*>(base + 2 * stride)};
 }
 
 static ShadowQ shadow_queue(uint8_t* base, uint32_t cap) {
@@ -2007,7 +1988,7 @@ static bool make_batch_plan(const rt_scene* const* scenes, const rt_camera* cams
     off = a256(off + 12 * (size_t)acc);
     for (int b = 0; b < 2; ++b) {
         bp.off_q[b] = off;
-        off = a256(off + 11 * (a256(4 * (size_t)bp.qcap)));
+        off = a256(off + ray_queue_bytes(bp.qcap));
     }
     bp.off_hit = off;
     off = a256(off + 2 * a256(4 * (size_t)bp.qcap));
@@ -2294,7 +2275,7 @@ static bool make_cache_plan(const SceneHost& h, const rt_camera& cam, const rt_p
     off = a256(off + (size_t)cp.rec_cap * (128 + 4 + 12 + 4) + 4 * 256);
     for (int b = 0; b < 2; ++b) {
         cp.off_tq[b] = off;
-        off = a256(off + 11 * a256(4 * (size_t)cp.tcap));
+        off = a256(off + ray_queue_bytes(cp.tcap));
     }
     cp.off_thit = off;
     off = a256(off + 2 * a256(4 * (size_t)cp.tcap));
