@@ -662,6 +662,36 @@ __device__ __forceinline__ uint32_t block_reserve(uint32_t wave_total, uint32_t*
     return r;
 }
 
+// Two reservations in one block-wide pass (the shadow rays and the next
+// depth's rays of a shading block).  lds8: 8 words.  All threads must call.
+__device__ __forceinline__ void block_reserve2(uint32_t tot_a, uint32_t* tail_a, uint32_t* also_a, uint32_t tot_b,
+                                               uint32_t* tail_b, uint32_t* lds8, uint32_t& base_a,
+                                               uint32_t& base_b) {
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        lds8[wave] = tot_a;
+        lds8[4 + wave] = tot_b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 2; ++k) {
+            uint32_t* v = lds8 + 4 * k;
+            const uint32_t t0 = v[0], t1 = v[1], t2 = v[2], t3 = v[3];
+            const uint32_t tot = t0 + t1 + t2 + t3;
+            const uint32_t base = tot ? atomicAdd(k ? tail_b : tail_a, tot) : 0u;
+            if (tot && !k && also_a) atomicAdd(also_a, tot);   // a second count (per-depth statistics)
+            v[0] = base;
+            v[1] = base + t0;
+            v[2] = base + t0 + t1;
+            v[3] = base + t0 + t1 + t2;
+        }
+    }
+    __syncthreads();
+    base_a = lds8[wave];
+    base_b = lds8[4 + wave];
+    __syncthreads();
+}
+
 struct LightTerm {
     float cr, cg, cb;
     bool emit;
@@ -782,7 +812,7 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
 template <bool BATCH, bool GI>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_shade(DevScene sc, ShadeConst c0, const BatchScene* tab, RayQ qin, HitQ hit,
                                                uint32_t* ctr, int depth, RayQ qout, ShadowQ sq, float* acc) {
-    __shared__ uint32_t lds_res[4];
+    __shared__ uint32_t lds_res[8];
     __shared__ float lds_add[3][256];   // depth 0: the block's background / ambient terms ...
     __shared__ uint32_t lds_pix[256];   // ... and their pixels
     const uint32_t qcap = c0.qcap, scap = c0.scap;
@@ -865,26 +895,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
             has_add = true;
         }
         if (sum0) {
-            // ray generation order: lane l of the block's four waves is one pixel in four samples, so wave 0
-            // adds their sum once (checked: different pixels are added one by one)
+            // ray generation order: lane l of the block's four waves is one pixel in four samples, so their
+            // sum is added once, each of three waves adding one channel (checked: different pixels are added
+            // one by one)
             lds_pix[threadIdx.x] = has_add ? pix : kDeadRay;
             lds_add[0][threadIdx.x] = add.x;
             lds_add[1][threadIdx.x] = add.y;
             lds_add[2][threadIdx.x] = add.z;
             __syncthreads();
-            if (threadIdx.x < 64) {
-                const uint32_t l = threadIdx.x, q0 = lds_pix[l];
+            if (threadIdx.x < 192) {   // wave c adds channel c
+                const uint32_t c = threadIdx.x >> 6, l = threadIdx.x & 63u, q0 = lds_pix[l];
                 const bool same = q0 != kDeadRay && lds_pix[64 + l] == q0 && lds_pix[128 + l] == q0 &&
                                   lds_pix[192 + l] == q0;
                 if (same) {
-                    for (int c = 0; c < 3; ++c)
-                        atomicAdd(acc + 3 * q0 + c,
-                                  (lds_add[c][l] + lds_add[c][64 + l]) + (lds_add[c][128 + l] + lds_add[c][192 + l]));
+                    atomicAdd(acc + 3 * q0 + c,
+                              (lds_add[c][l] + lds_add[c][64 + l]) + (lds_add[c][128 + l] + lds_add[c][192 + l]));
                 } else {
                     for (int k = 0; k < 4; ++k) {
                         const uint32_t q = lds_pix[64 * k + l];
                         if (q == kDeadRay) continue;
-                        for (int c = 0; c < 3; ++c) atomicAdd(acc + 3 * q + c, lds_add[c][64 * k + l]);
+                        atomicAdd(acc + 3 * q + c, lds_add[c][64 * k + l]);
                     }
                 }
             }
@@ -893,6 +923,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
             atomicAdd(acc + 3 * pix + 1, add.y);
             atomicAdd(acc + 3 * pix + 2, add.z);
         }
+        // a block whose rays all missed spawns nothing: skip the reservations and their barriers
+        if (!__syncthreads_or(shade ? 1 : 0)) continue;
         // ---- shadow rays: decide per light, reserve, then write
         uint32_t emit_mask = 0, n_sh = 0;
         if (shade) {
@@ -903,36 +935,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                     n_sh++;
                     if (l < 32) emit_mask |= 1u << l;
                 }
-            }
-        }
-        uint32_t wave_tot;
-        const uint32_t lane_off = wave_scan(n_sh, wave_tot);
-        // deferred: one queue for the shadow rays of every depth, traced once at the end of the pass
-        const uint32_t wave_base =
-            C.defer_shadow ? block_reserve(wave_tot, ctr + kCtrShadowAll, lds_res, ctr + kCtrShadow + depth)
-                           : block_reserve(wave_tot, ctr + kCtrShadow + depth, lds_res);
-        if (light_major) {
-            // light-major: for each light, the wave's emitting lanes take consecutive slots
-            uint32_t run = wave_base;
-            for (int l = 0; l < S.n_lights; ++l) {   // wave-uniform loop
-                const bool e = (emit_mask >> l) & 1u;
-                const uint64_t bal = __ballot(e);
-                if (e) {
-                    const uint32_t slot = run + __builtin_amdgcn_mbcnt_hi(
-                                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-                    const V3 lp = light_at(S, C, smp, l);
-                    const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
-                    write_shadow(sq, slot, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
-                }
-                run += (uint32_t)__popcll(bal);
-            }
-        } else if (n_sh) {
-            uint32_t slot = wave_base + lane_off;   // lane-major (more than 32 lights)
-            for (int l = 0; l < S.n_lights; ++l) {
-                const V3 lp = light_at(S, C, smp, l);
-                const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
-                if (!lt.emit) continue;
-                write_shadow(sq, slot++, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
             }
         }
         // ---- secondary rays
@@ -1016,10 +1018,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                 fr = v3(g * alb.x, g * alb.y, g * alb.z);
             }
         }
+        // ---- one block-wide reservation for both: shadow rays (deferred: one queue for the shadow rays of
+        // every depth, traced once at the end of the pass) and the next depth's rays
         const uint32_t nsec = (want_r ? 1u : 0u) + (want_t ? 1u : 0u);
-        uint32_t sec_tot;
+        uint32_t wave_tot, sec_tot;
+        const uint32_t lane_off = wave_scan(n_sh, wave_tot);
         const uint32_t sec_off = wave_scan(nsec, sec_tot);
-        uint32_t qslot = block_reserve(sec_tot, ctr + kCtrRays + depth + 1, lds_res) + sec_off;
+        uint32_t wave_base, sec_base;
+        block_reserve2(wave_tot, C.defer_shadow ? ctr + kCtrShadowAll : ctr + kCtrShadow + depth,
+                       C.defer_shadow ? ctr + kCtrShadow + depth : nullptr, sec_tot, ctr + kCtrRays + depth + 1,
+                       lds_res, wave_base, sec_base);
+        if (light_major) {
+            // light-major: for each light, the wave's emitting lanes take consecutive slots
+            uint32_t run = wave_base;
+            for (int l = 0; l < S.n_lights; ++l) {   // wave-uniform loop
+                const bool e = (emit_mask >> l) & 1u;
+                const uint64_t bal = __ballot(e);
+                if (e) {
+                    const uint32_t slot = run + __builtin_amdgcn_mbcnt_hi(
+                                                    (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                    const V3 lp = light_at(S, C, smp, l);
+                    const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
+                    write_shadow(sq, slot, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
+                }
+                run += (uint32_t)__popcll(bal);
+            }
+        } else if (n_sh) {
+            uint32_t slot = wave_base + lane_off;   // lane-major (more than 32 lights)
+            for (int l = 0; l < S.n_lights; ++l) {
+                const V3 lp = light_at(S, C, smp, l);
+                const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
+                if (!lt.emit) continue;
+                write_shadow(sq, slot++, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
+            }
+        }
+        uint32_t qslot = sec_base + sec_off;
         const uint32_t meta_next = (meta & ~15u) | (uint32_t)(depth + 1);
         if (want_r) {
             if (qslot < qcap) {
