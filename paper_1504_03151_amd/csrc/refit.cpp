@@ -82,7 +82,7 @@ __global__ void k_refit_prims(float4* prims, float4* normals, int64_t nb, int32_
     const double l = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
     if (l > 0)
         for (double& x : n) x /= l;
-    normals[i] = make_float4((float)n[0], (float)n[1], (float)n[2], 0.0f);
+    normals[i] = make_float4((float)n[0], (float)n[1], (float)n[2], p1.w);   // w: the material, as built
 }
 
 struct RBox {

@@ -437,8 +437,9 @@ __device__ __forceinline__ void extend_queue(const DevScene& sc, const BatchScen
     flush_work<COUNT>(w, work_out);
 }
 
-// Seven waves per SIMD: 71 registers instead of 80 (six waves), no spills in
-// the single-scene form.  L: the node layout compiled in (-1: read from the
+// Seven waves per SIMD (at most 72 registers; the single-scene form needs 68,
+// no spills; eight waves measured slower for the batched form, which shares
+// this kernel).  L: the node layout compiled in (-1: read from the
 // scene, as batched frames, whose scenes may differ, and counting frames do);
 // a kernel built for one layout spends no registers on the others' code.
 template <bool COUNT, bool BATCH, int L = -1>
@@ -449,8 +450,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7, 7))) voi
 }
 
 // The same for the bounces after the first: their queues are small and incoherent, so a launch is bound by
-// the latency of each ray's chain of node fetches; eight waves per SIMD (a few spilled registers) hide more
-// of it than the six the register count otherwise allows.
+// the latency of each ray's chain of node fetches; eight waves per SIMD (at most 64 registers) hide more of
+// it than fewer waves with more registers.
 template <int L>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_extend_deep(
     DevScene sc, RayQ q, HitQ hit, const uint32_t* count_p, uint32_t* cursor, uint32_t cap, uint32_t chunk,
@@ -459,9 +460,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 }
 
 // Any-hit over the shadow queue; adds the contribution of each unblocked light
-// to its pixel.  Eight waves per SIMD (a few spilled registers): more rays in
-// flight hide more of the node-fetch latency than the six the register count
-// otherwise allows.
+// to its pixel.  Eight waves per SIMD (at most 64 registers): more rays in
+// flight hide more of the node-fetch latency than fewer waves with more
+// registers.
 template <bool COUNT, bool BATCH, int L = -1>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_shadow(DevScene sc, const BatchScene* tab, ShadowQ s,
                                                 const uint32_t* count_p, uint32_t* cursor, uint32_t cap,
@@ -870,14 +871,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                 ng = xyz(pl);
                 mat = S.plane_mat[prim - S.n_bvh];
             } else {
-                const float4 p0 = S.prims[3 * prim];
-                const float4 p1 = S.prims[3 * prim + 1];
-                mat = as_int_f(p1.w);
-                if (as_int_f(p0.w) < S.n_spheres) {
+                // a triangle's normal record carries its material: one read; a sphere's holds ~material
+                const float4 nr = S.normals[prim];
+                const int code = as_int_f(nr.w);
+                if (code >= 0) {
+                    ng = xyz(nr);
+                    mat = code;
+                } else {
+                    const float4 p0 = S.prims[3 * prim];
+                    const float4 p1 = S.prims[3 * prim + 1];
+                    mat = ~code;
                     ng = (x - xyz(p0)) * p1.z;
                     ng = ng * (1.0f / sqrtf(dot(ng, ng)));
-                } else {
-                    ng = xyz(S.normals[prim]);
                 }
             }
         }
@@ -1205,12 +1210,13 @@ __global__ __launch_bounds__(256) void k_cache_shade(DevScene sc, ShadeConst c, 
             if (prim >= sc.n_bvh) {
                 ng = xyz(sc.planes[prim - sc.n_bvh]);
             } else {
-                const float4 p0 = sc.prims[3 * prim];
-                if (as_int_f(p0.w) < sc.n_spheres) {
+                const float4 nr = sc.normals[prim];
+                if (as_int_f(nr.w) >= 0) {   // a triangle (a sphere's record holds ~material)
+                    ng = xyz(nr);
+                } else {
+                    const float4 p0 = sc.prims[3 * prim];
                     ng = (x - xyz(p0)) * sc.prims[3 * prim + 1].z;
                     ng = ng * (1.0f / sqrtf(dot(ng, ng)));
-                } else {
-                    ng = xyz(sc.normals[prim]);
                 }
             }
             const V3 nf = dot(d, ng) < 0.0f ? ng : -ng;

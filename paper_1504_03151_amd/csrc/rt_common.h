@@ -95,7 +95,8 @@ struct DevScene {
     const Node4q* nodes4q;    // the same section, when wide == 2
     int wide;                 // 0 binary nodes; 1 four-wide (RT_LAYOUT_BVH4); 2 quantized four-wide (RT_LAYOUT_BVH4Q)
     const float4* prims;      // [n_bvh * 3]
-    const float4* normals;    // [n_bvh]  unit geometric normal of triangles (FP64 on host, rounded)
+    const float4* normals;    // [n_bvh]  triangle: unit geometric normal (FP64 on host, rounded), material (bits);
+                              //          sphere: 0, 0, 0, ~material (bits)
     const float4* planes;     // [n_planes] (n, h): n.x = h
     const int* plane_mat;     // [n_planes]
     const DevMaterial* mats;

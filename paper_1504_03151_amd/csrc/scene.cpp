@@ -635,7 +635,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
                 prims[3 * i] = make_float4(s[0], s[1], s[2], as_float_i(p));
                 prims[3 * i + 1] = make_float4(s[3], s[3] * s[3], 1.0f / s[3], as_float_i(desc->sphere_mat[p]));
                 prims[3 * i + 2] = make_float4(0, 0, 0, 0);
-                normals[i] = make_float4(0, 0, 0, 0);
+                normals[i] = make_float4(0, 0, 0, as_float_i(~desc->sphere_mat[p]));   // ~material: a sphere
             } else {
                 const int64_t j = p - ns;
                 const float* t = desc->tris + 9 * j;
@@ -650,7 +650,7 @@ rt_status rt_build_scene(const rt_scene_desc* desc, const rt_build_opts* opts, r
                 const double l = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
                 if (l > 0)
                     for (double& x : n) x /= l;
-                normals[i] = make_float4((float)n[0], (float)n[1], (float)n[2], 0.0f);
+                normals[i] = make_float4((float)n[0], (float)n[1], (float)n[2], as_float_i(desc->tri_mat[j]));
             }
         }
         float4* planes = reinterpret_cast<float4*>(base + h.off_planes);
