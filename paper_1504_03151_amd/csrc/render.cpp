@@ -294,8 +294,37 @@ constexpr uint32_t kDeadRay = 0xFFFFFFFFu;
 // Primary ray for slot `slot` = local thread index `g` of a pass over one
 // scene (64-pixel tiles, samples s0 .. s0 + ns - 1).  Returns false for a dead
 // padding slot.
-__device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int s0, int ns, int tiles_x, uint32_t g,
-                                        int per_sample, uint32_t acc_off, uint32_t meta_hi, RayQ q, uint32_t slot) {
+// The root node's child boxes against a ray, in the traversal's own arithmetic (closest hit, no bound on t):
+// false when no child box is reached, so that the traversal, starting there, would find nothing (BVH
+// primitives only; the caller rules out planes).
+template <int L>
+__device__ __forceinline__ bool root_reached(const DevScene& s, const TRay& r) {
+    if (L == 0) {
+        const Node* n = s.nodes;
+        bool hl, hr;
+        float tl, tr;
+        box2(r, n->a, n->b, n->c, INFINITY, hl, hr, tl, tr);
+        return hl || hr;
+    }
+    bool b0, b1, b2, b3;
+    float k0, k1, k2, k3;
+    int4 ch;
+    if (L == 2) kids_q(s.nodes4q, r, INFINITY, b0, b1, b2, b3, k0, k1, k2, k3, ch);
+    else kids_f(s.nodes4, r, INFINITY, b0, b1, b2, b3, k0, k1, k2, k3, ch);
+    return b0 || b1 || b2 || b3;
+}
+
+// What ray generation did with a slot.
+enum GenKind { kGenDead = 0, kGenQueued = 1, kGenMissed = 2 };
+
+// L >= 0 (scenes without planes): a camera ray that misses every child box of
+// the root can hit nothing; it is not queued (its slot is marked like a dead
+// one, which the later stages skip) and the caller adds its background term.
+template <int L = -1>
+__device__ __forceinline__ GenKind gen_ray(const CamConst& cam, uint32_t frame, int s0, int ns, int tiles_x, uint32_t g,
+                                           int per_sample, uint32_t acc_off, uint32_t meta_hi, RayQ q, uint32_t slot,
+                                           const DevScene* sc = nullptr, uint32_t* pix_out = nullptr,
+                                           uint32_t* sample_out = nullptr) {
     const uint32_t lane = g & 63u;
     const uint32_t tile_sample = g >> 6;
     const uint32_t tile = tile_sample / (uint32_t)ns;
@@ -306,7 +335,7 @@ __device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int
     const int py = ((int)ty << (6 - lw)) + (int)(lane >> lw);
     if (px >= cam.W || py >= cam.H) {
         q.a[slot].w = as_float_i((int)kDeadRay);
-        return false;
+        return kGenDead;
     }
     const uint32_t pixel = (uint32_t)py * cam.W + px;
     double jx = 0.5, jy = 0.5, xi0 = 0.5, xi1 = 0.5;
@@ -327,11 +356,18 @@ __device__ __forceinline__ bool gen_ray(const CamConst& cam, uint32_t frame, int
     for (int i = 0; i < 3; ++i) d[i] = cam.f[i] + X * cam.r[i] + Y * cam.u[i];
     const double inv = 1.0 / sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     const uint32_t pix = acc_off + (per_sample ? pixel * (uint32_t)cam.spp + (uint32_t)s : pixel);
-    q.a[slot] = make_float4((float)cam.eye[0], (float)cam.eye[1], (float)cam.eye[2], as_float_i((int)pix));
-    q.b[slot] = make_float4((float)(d[0] * inv), (float)(d[1] * inv), (float)(d[2] * inv),
-                            as_float_i((int)(meta_hi | ((uint32_t)s << 4))));
+    const V3 o = v3((float)cam.eye[0], (float)cam.eye[1], (float)cam.eye[2]);
+    const V3 dir = v3((float)(d[0] * inv), (float)(d[1] * inv), (float)(d[2] * inv));
+    if (L >= 0 && !root_reached<L>(*sc, make_tray(o, dir))) {
+        q.a[slot].w = as_float_i((int)kDeadRay);
+        *pix_out = pix;
+        *sample_out = pixel * (uint32_t)cam.spp + (uint32_t)s;
+        return kGenMissed;
+    }
+    q.a[slot] = make_float4(o.x, o.y, o.z, as_float_i((int)pix));
+    q.b[slot] = make_float4(dir.x, dir.y, dir.z, as_float_i((int)(meta_hi | ((uint32_t)s << 4))));
     q.c[slot] = make_float4(1.0f, 1.0f, 1.0f, 0.0f);
-    return true;
+    return kGenQueued;
 }
 
 __device__ __forceinline__ void count_dead(bool dead, uint32_t* ctr) {
@@ -340,15 +376,70 @@ __device__ __forceinline__ void count_dead(bool dead, uint32_t* ctr) {
         atomicAdd(ctr + kCtrDead, (uint32_t)__popcll(m));
 }
 
+// Adds each thread's term to its pixel of acc.  In ray generation order lane l
+// of a block's four waves is one pixel in four samples: then the four terms
+// are summed and added once, each of three waves adding one channel; a group
+// whose pixels differ adds its terms one by one.  All threads of the block
+// must call; lds_add and lds_pix are the block's shared arrays.
+__device__ __forceinline__ void add_block_terms(float* acc, bool has, uint32_t pix, V3 add, float (&lds_add)[3][256],
+                                                uint32_t (&lds_pix)[256]) {
+    lds_pix[threadIdx.x] = has ? pix : kDeadRay;
+    lds_add[0][threadIdx.x] = add.x;
+    lds_add[1][threadIdx.x] = add.y;
+    lds_add[2][threadIdx.x] = add.z;
+    __syncthreads();
+    if (threadIdx.x < 192) {   // wave c adds channel c
+        const uint32_t c = threadIdx.x >> 6, l = threadIdx.x & 63u, q0 = lds_pix[l];
+        const bool same =
+            q0 != kDeadRay && lds_pix[64 + l] == q0 && lds_pix[128 + l] == q0 && lds_pix[192 + l] == q0;
+        if (same) {
+            atomicAdd(acc + 3 * q0 + c, (lds_add[c][l] + lds_add[c][64 + l]) + (lds_add[c][128 + l] + lds_add[c][192 + l]));
+        } else {
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t q = lds_pix[64 * k + l];
+                if (q == kDeadRay) continue;
+                atomicAdd(acc + 3 * q + c, lds_add[c][64 * k + l]);
+            }
+        }
+    }
+}
+
+// Camera rays that ray generation finishes itself (RootMiss, when L >= 0): the
+// background term goes to acc (weight 1) and -1 to the hit ids.
+struct RootMiss {
+    float* acc;
+    int32_t* out_ids;   // [pixels][spp] or NULL
+    float bg[3];
+};
+
+// L < 0: every live slot is queued.  L >= 0 (the node layout; scenes without
+// planes): rays that miss the root's child boxes are finished here and count
+// as traced rays, not as dead slots.
+template <int L>
 __global__ __launch_bounds__(256) void k_raygen(CamConst cam, int s0, int ns, int tiles_x, uint32_t n_threads,
-                                                RayQ q, uint32_t* ctr, uint32_t cap, int per_sample) {
+                                                RayQ q, uint32_t* ctr, uint32_t cap, int per_sample, DevScene sc,
+                                                RootMiss rm) {
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g == 0) {
         ctr[kCtrRays] = min(n_threads, cap);
         if (n_threads > cap) atomicOr(ctr + kCtrStatus, 1u);
     }
-    if (g >= n_threads || g >= cap) return;
-    count_dead(!gen_ray(cam, ctr[kCtrFrame], s0, ns, tiles_x, g, per_sample, 0u, 0u, q, g), ctr);
+    const bool in = g < n_threads && g < cap;
+    if (L < 0) {
+        if (in) count_dead(gen_ray(cam, ctr[kCtrFrame], s0, ns, tiles_x, g, per_sample, 0u, 0u, q, g) == kGenDead, ctr);
+        return;
+    }
+    __shared__ float lds_add[3][256];
+    __shared__ uint32_t lds_pix[256];
+    uint32_t pix = 0, sample = 0;
+    const GenKind k =
+        in ? gen_ray<L>(cam, ctr[kCtrFrame], s0, ns, tiles_x, g, per_sample, 0u, 0u, q, g, &sc, &pix, &sample)
+           : kGenQueued;
+    count_dead(k == kGenDead, ctr);
+    const bool missed = k == kGenMissed;
+    if (missed && rm.out_ids) rm.out_ids[sample] = -1;
+    if (!__syncthreads_or(missed ? 1 : 0)) return;   // block-uniform
+    add_block_terms(rm.acc, missed, pix, v3(rm.bg[0], rm.bg[1], rm.bg[2]), lds_add, lds_pix);
 }
 
 // Batched frames: one global slot space over all scenes; each thread finds
@@ -369,7 +460,7 @@ __global__ __launch_bounds__(256) void k_raygen_batch(const BatchScene* tab, int
     }
     const BatchScene& B = tab[lo];
     const bool live = gen_ray(B.cam, B.cam.frame, 0, B.shc.spp, B.tiles_x, g - B.ray_off, B.shc.per_sample,
-                              B.shc.acc_off, (uint32_t)lo << 20, q, g);
+                              B.shc.acc_off, (uint32_t)lo << 20, q, g) != kGenDead;
     count_dead(!live, ctr);
 }
 
@@ -900,29 +991,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
             has_add = true;
         }
         if (sum0) {
-            // ray generation order: lane l of the block's four waves is one pixel in four samples, so their
-            // sum is added once, each of three waves adding one channel (checked: different pixels are added
-            // one by one)
-            lds_pix[threadIdx.x] = has_add ? pix : kDeadRay;
-            lds_add[0][threadIdx.x] = add.x;
-            lds_add[1][threadIdx.x] = add.y;
-            lds_add[2][threadIdx.x] = add.z;
-            __syncthreads();
-            if (threadIdx.x < 192) {   // wave c adds channel c
-                const uint32_t c = threadIdx.x >> 6, l = threadIdx.x & 63u, q0 = lds_pix[l];
-                const bool same = q0 != kDeadRay && lds_pix[64 + l] == q0 && lds_pix[128 + l] == q0 &&
-                                  lds_pix[192 + l] == q0;
-                if (same) {
-                    atomicAdd(acc + 3 * q0 + c,
-                              (lds_add[c][l] + lds_add[c][64 + l]) + (lds_add[c][128 + l] + lds_add[c][192 + l]));
-                } else {
-                    for (int k = 0; k < 4; ++k) {
-                        const uint32_t q = lds_pix[64 * k + l];
-                        if (q == kDeadRay) continue;
-                        atomicAdd(acc + 3 * q + c, lds_add[c][64 * k + l]);
-                    }
-                }
-            }
+            add_block_terms(acc, has_add, pix, add, lds_add, lds_pix);
         } else if (has_add) {
             atomicAdd(acc + 3 * pix + 0, add.x);
             atomicAdd(acc + 3 * pix + 1, add.y);
@@ -1734,6 +1803,23 @@ static void defer_and_bin_shadows(FrameArgs& A, const SceneHost& h) {
     }
 }
 
+// Ray generation of a pass.  In a scene without planes, camera rays that miss
+// the root's child boxes are finished at once (background into acc); counting
+// frames queue every ray, so their node counts cover all camera rays.
+static void launch_raygen(const FrameArgs& A, int s0, int ns, int tiles_x, uint32_t nthreads, const RayQ& q,
+                          uint32_t* ctr, uint32_t cap, float* acc, hipStream_t st) {
+    const RootMiss rm{acc, A.shc.out_ids, {A.shc.bg[0], A.shc.bg[1], A.shc.bg[2]}};
+    const dim3 grid((nthreads + 255) / 256);
+    if (!A.count_work && A.sc.n_planes == 0)
+        by_layout(A.sc.wide, [&](auto L) {
+            hipLaunchKernelGGL(k_raygen<decltype(L)::value>, grid, dim3(256), 0, st, A.cam, s0, ns, tiles_x,
+                               nthreads, q, ctr, cap, A.shc.per_sample, A.sc, rm);
+        });
+    else
+        hipLaunchKernelGGL(k_raygen<-1>, grid, dim3(256), 0, st, A.cam, s0, ns, tiles_x, nthreads, q, ctr, cap,
+                           A.shc.per_sample, A.sc, rm);
+}
+
 static void enqueue_shadow_segment(const FrameArgs& A, const ShadowQ& sq, const ShadowSegment& g, int nb, float* acc,
                                    unsigned long long* swork, hipStream_t st) {
     if (g.perm) {
@@ -1803,8 +1889,7 @@ static rt_status enqueue_frame(const FrameArgs& A, hipStream_t st) {
         const int ns = std::min(pl.spp_pass, A.spp - s0);
         clear_counters(ctr, st);
         const uint32_t nthreads = (uint32_t)((int64_t)tiles_x * tiles_y * ns * 64);
-        hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, s0, ns, tiles_x,
-                           nthreads, q[0], ctr, pl.qcap, A.shc.per_sample);
+        launch_raygen(A, s0, ns, tiles_x, nthreads, q[0], ctr, pl.qcap, acc, st);
         for (int k = 0; k <= A.shc.max_depth; ++k) {
             RayQ& qi = q[k & 1];
             RayQ& qo = q[(k + 1) & 1];
@@ -2429,8 +2514,7 @@ static rt_status enqueue_cached(const CacheArgs& C, hipStream_t st) {
     }
     const int tiles_x = (int)tiles_x_of(A.cam.W, A.tile), tiles_y = (int)tiles_y_of(A.cam.H, A.tile);
     const uint32_t nthreads = (uint32_t)((int64_t)tiles_x * tiles_y * A.spp * 64);
-    hipLaunchKernelGGL(k_raygen, dim3((nthreads + 255) / 256), dim3(256), 0, st, A.cam, 0, A.spp, tiles_x, nthreads,
-                       q[0], ctr, pl.qcap, A.shc.per_sample);
+    launch_raygen(A, 0, A.spp, tiles_x, nthreads, q[0], ctr, pl.qcap, acc, st);
     for (int k = 0; k < cd; ++k) bounce(q[k & 1], q[(k + 1) & 1], hq, sq, ctr, A.shc, acc, k);
     shadows(sq, ctr, pl.scap, reinterpret_cast<uint32_t*>(A.ws + pl.off_s2 + sstride),
             reinterpret_cast<uint32_t*>(A.ws + pl.off_bins), acc);
