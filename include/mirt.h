@@ -130,7 +130,7 @@ enum {
                                  left in the workspace by the previous rt_params.accum_frames frames (0: start
                                  afresh) and output the average over all of them, the paper's pass-by-pass
                                  image update (Section V) */
-    RT_FLAG_GI = 64           /* diffuse global illumination (Eq. 8, the hemisphere integral of Section II) by
+    RT_FLAG_GI = 64,          /* diffuse global illumination (Eq. 8, the hemisphere integral of Section II) by
                                  path tracing (rt_render and rt_render_batch; per scene in a batch): every
                                  hit still adds its Phong local terms through shadow rays, and the path
                                  continues with ONE ray while depth < max_depth, chosen at random among the
@@ -144,6 +144,9 @@ enum {
                                  direction); 24 bits each.  rt_render_cached: the image's paths
                                  end at the cache depth; the training targets are paths from the
                                  selected queries keyed by (training index, sample 0). */
+    RT_FLAG_TIME_SHADOW = 128 /* record HIP events around the shadow traversal launches only (implies
+                                 RT_FLAG_NO_GRAPH): each recorded event leaves the GPU idle for a few
+                                 microseconds, so a timed frame records only the pair it needs */
 };
 
 enum { RT_TILE_8X8 = 0, RT_TILE_16X4 = 1, RT_TILE_32X2 = 2, RT_TILE_4X16 = 3 };

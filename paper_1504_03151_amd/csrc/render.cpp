@@ -1732,6 +1732,7 @@ struct FrameArgs {
     int gxd;                    // grid of k_extend_deep
     size_t lds;
     bool time_kernels;
+    bool time_shadow = false;   // events around the shadow launches only (RT_FLAG_TIME_SHADOW)
     uint32_t chunk;             // queue entries per fetch of a persistent traversal wave
     int tile;                   // RT_TILE_* of the primary rays
     bool bin_shadows;           // deferred shadow rays are binned before their traversal
@@ -1833,7 +1834,7 @@ static void enqueue_shadow_segment(const FrameArgs& A, const ShadowQ& sq, const 
     uint32_t* vis = g.perm && A.shc.gi ? sq.key : nullptr;   // path-traced frames (many unblocked rays)
     if (vis) hipLaunchKernelGGL(k_vis_clear, dim3(1024), dim3(256), 0, st, vis, g.begin_p, g.end_p, g.cap);
     {
-        KernelTimer kt(A.time_kernels, st, 2);
+        KernelTimer kt(A.time_kernels || A.time_shadow, st, 2);
         if (A.count_work)
             hipLaunchKernelGGL((k_shadow<true, false>), dim3(g.grid), dim3(256), A.lds, st, A.sc, nullptr, sq,
                                g.end_p, g.cursor, g.cap, A.chunk, acc, g.overflow, swork, g.perm, g.begin_p, vis);
@@ -2136,7 +2137,7 @@ struct BatchArgs {
     BatchPlan pl;
     uint8_t* ws;
     rt_stats* stats;
-    bool count_work, time_kernels;
+    bool count_work, time_kernels, time_shadow = false;
     uint32_t chunk;
     int gx, gs, shade_blocks;
 };
@@ -2232,7 +2233,7 @@ static rt_status enqueue_batch(const BatchArgs& B, hipStream_t st) {
         }
     }
     {   // the deferred shadow rays of every scene and depth
-        KernelTimer kt(B.time_kernels, st, 2);
+        KernelTimer kt(B.time_kernels || B.time_shadow, st, 2);
         if (B.count_work)
             hipLaunchKernelGGL((k_shadow<true, true>), dim3(B.gs), dim3(256), 0, st, none, tab, sq,
                                ctr + kCtrShadowAll, xcd_cursor(ctr, kCtrShadowAllCur), pl.scap, B.chunk, acc,
@@ -2745,12 +2746,13 @@ rt_status rt_render(const rt_scene* scene, const rt_camera* cam, const rt_params
     A.count_work = (p.flags & RT_FLAG_COUNT_WORK) != 0;
     A.spp = p.spp;
     A.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
+    A.time_shadow = (p.flags & RT_FLAG_TIME_SHADOW) != 0;
     A.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
     A.tile = p.tile;
     rt_status rs = frame_grids(A);
     if (rs != RT_OK) return rs;
     hipStream_t st = static_cast<hipStream_t>(p.stream);
-    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
+    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS | RT_FLAG_TIME_SHADOW)) == 0;
     HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + pl.off_ctr + 4 * kCtrFrame), (int)p.frame, 1,
                               st));
     const uint32_t accum = (p.flags & RT_FLAG_ACCUMULATE) ? p.accum_frames : 0u;
@@ -2951,6 +2953,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     A.count_work = (p.flags & RT_FLAG_COUNT_WORK) != 0;
     A.spp = p.spp;
     A.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
+    A.time_shadow = (p.flags & RT_FLAG_TIME_SHADOW) != 0;
     A.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
     A.tile = p.tile;
     C.state = static_cast<uint8_t*>(cache->state);
@@ -2963,7 +2966,7 @@ rt_status rt_render_cached(const rt_scene* scene, const rt_camera* cam, const rt
     // the target paths' counters carry the frame number too (it keys their random numbers)
     HIP_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(A.ws + C.cp.off_tctr + 4 * kCtrFrame), (int)p.frame, 1,
                               st));
-    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
+    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS | RT_FLAG_TIME_SHADOW)) == 0;
     rs = launch_cached(C, st, graph, h.uid);
     if (rs != RT_OK) return rs;
     if (p.flags & RT_FLAG_SYNC) {
@@ -3044,13 +3047,14 @@ rt_status rt_render_batch(const rt_scene* const* scenes, const rt_camera* cams, 
     B.stats = static_cast<rt_stats*>(p.stats);
     B.count_work = (p.flags & RT_FLAG_COUNT_WORK) != 0;
     B.time_kernels = (p.flags & RT_FLAG_TIME_KERNELS) != 0;
+    B.time_shadow = (p.flags & RT_FLAG_TIME_SHADOW) != 0;
     B.chunk = p.queue_chunk > 0 ? (uint32_t)((std::min(p.queue_chunk, 1 << 16) + 63) / 64 * 64) : 128u;
     rt_status rs = batch_grids(B);
     if (rs != RT_OK) return rs;
     hipStream_t st = static_cast<hipStream_t>(p.stream);
     rs = upload_table(table, B.ws + bp.off_tab, st);
     if (rs != RT_OK) return rs;
-    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS)) == 0;
+    const bool graph = (p.flags & (RT_FLAG_NO_GRAPH | RT_FLAG_TIME_KERNELS | RT_FLAG_TIME_SHADOW)) == 0;
     rs = launch_batch(B, st, graph);
     if (rs != RT_OK) return rs;
     if (p.flags & RT_FLAG_SYNC) {

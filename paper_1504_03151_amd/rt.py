@@ -24,6 +24,7 @@ RT_ERR = {-1: "INVALID_ARG", -2: "UNSUPPORTED", -3: "HIP", -4: "BVH_DEPTH", -5: 
 FLAG_SYNC, FLAG_COUNT_WORK, FLAG_NO_GRAPH, FLAG_TIME_KERNELS, FLAG_PER_SAMPLE = 1, 2, 4, 8, 16
 FLAG_ACCUMULATE = 32
 FLAG_GI = 64            # diffuse global illumination by path tracing (set from Params.gi)
+FLAG_TIME_SHADOW = 128  # HIP events around the shadow launches only
 STATS_MAX_DEPTH = 16
 
 

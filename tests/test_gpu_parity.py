@@ -131,6 +131,40 @@ def test_pass_splits_give_the_same_frame(rt):
     compare(w, out[1][0], out[1][1], min_robust=0.965)    # oracle: 0.973 (10 samples per pixel)
 
 
+def test_rays_missing_the_root_end_at_ray_generation(rt):
+    """Without planes, ray generation ends the camera rays that reach none of the root's child boxes (89% of
+    them here): their background terms are summed per pixel there and their hit ids set to -1.  Every pass
+    split, per-sample output and graph replays give the oracle's frame, and the timing flags change nothing:
+    RT_FLAG_TIME_SHADOW records events around the shadow launches only."""
+    w = S.random_tiny(7, size=37, depth=3, with_plane=False)   # ragged tiles: dead lanes in the blocks
+    w.camera.height = 29
+    w.params.spp, w.params.jitter = 10, 1
+    sc = rt.Scene(w.scene).upload()
+    out = []
+    for spp_pass in (10, 4, 3):
+        r = rt.Renderer(sc, w.camera, w.params, samples_per_pass=spp_pass)
+        rgb, ids = r.render(rt.FLAG_SYNC)
+        out.append((rgb.clone(), ids.clone()))
+        for flags in (rt.FLAG_TIME_SHADOW, rt.FLAG_TIME_KERNELS, 0, 0):   # eager timed frames, graph replays
+            rt.kernel_times(reset=True)
+            again = r.render(rt.FLAG_SYNC | flags)
+            kt = rt.kernel_times(reset=True)
+            assert torch.equal(again[1], ids)
+            assert torch.allclose(again[0], rgb, rtol=1e-5, atol=1e-6)
+            timed = {k for k, (ms, n) in kt.items() if n > 0}
+            assert timed == ({"shadow"} if flags == rt.FLAG_TIME_SHADOW else
+                             {"extend", "shade", "shadow"} if flags == rt.FLAG_TIME_KERNELS else set()), (flags, kt)
+    rs = rt.Renderer(sc, w.camera, w.params, per_sample=True)
+    rgb_s, ids_s = rs.render(rt.FLAG_SYNC)
+    for rgb, ids in out[1:]:
+        assert torch.equal(ids, out[0][1])
+        assert torch.allclose(rgb, out[0][0], rtol=1e-5, atol=1e-6)
+    assert torch.equal(ids_s, out[0][1])
+    assert torch.allclose(rgb_s.mean(dim=2), out[0][0], rtol=1e-5, atol=2e-6)
+    assert (out[0][1] == -1).double().mean() > 0.8
+    compare(w, out[2][0], out[2][1], min_robust=0.98)      # oracle: 0.9907
+
+
 def test_edge_cases(rt):
     # empty scene (only background), a planes-only scene, a 1x1 image, depth 0
     bg = (0.25, 0.5, 0.75)
