@@ -656,6 +656,7 @@ __global__ __launch_bounds__(256) void k_vis_resolve(ShadowQ s, const uint32_t* 
 // arbitrary.
 constexpr int kBinMax = 4096;
 constexpr uint32_t kBinChunk = 16384;
+constexpr int kBinBlocks = 4096;   // binning grid: 16 blocks per CU, one chunk each up to 64M entries
 
 __global__ __launch_bounds__(256) void k_bin_count(const uint32_t* key, const uint32_t* begin_p,
                                                    const uint32_t* count_p, uint32_t cap, uint32_t* hist, int nb) {
@@ -1825,9 +1826,9 @@ static void enqueue_shadow_segment(const FrameArgs& A, const ShadowQ& sq, const 
                                    unsigned long long* swork, hipStream_t st) {
     if (g.perm) {
         hipLaunchKernelGGL(k_zero_u32, dim3((nb + 255) / 256), dim3(256), 0, st, g.bins, nb);
-        hipLaunchKernelGGL(k_bin_count, dim3(1024), dim3(256), 0, st, sq.key, g.begin_p, g.end_p, g.cap, g.bins, nb);
+        hipLaunchKernelGGL(k_bin_count, dim3(kBinBlocks), dim3(256), 0, st, sq.key, g.begin_p, g.end_p, g.cap, g.bins, nb);
         hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, st, g.bins, g.bins + kBinMax, nb);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(1024), dim3(256), 0, st, sq.key, g.begin_p, g.end_p, g.cap,
+        hipLaunchKernelGGL(k_bin_scatter, dim3(kBinBlocks), dim3(256), 0, st, sq.key, g.begin_p, g.end_p, g.cap,
                            g.bins + kBinMax, g.perm, nb);
     }
     // binned launches mark unblocked entries in the key array (no longer needed once the order is known)
