@@ -550,6 +550,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     extend_queue<false, false, L>(sc, nullptr, q, hit, count_p, cursor, cap, chunk, overflow, nullptr);
 }
 
+// A shadow-queue record is read once (binned order, all of a launch's rays):
+// non-temporal loads keep the stream from evicting the BVH node lines the
+// traversal re-reads from the L2.  (The closest-hit queues are read normally:
+// shading reads the same records right after.)
+__device__ __forceinline__ float4 load_stream(const float4* p) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Any-hit over the shadow queue; adds the contribution of each unblocked light
 // to its pixel.  Eight waves per SIMD (at most 64 registers): more rays in
 // flight hide more of the node-fetch latency than fewer waves with more
@@ -573,8 +583,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
         for (uint32_t b = base; b < end; b += 64) {
             const uint32_t j = b + lane_id();
             if (j < end) {
-                const uint32_t i = perm ? perm[j] : begin + j;   // binned order of deferred shadow rays
-                const float4 ea = s.a[i], eb = s.b[i];
+                const uint32_t i = perm ? __builtin_nontemporal_load(perm + j) : begin + j;   // binned order
+                const float4 ea = load_stream(s.a + i), eb = load_stream(s.b + i);
                 const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? (uint32_t)as_int_f(eb.w) : 0u);
                 const TRay r = make_tray(v3(ea.x, ea.y, ea.z), v3(eb.x, eb.y, eb.z));
                 const Hit h = traverse<true, COUNT, L>(S, r, ea.w, stk, w);
@@ -582,7 +592,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                     if (vis) {   // binned order visits pixels at random: mark the entry, add in queue order later
                         atomicOr(vis + (i >> 5), 1u << (i & 31u));
                     } else {
-                        const float4 ec = s.c[i];
+                        const float4 ec = load_stream(s.c + i);
                         const uint32_t p = (uint32_t)as_int_f(ec.w);
                         atomicAdd(acc + 3 * p + 0, ec.x);
                         atomicAdd(acc + 3 * p + 1, ec.y);
