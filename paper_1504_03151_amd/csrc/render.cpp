@@ -881,6 +881,15 @@ __device__ __forceinline__ uint32_t bin_axis(float x, float lo, float inv, int c
     return (uint32_t)f;
 }
 
+// Shadow-queue records are written during the bounces and read only by the
+// shadow launch at the end of the frame: non-temporal stores keep them from
+// evicting the BVH node and ray-queue lines the bounces re-read from the L2.
+__device__ __forceinline__ void store_stream(float4* p, float4 v) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const f4v x = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
+}
+
 __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, uint32_t cap, uint32_t* ctr, V3 xs,
                                              V3 lp, V3 w, const LightTerm& lt, uint32_t pix, uint32_t sid,
                                              const ShadeConst& C, int l) {
@@ -893,15 +902,15 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
     V3 sd = xs - lp;
     const float dist = sqrtf(dot(sd, sd));
     sd = sd * (1.0f / dist);
-    sq.a[slot] = make_float4(lp.x, lp.y, lp.z, dist);
-    sq.b[slot] = make_float4(sd.x, sd.y, sd.z, as_float_i((int)sid));
-    sq.c[slot] = make_float4(w.x * lt.cr, w.y * lt.cg, w.z * lt.cb, as_float_i((int)pix));
+    store_stream(sq.a + slot, make_float4(lp.x, lp.y, lp.z, dist));
+    store_stream(sq.b + slot, make_float4(sd.x, sd.y, sd.z, as_float_i((int)sid)));
+    store_stream(sq.c + slot, make_float4(w.x * lt.cr, w.y * lt.cg, w.z * lt.cb, as_float_i((int)pix)));
     if (sq.key) {
         const int c = C.bin_c;
         const uint32_t cell = bin_axis(xs.x, C.bin_lo[0], C.bin_inv[0], c) +
                               (uint32_t)c * (bin_axis(xs.y, C.bin_lo[1], C.bin_inv[1], c) +
                                              (uint32_t)c * bin_axis(xs.z, C.bin_lo[2], C.bin_inv[2], c));
-        sq.key[slot] = (uint32_t)(l & 31) * (uint32_t)(c * c * c) + cell;
+        __builtin_nontemporal_store((uint32_t)(l & 31) * (uint32_t)(c * c * c) + cell, sq.key + slot);
     }
 }
 
