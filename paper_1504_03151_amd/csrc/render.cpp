@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
             const uint32_t j = b + lane_id();
             if (j < end) {
                 const uint32_t i = perm ? __builtin_nontemporal_load(perm + j) : begin + j;   // binned order
-                const float4 ea = load_stream(s.a + i), eb = load_stream(s.b + i);
+                const float4 ea = BATCH ? s.a[i] : load_stream(s.a + i), eb = BATCH ? s.b[i] : load_stream(s.b + i);
                 const DevScene& S = scene_of<BATCH>(sc, tab, BATCH ? (uint32_t)as_int_f(eb.w) : 0u);
                 const TRay r = make_tray(v3(ea.x, ea.y, ea.z), v3(eb.x, eb.y, eb.z));
                 const Hit h = traverse<true, COUNT, L>(S, r, ea.w, stk, w);
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
                     if (vis) {   // binned order visits pixels at random: mark the entry, add in queue order later
                         atomicOr(vis + (i >> 5), 1u << (i & 31u));
                     } else {
-                        const float4 ec = load_stream(s.c + i);
+                        const float4 ec = BATCH ? s.c[i] : load_stream(s.c + i);
                         const uint32_t p = (uint32_t)as_int_f(ec.w);
                         atomicAdd(acc + 3 * p + 0, ec.x);
                         atomicAdd(acc + 3 * p + 1, ec.y);
@@ -890,6 +890,7 @@ __device__ __forceinline__ void store_stream(float4* p, float4 v) {
     __builtin_nontemporal_store(x, reinterpret_cast<f4v*>(p));
 }
 
+template <bool STREAM>
 __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, uint32_t cap, uint32_t* ctr, V3 xs,
                                              V3 lp, V3 w, const LightTerm& lt, uint32_t pix, uint32_t sid,
                                              const ShadeConst& C, int l) {
@@ -902,9 +903,17 @@ __device__ __forceinline__ void write_shadow(const ShadowQ& sq, uint32_t slot, u
     V3 sd = xs - lp;
     const float dist = sqrtf(dot(sd, sd));
     sd = sd * (1.0f / dist);
-    store_stream(sq.a + slot, make_float4(lp.x, lp.y, lp.z, dist));
-    store_stream(sq.b + slot, make_float4(sd.x, sd.y, sd.z, as_float_i((int)sid)));
-    store_stream(sq.c + slot, make_float4(w.x * lt.cr, w.y * lt.cg, w.z * lt.cb, as_float_i((int)pix)));
+    const float4 a = make_float4(lp.x, lp.y, lp.z, dist), b = make_float4(sd.x, sd.y, sd.z, as_float_i((int)sid)),
+                 c = make_float4(w.x * lt.cr, w.y * lt.cg, w.z * lt.cb, as_float_i((int)pix));
+    if (STREAM) {
+        store_stream(sq.a + slot, a);
+        store_stream(sq.b + slot, b);
+        store_stream(sq.c + slot, c);
+    } else {
+        sq.a[slot] = a;
+        sq.b[slot] = b;
+        sq.c[slot] = c;
+    }
     if (sq.key) {
         const int c = C.bin_c;
         const uint32_t cell = bin_axis(xs.x, C.bin_lo[0], C.bin_inv[0], c) +
@@ -1133,7 +1142,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                                                     (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
                     const V3 lp = light_at(S, C, smp, l);
                     const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
-                    write_shadow(sq, slot, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
+                    write_shadow<!BATCH>(sq, slot, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
                 }
                 run += (uint32_t)__popcll(bal);
             }
@@ -1143,7 +1152,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                 const V3 lp = light_at(S, C, smp, l);
                 const LightTerm lt = light_term(lp, S.lights[l].intensity, x, nf, d, alb, kd, ks, shin);
                 if (!lt.emit) continue;
-                write_shadow(sq, slot++, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
+                write_shadow<!BATCH>(sq, slot++, scap, ctr, xs, lp, w, lt, pix, sid, C, l);
             }
         }
         uint32_t qslot = sec_base + sec_off;
