@@ -550,10 +550,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
     extend_queue<false, false, L>(sc, nullptr, q, hit, count_p, cursor, cap, chunk, overflow, nullptr);
 }
 
-// A shadow-queue record is read once (binned order, all of a launch's rays):
-// non-temporal loads keep the stream from evicting the BVH node lines the
-// traversal re-reads from the L2.  (The closest-hit queues are read normally:
-// shading reads the same records right after.)
+// A record read for the last time (a shadow-queue record by the shadow
+// launch; a ray and its hit by shading): non-temporal loads keep the stream
+// from evicting the BVH node and queue lines that are read again from the L2.
+// (The closest-hit launches read their queue normally: shading reads the same
+// records right after.)
 __device__ __forceinline__ float4 load_stream(const float4* p) {
     typedef float f4v __attribute__((ext_vector_type(4)));
     const f4v v = __builtin_nontemporal_load(reinterpret_cast<const f4v*>(p));
@@ -950,14 +951,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
         float t = 0.0f;
         float4 ra = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         if (active) {
-            ra = qin.a[i];
+            ra = BATCH ? qin.a[i] : load_stream(qin.a + i);
             pix = (uint32_t)as_int_f(ra.w);
             active = pix != kDeadRay;
         }
         if (active) {
-            prim = hit.prim[i];
-            t = hit.t[i];
-            const float4 rb = qin.b[i], rc = qin.c[i];
+            prim = BATCH ? hit.prim[i] : __builtin_nontemporal_load(hit.prim + i);
+            t = BATCH ? hit.t[i] : __builtin_nontemporal_load(hit.t + i);
+            const float4 rb = BATCH ? qin.b[i] : load_stream(qin.b + i), rc = BATCH ? qin.c[i] : load_stream(qin.c + i);
             meta = (uint32_t)as_int_f(rb.w);
             o = v3(ra.x, ra.y, ra.z);
             d = v3(rb.x, rb.y, rb.z);
