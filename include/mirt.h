@@ -317,8 +317,8 @@ rt_status rt_occluded(const rt_scene* scene, const float* rays, int64_t n, uint8
 rt_status rt_host_trace(const rt_scene* scene, const float* rays, int64_t n, int32_t any_hit, float* t,
                         int32_t* id, uint32_t* work, int32_t nthreads);
 
-/* Kernel timings recorded by frames rendered with RT_FLAG_TIME_KERNELS since
- * the last reset: total milliseconds and launch counts of the closest-hit
+/* Kernel timings recorded by frames rendered with RT_FLAG_TIME_KERNELS (or
+ * RT_FLAG_TIME_SHADOW, which records index 2 only) since the last reset: total milliseconds and launch counts of the closest-hit
  * (index 0), shading (1) and shadow any-hit (2) kernels, the cache inference
  * (3) and a learned frame's whole training part (4).  Waits for the recorded
  * events.  ms [5] and launches [5] are host arrays; reset != 0 clears the

@@ -484,7 +484,8 @@ def occluded(scene: Scene, rays, stream=None):
 
 
 def kernel_times(reset: bool = True) -> dict:
-    """Totals recorded by frames rendered with FLAG_TIME_KERNELS: {kernel: (ms, launches)}."""
+    """Totals recorded by frames rendered with FLAG_TIME_KERNELS (every traversal and shading launch) or
+    FLAG_TIME_SHADOW (the shadow launches only): {kernel: (ms, launches)}."""
     ms = (C.c_double * 5)()
     n = (C.c_int64 * 5)()
     _check(lib().rt_kernel_times(ms, n, int(reset)), "rt_kernel_times")
